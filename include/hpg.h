@@ -1,0 +1,184 @@
+/*
+ * hpg.h - C ABI of the MI355X hierarchical proximal Galerkin (hpG) library.
+ *
+ * The library solves the obstacle problem (u <= phi) and the gradient-type
+ * problem (|grad u| <= phi) for the Dirichlet energy on a tensor-product
+ * domain (0,1)^d, d = 1, 2, 3 (paper: Sec. 2 problem setup; d = 3 as in
+ * Sec. 6.5), with homogeneous Dirichlet conditions, by the latent-variable
+ * proximal point method discretised with the hierarchical p-FEM basis
+ * (Sec. 2.1-2.2, Sec. 3, Sec. 4).  Each proximal subproblem eq. (pG) /
+ * eq. (pG:gradient) is solved by Newton's method; every Newton system
+ * eq. (pG-matrix) is solved matrix-free on the GPU by preconditioned MINRES
+ * with the block-diagonal preconditioner P_D of eq. (schur4) and the Schur
+ * approximation of eq. (schur-preconditioner) (obstacle) or
+ * eq. (schur-preconditioner:gradient) (gradient).
+ *
+ * Conventions used by every call:
+ *  - Mesh: per direction k a breakpoint vector 0 = x_0 < ... < x_{m_k} = 1
+ *    (Sec. 3).  Cells are numbered lexicographically, direction 0 fastest.
+ *    One partial degree p on every cell (p >= 2 obstacle, p >= 1 gradient).
+ *  - u unknowns (U_{0,h,p}): per direction n1_k = m_k p - 1; the hat of
+ *    interior vertex v is 1-D unknown v p - 1, bubble W_n of cell c is
+ *    c p + n; the d-D vector is the n1_0 x ... x n1_{d-1} array, direction 0
+ *    fastest.  Coefficients are w.r.t. the hats and W_n of eq. (Wn).
+ *  - psi unknowns (Psi_{h,p}, Legendre P_n, Sec. 3): cell-major; inside a cell
+ *    the Legendre multi-index with direction 0 fastest, P = p-1 (obstacle) or
+ *    P = p (gradient) modes per direction; gradient: d components per cell,
+ *    component-major.
+ *  - Quadrature points: tensor Gauss-Legendre, q = p+1 per direction per
+ *    cell; cell-major, direction 0 fastest inside a cell.  Data f and phi are
+ *    given by their values at these points, which define the discrete problem.
+ *  - All host pointers are owned by the caller and only read/written during
+ *    the call.  Device pointers (hpg_solve_device, hpg_op_*) are caller-owned
+ *    device memory on the problem's device; work is enqueued on the given HIP
+ *    stream (NULL = the HIP null stream, as for HIP runtime calls) and the
+ *    call returns after that stream has finished.  hpg_solve (host buffers)
+ *    runs on a stream the library owns.
+ *  - Every call returns a status; none aborts.  On error hpg_last_error()
+ *    returns a thread-local message.
+ */
+#ifndef HPG_H
+#define HPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hpg_status;
+#define HPG_OK 0
+#define HPG_NOT_CONVERGED 1      /* outputs written: best iterate so far */
+#define HPG_PENDING 2            /* serving: result not ready yet */
+#define HPG_ERR_INVALID_ARG (-1)
+#define HPG_ERR_NOMEM (-2)
+#define HPG_ERR_DEVICE (-3)
+#define HPG_ERR_NUMERIC (-4)
+#define HPG_ERR_BUDGET (-5)
+
+#define HPG_OBSTACLE 0
+#define HPG_GRADIENT 1
+
+#define HPG_FP64 0               /* every GPU operation in FP64 */
+#define HPG_MIXED 1              /* FP32 Krylov operator/preconditioner, FP64 Newton */
+
+typedef struct hpg_mesh hpg_mesh;
+typedef struct hpg_problem hpg_problem;
+
+/* Thread-local text of the last error (never NULL). */
+const char* hpg_last_error(void);
+
+/* ---- mesh (paper Sec. 3) ------------------------------------------------
+ * dim: 1..3.  ncells[k]: cells in direction k (>= 1).  breaks: NULL for
+ * uniform cells on (0,1), else breaks[k] points to ncells[k]+1 strictly
+ * increasing values with breaks[k][0] = 0 and breaks[k][ncells[k]] = 1.
+ * p: partial degree; constraint: HPG_OBSTACLE or HPG_GRADIENT.
+ * Inputs are copied; the handle is freed with hpg_destroy_mesh.
+ * Errors: HPG_ERR_INVALID_ARG for any out-of-range argument. */
+hpg_status hpg_create_mesh(int dim, const int32_t* ncells, const double* const* breaks,
+                           int32_t p, int32_t constraint, hpg_mesh** out);
+void hpg_destroy_mesh(hpg_mesh* mesh);
+
+typedef struct hpg_mesh_info {
+    int32_t dim, p, q, P, constraint;
+    int32_t ncells[3];
+    int64_t n_cells, n_u, n_psi, n_qp;
+} hpg_mesh_info;
+
+hpg_status hpg_get_mesh_info(const hpg_mesh* mesh, hpg_mesh_info* out);
+
+/* Physical Gauss-Legendre points, xyz[i*dim + k] for point i (documented order). */
+hpg_status hpg_quadrature_points(const hpg_mesh* mesh, double* xyz);
+
+/* ---- problem: mesh + data + device state --------------------------------
+ * device: HIP device ordinal.  Allocates the device tables and work buffers
+ * (HPG_ERR_NOMEM / HPG_ERR_DEVICE on failure).  The mesh may be destroyed
+ * afterwards (the problem keeps its own copy). */
+hpg_status hpg_create_problem(const hpg_mesh* mesh, int device, hpg_problem** out);
+void hpg_destroy_problem(hpg_problem* prob);
+
+/* f and phi at the n_qp quadrature points (host arrays).  Non-finite values
+ * give HPG_ERR_NUMERIC; for the gradient constraint phi must be > 0
+ * (Sec. 2.2) else HPG_ERR_INVALID_ARG. */
+hpg_status hpg_set_forcing(hpg_problem* prob, const double* f_qp, size_t n_qp);
+hpg_status hpg_set_obstacle(hpg_problem* prob, const double* phi_qp, size_t n_qp);
+
+/* ---- solve options and statistics ---------------------------------------- */
+typedef struct hpg_solve_opts {
+    int32_t size;           /* sizeof(hpg_solve_opts), for ABI evolution */
+    double alpha0;          /* alpha_1 (default 2) */
+    double alpha_factor;    /* alpha_{k+1} = min(alpha_k * factor, alpha_max) (default 2) */
+    double alpha_max;       /* default 1e300 (uncapped) */
+    int32_t max_prox;       /* proximal step cap (default 60) */
+    double prox_tol;        /* ||u_k - u_{k-1}||_L2 <= prox_tol ||u_k||_L2 (default 1e-10) */
+    int32_t fixed_prox_steps; /* > 0: run exactly this many proximal steps */
+    double newton_tol;      /* default 1e-12 (FP64), 1e-10 suggested for MIXED */
+    double stall_tol;       /* line search failure accepted below this (default 1e-9) */
+    int32_t max_newton;     /* per subproblem (default 60) */
+    double krylov_rtol;     /* MINRES relative tolerance (default 1e-10) */
+    int32_t max_krylov;     /* per Newton step (default 2000) */
+    double beta;            /* E_beta weight, Jacobian only (default 0) */
+    int32_t precision;      /* HPG_FP64 or HPG_MIXED */
+    int32_t krylov_chunk;   /* iterations enqueued between convergence checks (default 16) */
+} hpg_solve_opts;
+
+void hpg_default_opts(hpg_solve_opts* opts);
+
+typedef struct hpg_solve_stats {
+    int32_t status;
+    int32_t prox_steps;
+    int32_t newton_iters;
+    int32_t line_search_halvings;
+    int64_t krylov_iters;
+    double newton_error;    /* last Newton error of the last subproblem */
+    double seconds;         /* wall time of the solve */
+    double alpha_last;
+} hpg_solve_stats;
+
+/* Solve; u_out[n_u], psi_out[n_psi] (psi may be NULL), lam_out[n_psi]
+ * (lambda_K = (psi_{K-1} - psi_K)/alpha_K, may be NULL).  Host buffers.
+ * Returns HPG_OK, HPG_NOT_CONVERGED (outputs hold the last iterate) or an error. */
+hpg_status hpg_solve(hpg_problem* prob, const hpg_solve_opts* opts, double* u_out,
+                     double* psi_out, double* lam_out, hpg_solve_stats* stats);
+
+/* Same with caller-owned device buffers d_u[n_u], d_psi[n_psi] (FP64) on the
+ * problem's device, enqueued on `stream` (a hipStream_t; NULL = null stream). */
+hpg_status hpg_solve_device(hpg_problem* prob, const hpg_solve_opts* opts, double* d_u,
+                            double* d_psi, void* stream, hpg_solve_stats* stats);
+
+/* ---- operator-level calls (the Newton linear system of eq. (pG-matrix)) ---
+ * hpg_op_setup linearises at psi (device, FP64, n_psi) for step size alpha
+ * and E_beta weight beta: computes the quadrature weights omega of D_psi
+ * (Sec. 4.3) and the inverted cell blocks of -S_hat (Sec. 4.5/4.6).
+ * precision selects the element type of the hpg_op_apply_* vectors:
+ * double for HPG_FP64, float for HPG_MIXED.  Vectors have n_u + n_psi
+ * entries, u first. */
+hpg_status hpg_op_setup(hpg_problem* prob, const double* d_psi, double alpha, double beta,
+                        int32_t precision, void* stream);
+/* y = G x, G = [[alpha A, B], [B^T, -D_psi - E_beta]] (eq. (pG-matrix)). */
+hpg_status hpg_op_apply_G(hpg_problem* prob, const void* d_x, void* d_y, void* stream);
+/* z = diag(alpha A, -S_hat)^{-1} r (SPD form of P_D, eq. (schur4)). */
+hpg_status hpg_op_apply_prec(hpg_problem* prob, const void* d_r, void* d_z, void* stream);
+/* Solve G x = b by preconditioned MINRES from x = 0; *iters = iterations. */
+hpg_status hpg_op_minres(hpg_problem* prob, const void* d_b, void* d_x, double rtol,
+                         int32_t max_iters, int32_t* iters, void* stream);
+/* FP64 residual of eq. (pG) / eq. (pG:gradient) at (u, psi) with previous
+ * latent iterate psi_prev and step alpha: R (n_u + n_psi, FP64, u first). */
+hpg_status hpg_op_residual(hpg_problem* prob, const double* d_u, const double* d_psi,
+                           const double* d_psi_prev, double alpha, double* d_R, void* stream);
+
+/* ---- kernel timing (for measurement harnesses) ----------------------------
+ * When enabled, the library brackets every launch of the named kernel group
+ * ("apply_G", "apply_prec", "minres_vec", "setup", "residual") with HIP events
+ * on the stream it is launched on.  hpg_kernel_time returns the number of
+ * bracketed launches and their summed duration in milliseconds. */
+hpg_status hpg_set_kernel_timing(hpg_problem* prob, int32_t enable);
+hpg_status hpg_kernel_time(hpg_problem* prob, const char* group, int64_t* launches,
+                           double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPG_H */

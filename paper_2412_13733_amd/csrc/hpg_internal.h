@@ -1,0 +1,88 @@
+// Internal declarations of the hpG library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hpg.h"
+
+namespace hpg {
+
+// ---------------------------------------------------------------------------
+// Error plumbing: every API call catches hpg::Error and turns it into a status.
+struct Error {
+    hpg_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(hpg_status code, const std::string& msg);
+void set_last_error(const std::string& msg);
+#define HPG_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            ::hpg::fail(HPG_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// 1-D reference tables on [-1, 1] (Sec. 3): Legendre P_n, hats, bubbles
+// W_n = (P_n - P_{n+2})/(2n+3) with W_n' = -P_{n+1}, spectral-Galerkin
+// Y_n = P_n - P_{n+2}, and a Gauss-Legendre rule.
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w);
+void legendre_all(int nmax, double y, double* P, double* dP);
+
+struct RefTables {
+    int p = 0, P = 0, q = 0;
+    std::vector<double> y, w;          // q nodes / weights
+    std::vector<double> Vu, Du;        // q x (p+1): local u basis and d/dy
+    std::vector<double> Vpsi;          // q x P: Legendre modes
+    std::vector<double> A1, M1;        // (p+1)^2 reference stiffness / mass (d/dy)
+    std::vector<double> B1;            // (p+1) x P: (phi_l, P_a) on [-1,1]
+    std::vector<double> G1;            // (p+1) x P: (phi_l', P_a) on [-1,1]
+    std::vector<double> MpsiDiag;      // P: 2/(2a+1)
+    // Phi_h (Y basis, P functions): gradient stiffness, mass, Gram with P_a
+    std::vector<double> AY, MY, BY;    // P x P
+    void build(int p, int P, int q);
+};
+
+// ---------------------------------------------------------------------------
+// Host mesh (uniform partial degree p, tensor breakpoints).
+struct Mesh {
+    int d = 0, p = 0, P = 0, q = 0, kind = HPG_OBSTACLE;
+    int m[3] = {1, 1, 1};
+    int n1[3] = {1, 1, 1};
+    std::vector<double> breaks[3];
+    int64_t n_cells = 0, n_u = 0, n_psi = 0, n_qp = 0;
+    int ncomp = 1;
+    int64_t psi_per_cell = 0;   // ncomp * P^d
+    int64_t Pd = 0, Qd = 0, Ld = 0;   // P^d, q^d, (p+1)^d
+    RefTables ref;
+    double h(int k, int c) const { return breaks[k][c + 1] - breaks[k][c]; }
+};
+
+// Sparse 1-D global rows in direction k (assembled from the cell matrices):
+// for every 1-D u unknown g: up to 7 (column, stiffness, mass) entries and up
+// to 4 (psi 1-D index c*P + a, Gram value) entries; gradient adds up to 4
+// (psi index, (phi', P_a)) entries.
+struct Rows1D {
+    static constexpr int WM = 7, WB = 4;
+    int n = 0;
+    std::vector<int32_t> lenM, colM;
+    std::vector<double> aM, mM;
+    std::vector<int32_t> lenB, colB;
+    std::vector<double> vB;
+    std::vector<int32_t> lenG, colG;
+    std::vector<double> vG;
+    std::vector<double> Adense, Mdense;   // n x n global 1-D stiffness and mass (for FDM)
+};
+void build_rows(const Mesh& M, int k, Rows1D& R);
+
+// Fast diagonalisation (Lynch-Rice-Thomas): A1 V = M1 V Lambda, V^T M1 V = I.
+void generalized_eig(int n, const std::vector<double>& A, const std::vector<double>& B,
+                     std::vector<double>& V, std::vector<double>& lam);
+
+}  // namespace hpg

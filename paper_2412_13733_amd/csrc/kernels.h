@@ -1,0 +1,109 @@
+// Kernel-side structs and launchers of the hpG library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hpg {
+namespace dev {
+
+constexpr int MODE_APPLY = 0;
+constexpr int MODE_RES = 1;
+
+// mesh geometry, passed by value
+struct Geo {
+    int d, p, P, q;
+    int m[3];
+    int n1[3];
+    int64_t n_u, n_psi, n_cells;
+    int Pd, Qd, Ld;
+    int S;   // per-cell LDS stride: max(p+1, q)^d
+};
+
+// sparse global 1-D rows of one direction (see Rows1D on the host)
+template <typename T>
+struct URows {
+    static constexpr int WM = 7, WB = 4;
+    const int32_t* lenM;
+    const int32_t* colM;
+    const T* aM;
+    const T* mM;
+    const int32_t* lenB;
+    const int32_t* cellB;
+    const int32_t* modeB;
+    const T* vB;
+};
+
+// 1-D reference tables and cell widths
+template <typename T>
+struct PsiTabs {
+    const T* B1;     // (p+1) x P
+    const T* Vpsi;   // q x P
+    const T* Vu;     // q x (p+1)
+    const T* w;      // q
+    const T* Mdiag;  // P: 2/(2a+1)
+    const T* h[3];   // cell widths per direction
+};
+
+// MINRES scalar state (device)
+struct KState {
+    double gamma1, gamma, gamma_new, delta;
+    double c, c_prev, s, s_prev, eta;
+    double a1, a2, a3, step;
+    double rtol;
+    int iters, max_iters, done, breakdown;
+};
+
+template <typename T>
+void launch_u_side(const Geo& g, const URows<T>* r, T alpha, const T* xu, const T* xb,
+                   const T* xb_prev, const double* F, T* yu, double* partial, const int* done,
+                   int mode, hipStream_t s);
+template <typename T>
+void launch_psi_side(const Geo& g, const PsiTabs<T>& tb, int cpb, T beta, const T* xu,
+                     const T* xpsi, const T* omega, const double* Phi, T* ypsi, double* partial,
+                     const int* done, int mode, hipStream_t s);
+size_t setup_smem_per_cell(const Geo& g);
+void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* psi,
+                  double alpha, double beta, const double* C, const int* cclass, double* om64,
+                  float* om32, double* s64, float* s32, hipStream_t s);
+template <typename T>
+void launch_prec_psi(int64_t n_cells, int n, const T* sinv, const T* r, T* z, double* partial,
+                     const int* done, hipStream_t s);
+template <typename T>
+void launch_gemm_right(int64_t R, int N, const T* X, const T* Mat, T* Y, const int* done,
+                       hipStream_t s);
+template <typename T>
+void launch_gemm_left(int64_t O, int N, int64_t C, const T* X, const T* Mat, T* Y,
+                      const int* done, hipStream_t s);
+template <typename T>
+void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
+                      const int* done, hipStream_t s);
+template <typename T>
+void launch_dot(int64_t n, const T* a, const T* b, double* partial, int nblocks, const int* done,
+                hipStream_t s);
+void launch_kr_delta(KState* st, const double* partial, int np, hipStream_t s);
+template <typename T>
+void launch_kr_vhat(int64_t n, const KState* st, const T* Gq, const T* vcur, T* vprev,
+                    const int* done, hipStream_t s);
+void launch_kr_rotate(KState* st, const double* partial, int np, int* done, hipStream_t s);
+template <typename T>
+void launch_kr_update(int64_t n, const KState* st, T* q, T* wprev, const T* wcur, T* x, T* vprev,
+                      const T* z, const int* done, hipStream_t s);
+void launch_kr_finish(KState* st, int* done, hipStream_t s);
+void launch_kr_init(KState* st, const double* partial, int np, double rtol, int maxit, int* done,
+                    hipStream_t s);
+template <typename T>
+void launch_kr_start(int64_t n, const KState* st, const T* b, const T* z, T* vcur, T* vprev,
+                     T* q, T* wprev, T* wcur, T* x, hipStream_t s);
+template <typename TI, typename TO>
+void launch_convert(int64_t n, const TI* a, TO* b, double scale, hipStream_t s);
+template <typename T>
+void launch_axpy_to(int64_t n, const double* x, double t, const T* d, double* y, hipStream_t s);
+void launch_lambda(int64_t n, const double* psi_prev, const double* psi, double alpha,
+                   double* lam, hipStream_t s);
+void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u, const double* v,
+               double* partial, hipStream_t s);
+
+}  // namespace dev
+}  // namespace hpg

@@ -1,0 +1,125 @@
+// Problem state of the hpG library: device tables, data and work buffers.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "hpg_internal.h"
+#include "kernels.h"
+
+struct hpg_mesh {
+    hpg::Mesh M;
+};
+
+namespace hpg {
+
+// device buffer with RAII
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    ~DBuf();
+    void alloc(size_t b);
+    template <typename T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+template <typename T>
+struct DevRows {
+    DBuf lenM, colM, aM, mM, lenB, cellB, modeB, vB;
+    dev::URows<T> view() const;
+};
+
+template <typename T>
+struct DevTabs {
+    DBuf B1, Vpsi, Vu, w, Mdiag, h[3];
+    dev::PsiTabs<T> view() const;
+};
+
+template <typename T>
+struct DevFdm {
+    DBuf V[3], Vt[3], lam[3];
+};
+
+// MINRES workspace of one precision
+template <typename T>
+struct KrylovWork {
+    DBuf z, vcur, vprev, q, Gq, wprev, wcur, t1, t2;
+    int64_t n = 0;
+    void ensure(int64_t n_, int64_t n_u);
+};
+
+struct TimingGroup {
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+};
+
+struct Problem {
+    Mesh M;
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    dev::Geo geo{};
+    int cpb_psi = 1, cpb_setup = 1, cpb_l2 = 1;
+    DevRows<double> rows64[3];
+    DevRows<float> rows32[3];
+    DevTabs<double> tab64;
+    DevTabs<float> tab32;
+    DevFdm<double> fdm64;
+    DevFdm<float> fdm32;
+    DBuf C, cclass;
+    // data
+    std::vector<double> f_qp, phi_qp;
+    bool have_f = false, have_phi = false;
+    DBuf F, Phi;
+    double normF = 1.0, normPhi = 1.0;
+    // linearisation (hpg_op_setup / Newton setup)
+    double alpha = 1.0, beta = 0.0;
+    int precision = HPG_FP64;
+    bool linearised = false;
+    DBuf om64, om32, sinv64, sinv32;
+    // Krylov
+    KrylovWork<double> kw64;
+    KrylovWork<float> kw32;
+    DBuf partial, kstate, done;
+    int np_u = 0, np_psi = 0, np_dot = 0, np_cap = 0;
+    // Newton state
+    DBuf u, psi, psi_prev, ut, pt, R, u_old, delta64, delta32, rhs32, xk64;
+    // timing
+    bool timing = false;
+    std::map<std::string, TimingGroup> groups;
+
+    // device-buffer calls run on the caller's stream; NULL is the HIP null stream
+    hipStream_t stream(void* s) const { return (hipStream_t)s; }
+    size_t lds_max = 65536;
+    void build(const Mesh& mesh, int device);
+    void set_data(const double* f, const double* phi);
+    void ensure_work();
+    void ensure_linearisation_buffers();
+
+    // operations (all enqueue on stream s)
+    void setup(const double* d_psi, double alpha, double beta, int precision, hipStream_t s);
+    template <typename T>
+    void apply_G(const T* x, T* y, double* partial, const int* done, hipStream_t s);
+    template <typename T>
+    void apply_prec(const T* r, T* z, double* partial, const int* done, hipStream_t s);
+    template <typename T>
+    int minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s);
+    // residual into R; returns (||R_u||^2, ||R_psi||^2) (synchronises)
+    void residual(const double* u, const double* psi, const double* psi_prev, double alpha,
+                  double* R, hipStream_t s, double* nu2, double* np2);
+    double l2_diff(const double* a, const double* b, double* norm_a, hipStream_t s);
+    hpg_status solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stats* st, double* d_u_out,
+                     double* d_psi_out, double* d_lam_out);
+
+    void tstart(const char* grp, hipStream_t s);
+    void tstop(const char* grp, hipStream_t s);
+    ~Problem();
+};
+
+}  // namespace hpg
+
+struct hpg_problem {
+    hpg::Problem P;
+};

@@ -1,0 +1,837 @@
+// Host-side problem set-up, operator entry points, MINRES and the
+// Newton / proximal-point drivers of the hpG library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "problem.h"
+
+namespace hpg {
+
+// ---------------------------------------------------------------------------
+DBuf::~DBuf() {
+    if (p) (void)hipFree(p);
+}
+void DBuf::alloc(size_t b) {
+    if (p && bytes >= b) return;
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+    }
+    bytes = 0;
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        p = nullptr;
+        fail(e == hipErrorOutOfMemory ? HPG_ERR_NOMEM : HPG_ERR_DEVICE,
+             std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    bytes = b;
+}
+
+template <typename T>
+static void upload(DBuf& d, const std::vector<T>& h) {
+    d.alloc(h.size() * sizeof(T));
+    if (!h.empty()) HPG_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+template <typename TO>
+static std::vector<TO> cast(const std::vector<double>& v) {
+    return std::vector<TO>(v.begin(), v.end());
+}
+
+template <typename T>
+dev::URows<T> DevRows<T>::view() const {
+    dev::URows<T> r;
+    r.lenM = lenM.as<int32_t>();
+    r.colM = colM.as<int32_t>();
+    r.aM = aM.as<T>();
+    r.mM = mM.as<T>();
+    r.lenB = lenB.as<int32_t>();
+    r.cellB = cellB.as<int32_t>();
+    r.modeB = modeB.as<int32_t>();
+    r.vB = vB.as<T>();
+    return r;
+}
+template <typename T>
+dev::PsiTabs<T> DevTabs<T>::view() const {
+    dev::PsiTabs<T> t;
+    t.B1 = B1.as<T>();
+    t.Vpsi = Vpsi.as<T>();
+    t.Vu = Vu.as<T>();
+    t.w = w.as<T>();
+    t.Mdiag = Mdiag.as<T>();
+    for (int k = 0; k < 3; ++k) t.h[k] = h[k].as<T>();
+    return t;
+}
+
+template <typename T>
+void KrylovWork<T>::ensure(int64_t n_, int64_t n_u) {
+    if (n >= n_) return;
+    const size_t b = n_ * sizeof(T), bu = n_u * sizeof(T);
+    z.alloc(b);
+    vcur.alloc(b);
+    vprev.alloc(b);
+    q.alloc(b);
+    Gq.alloc(b);
+    wprev.alloc(b);
+    wcur.alloc(b);
+    t1.alloc(bu);
+    t2.alloc(bu);
+    n = n_;
+}
+
+Problem::~Problem() {
+    for (auto& kv : groups) {
+        for (auto e : kv.second.start) (void)hipEventDestroy(e);
+        for (auto e : kv.second.stop) (void)hipEventDestroy(e);
+    }
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+}
+
+// ---------------------------------------------------------------------------
+// small host tensor helper: contract axis ax of a d-D tensor (dims din,
+// direction 0 fastest) with mat(i, j) = mat[i*ld + j] (or transposed)
+static std::vector<double> hcontract(const std::vector<double>& in, int d, int din[3], int ax,
+                                     int nout, const std::vector<double>& mat, int ld,
+                                     bool trans) {
+    int dout[3] = {din[0], din[1], din[2]};
+    dout[ax] = nout;
+    std::vector<double> out((size_t)dout[0] * dout[1] * dout[2], 0.0);
+    const int sax = ax == 0 ? 1 : (ax == 1 ? din[0] : din[0] * din[1]);
+    for (int i2 = 0; i2 < dout[2]; ++i2)
+        for (int i1 = 0; i1 < dout[1]; ++i1)
+            for (int i0 = 0; i0 < dout[0]; ++i0) {
+                int idx[3] = {i0, i1, i2};
+                const int io = idx[ax];
+                idx[ax] = 0;
+                const double* src = in.data() + idx[0] + din[0] * (idx[1] + din[1] * idx[2]);
+                double s = 0.0;
+                for (int j = 0; j < din[ax]; ++j)
+                    s += (trans ? mat[j * ld + io] : mat[io * ld + j]) * src[j * sax];
+                out[i0 + dout[0] * (i1 + dout[1] * i2)] = s;
+            }
+    (void)d;
+    din[ax] = nout;
+    return out;
+}
+
+// dense Cholesky solve A X = B (A n x n SPD, B n x m), row-major
+static void chol_solve(int n, std::vector<double> A, std::vector<double>& B, int m) {
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+        if (s <= 0.0) fail(HPG_ERR_NUMERIC, "Phi-basis stiffness not positive definite");
+        s = std::sqrt(s);
+        A[j * n + j] = s;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = t / s;
+        }
+    }
+    for (int c = 0; c < m; ++c) {
+        for (int i = 0; i < n; ++i) {
+            double t = B[i * m + c];
+            for (int k = 0; k < i; ++k) t -= A[i * n + k] * B[k * m + c];
+            B[i * m + c] = t / A[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double t = B[i * m + c];
+            for (int k = i + 1; k < n; ++k) t -= A[k * n + i] * B[k * m + c];
+            B[i * m + c] = t / A[i * n + i];
+        }
+    }
+}
+
+static std::vector<double> kron(const std::vector<double>& A, int ar, int ac,
+                                const std::vector<double>& B, int br, int bc) {
+    std::vector<double> K((size_t)ar * br * ac * bc);
+    for (int i = 0; i < ar; ++i)
+        for (int j = 0; j < ac; ++j)
+            for (int k = 0; k < br; ++k)
+                for (int l = 0; l < bc; ++l)
+                    K[(size_t)(i * br + k) * (ac * bc) + j * bc + l] = A[i * ac + j] * B[k * bc + l];
+    return K;
+}
+
+// C_K = Bhat^T Ahat^{-1} Bhat for one cell shape (Sec. 4.5, alpha factored out):
+// Ahat = sum_k (x)(AY (2/h_k) in slot k, MY (h_k/2) elsewhere), Bhat = (x)_k BY h_k/2
+static std::vector<double> schur_block(const Mesh& M, const double* hk) {
+    const int P = M.P, d = M.d;
+    const RefTables& T = M.ref;
+    std::vector<double> Ah, Bh;
+    int n = 1;
+    for (int k = 0; k < d; ++k) {
+        // kron with direction k as the slow factor: kron(X_k, current)
+        std::vector<double> ak(P * P), mk(P * P), bk(P * P);
+        for (int i = 0; i < P * P; ++i) {
+            ak[i] = T.AY[i] * (2.0 / hk[k]);
+            mk[i] = T.MY[i] * (0.5 * hk[k]);
+            bk[i] = T.BY[i] * (0.5 * hk[k]);
+        }
+        if (k == 0) {
+            Ah = ak;
+            Bh = bk;
+            n = P;
+            continue;
+        }
+        // current Ah is the (k)-direction sum on the faster factors; mass of the faster ones:
+        // rebuild Mfast = kron of MY over directions < k
+        std::vector<double> Mf = {1.0};
+        int nf = 1;
+        for (int j = 0; j < k; ++j) {
+            std::vector<double> mj(P * P);
+            for (int i = 0; i < P * P; ++i) mj[i] = T.MY[i] * (0.5 * hk[j]);
+            Mf = kron(mj, P, P, Mf, nf, nf);
+            nf *= P;
+        }
+        std::vector<double> A1 = kron(mk, P, P, Ah, n, n);
+        std::vector<double> A2 = kron(ak, P, P, Mf, nf, nf);
+        for (size_t i = 0; i < A1.size(); ++i) A1[i] += A2[i];
+        Ah = A1;
+        Bh = kron(bk, P, P, Bh, n, n);
+        n *= P;
+    }
+    // X = Ahat^{-1} Bhat; C = Bhat^T X
+    std::vector<double> X(Bh);
+    chol_solve(n, Ah, X, n);
+    std::vector<double> C((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += Bh[(size_t)k * n + i] * X[(size_t)k * n + j];
+            C[(size_t)i * n + j] = s;
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) {
+            double s = 0.5 * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
+            C[(size_t)i * n + j] = C[(size_t)j * n + i] = s;
+        }
+    return C;
+}
+
+static int pick_cpb(int per_cell_elems, int elem_bytes, int work_per_cell, size_t budget) {
+    int cpb = std::max(1, 256 / std::max(1, work_per_cell));
+    while (cpb > 1 && (size_t)cpb * per_cell_elems * elem_bytes > budget) --cpb;
+    return cpb;
+}
+
+void Problem::build(const Mesh& mesh, int dev_) {
+    M = mesh;
+    device = dev_;
+    int ndev = 0;
+    HPG_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(HPG_ERR_INVALID_ARG, "no such HIP device");
+    HPG_HIP(hipSetDevice(device));
+    HPG_HIP(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+    {
+        hipDeviceProp_t prop;
+        HPG_HIP(hipGetDeviceProperties(&prop, device));
+        lds_max = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+    }
+    if (M.kind != HPG_OBSTACLE)
+        fail(HPG_ERR_INVALID_ARG, "the GPU path implements the obstacle constraint");
+    // geometry
+    geo.d = M.d;
+    geo.p = M.p;
+    geo.P = M.P;
+    geo.q = M.q;
+    for (int k = 0; k < 3; ++k) {
+        geo.m[k] = M.m[k];
+        geo.n1[k] = M.n1[k];
+    }
+    geo.n_u = M.n_u;
+    geo.n_psi = M.n_psi;
+    geo.n_cells = M.n_cells;
+    geo.Pd = (int)M.Pd;
+    geo.Qd = (int)M.Qd;
+    geo.Ld = (int)M.Ld;
+    int sb = std::max(M.p + 1, M.q), S = 1;
+    for (int k = 0; k < M.d; ++k) S *= sb;
+    geo.S = S;
+    // per-kernel cells per block
+    if ((size_t)5 * S * 8 > lds_max || (size_t)4 * S * 8 > lds_max)
+        fail(HPG_ERR_INVALID_ARG, "(p+1)^d too large for the LDS-staged cell kernels");
+    cpb_psi = pick_cpb(5 * S, 8, geo.Qd, std::min<size_t>(48 * 1024, lds_max));
+    cpb_l2 = pick_cpb(4 * S, 8, geo.Qd, std::min<size_t>(48 * 1024, lds_max));
+    const size_t setup_cell = dev::setup_smem_per_cell(geo);
+    if (setup_cell > lds_max)
+        fail(HPG_ERR_INVALID_ARG, "P^d too large for the in-LDS Schur block inverse");
+    cpb_setup = std::max(1, std::min(256 / std::max(1, geo.Pd), (int)(lds_max / setup_cell)));
+    while (cpb_setup > 1 && setup_cell * cpb_setup > std::min<size_t>(64 * 1024, lds_max)) --cpb_setup;
+    // 1-D rows per direction
+    for (int k = 0; k < 3; ++k) {
+        Rows1D R;
+        if (k < M.d) {
+            build_rows(M, k, R);
+        } else {
+            R.n = 1;
+            R.lenM = {0};
+            R.colM.assign(Rows1D::WM, 0);
+            R.aM.assign(Rows1D::WM, 0.0);
+            R.mM.assign(Rows1D::WM, 0.0);
+            R.lenB = {0};
+            R.colB.assign(Rows1D::WB, 0);
+            R.vB.assign(Rows1D::WB, 0.0);
+        }
+        std::vector<int32_t> cellB(R.colB.size()), modeB(R.colB.size());
+        for (size_t i = 0; i < R.colB.size(); ++i) {
+            cellB[i] = R.colB[i] / std::max(1, M.P);
+            modeB[i] = R.colB[i] % std::max(1, M.P);
+        }
+        upload(rows64[k].lenM, R.lenM);
+        upload(rows64[k].colM, R.colM);
+        upload(rows64[k].aM, R.aM);
+        upload(rows64[k].mM, R.mM);
+        upload(rows64[k].lenB, R.lenB);
+        upload(rows64[k].cellB, cellB);
+        upload(rows64[k].modeB, modeB);
+        upload(rows64[k].vB, R.vB);
+        upload(rows32[k].lenM, R.lenM);
+        upload(rows32[k].colM, R.colM);
+        upload(rows32[k].aM, cast<float>(R.aM));
+        upload(rows32[k].mM, cast<float>(R.mM));
+        upload(rows32[k].lenB, R.lenB);
+        upload(rows32[k].cellB, cellB);
+        upload(rows32[k].modeB, modeB);
+        upload(rows32[k].vB, cast<float>(R.vB));
+        // fast diagonalisation of the 1-D pair (A1, M1)
+        std::vector<double> V, lam;
+        if (k < M.d) {
+            generalized_eig(R.n, R.Adense, R.Mdense, V, lam);
+        } else {
+            V = {1.0};
+            lam = {0.0};
+        }
+        std::vector<double> Vt(V.size());
+        for (int i = 0; i < R.n; ++i)
+            for (int j = 0; j < R.n; ++j) Vt[(size_t)i * R.n + j] = V[(size_t)j * R.n + i];
+        upload(fdm64.V[k], V);
+        upload(fdm64.Vt[k], Vt);
+        upload(fdm64.lam[k], lam);
+        upload(fdm32.V[k], cast<float>(V));
+        upload(fdm32.Vt[k], cast<float>(Vt));
+        upload(fdm32.lam[k], cast<float>(lam));
+    }
+    // reference tables
+    const RefTables& T = M.ref;
+    upload(tab64.B1, T.B1);
+    upload(tab64.Vpsi, T.Vpsi);
+    upload(tab64.Vu, T.Vu);
+    upload(tab64.w, T.w);
+    upload(tab64.Mdiag, T.MpsiDiag);
+    upload(tab32.B1, cast<float>(T.B1));
+    upload(tab32.Vpsi, cast<float>(T.Vpsi));
+    upload(tab32.Vu, cast<float>(T.Vu));
+    upload(tab32.w, cast<float>(T.w));
+    upload(tab32.Mdiag, cast<float>(T.MpsiDiag));
+    for (int k = 0; k < 3; ++k) {
+        std::vector<double> hv;
+        if (k < M.d)
+            for (int c = 0; c < M.m[k]; ++c) hv.push_back(M.h(k, c));
+        else
+            hv.push_back(2.0);   // unused direction: h/2 = 1
+        upload(tab64.h[k], hv);
+        upload(tab32.h[k], cast<float>(hv));
+    }
+    // C_K per distinct cell shape
+    std::map<std::tuple<double, double, double>, int> cls;
+    std::vector<int32_t> cc(M.n_cells);
+    std::vector<double> Call;
+    for (int64_t c = 0; c < M.n_cells; ++c) {
+        int64_t t = c;
+        double hk[3] = {2.0, 2.0, 2.0};
+        for (int k = 0; k < M.d; ++k) {
+            hk[k] = M.h(k, (int)(t % M.m[k]));
+            t /= M.m[k];
+        }
+        auto key = std::make_tuple(hk[0], hk[1], hk[2]);
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+            int id = (int)cls.size();
+            cls[key] = id;
+            std::vector<double> C = schur_block(M, hk);
+            Call.insert(Call.end(), C.begin(), C.end());
+            cc[c] = id;
+        } else {
+            cc[c] = it->second;
+        }
+    }
+    upload(C, Call);
+    upload(cclass, cc);
+    // reduction scratch
+    np_u = (int)((M.n_u + 255) / 256);
+    np_psi = (int)((M.n_cells + cpb_psi - 1) / cpb_psi);
+    np_dot = 512;
+    const int np_l2 = 2 * (int)((M.n_cells + cpb_l2 - 1) / cpb_l2);
+    np_cap = std::max({np_u + np_psi, np_dot + (int)((M.n_cells * M.Pd + 255) / 256), np_l2});
+    partial.alloc((size_t)np_cap * sizeof(double));
+    kstate.alloc(sizeof(dev::KState));
+    done.alloc(sizeof(int));
+    HPG_HIP(hipMemset(done.p, 0, sizeof(int)));
+}
+
+// F_i = (f, v_i), Phi_i = (phi, zeta_i) by the Gauss-Legendre rule (sum-factorised)
+void Problem::set_data(const double* f, const double* phi) {
+    const int d = M.d, q = M.q, L = M.p + 1, P = M.P;
+    const RefTables& T = M.ref;
+    if (f) {
+        std::vector<double> Fh(M.n_u, 0.0);
+        std::vector<double> vals(M.Qd);
+        for (int64_t c = 0; c < M.n_cells; ++c) {
+            int64_t t = c;
+            int cc[3] = {0, 0, 0};
+            double hk[3] = {2, 2, 2};
+            double J = 1.0;
+            for (int k = 0; k < d; ++k) {
+                cc[k] = (int)(t % M.m[k]);
+                t /= M.m[k];
+                hk[k] = M.h(k, cc[k]);
+                J *= 0.5 * hk[k];
+            }
+            for (int64_t j = 0; j < M.Qd; ++j) {
+                int jj[3] = {(int)(j % q), (int)((j / q) % q), (int)(j / (q * q))};
+                double wq = J;
+                for (int k = 0; k < d; ++k) wq *= T.w[jj[k]];
+                vals[j] = wq * f[c * M.Qd + j];
+            }
+            int din[3] = {1, 1, 1};
+            for (int k = 0; k < d; ++k) din[k] = q;
+            std::vector<double> cur = vals;
+            for (int k = 0; k < d; ++k) cur = hcontract(cur, d, din, k, L, T.Vu, L, true);
+            for (int64_t l = 0; l < M.Ld; ++l) {
+                int ll[3] = {(int)(l % L), (int)((l / L) % L), (int)(l / (L * L))};
+                int64_t flat = 0, st = 1;
+                bool ok = true;
+                for (int k = 0; k < d; ++k) {
+                    int g = cc[k] * M.p + ll[k] - 1;
+                    ok = ok && g >= 0 && g < M.n1[k];
+                    flat += (int64_t)g * st;
+                    st *= M.n1[k];
+                }
+                if (ok) Fh[flat] += cur[l];
+            }
+        }
+        double s = 0.0;
+        for (double v : Fh) s += v * v;
+        normF = std::max(std::sqrt(s), 1e-300);
+        upload(F, Fh);
+        have_f = true;
+    }
+    if (phi) {
+        std::vector<double> Ph(M.n_psi, 0.0);
+        std::vector<double> vals(M.Qd);
+        for (int64_t c = 0; c < M.n_cells; ++c) {
+            int64_t t = c;
+            double J = 1.0;
+            for (int k = 0; k < d; ++k) {
+                J *= 0.5 * M.h(k, (int)(t % M.m[k]));
+                t /= M.m[k];
+            }
+            for (int64_t j = 0; j < M.Qd; ++j) {
+                int jj[3] = {(int)(j % q), (int)((j / q) % q), (int)(j / (q * q))};
+                double wq = J;
+                for (int k = 0; k < d; ++k) wq *= T.w[jj[k]];
+                vals[j] = wq * phi[c * M.Qd + j];
+            }
+            int din[3] = {1, 1, 1};
+            for (int k = 0; k < d; ++k) din[k] = q;
+            std::vector<double> cur = vals;
+            for (int k = 0; k < d; ++k) cur = hcontract(cur, d, din, k, P, T.Vpsi, P, true);
+            for (int64_t a = 0; a < M.Pd; ++a) Ph[c * M.Pd + a] = cur[a];
+        }
+        double s = 0.0;
+        for (double v : Ph) s += v * v;
+        normPhi = std::max(std::sqrt(s), 1e-300);
+        upload(Phi, Ph);
+        have_phi = true;
+    }
+}
+
+void Problem::ensure_linearisation_buffers() {
+    const size_t nq = (size_t)M.n_cells * M.Qd;
+    const size_t ns = (size_t)M.n_cells * M.Pd * M.Pd;
+    if (precision == HPG_FP64) {
+        om64.alloc(nq * sizeof(double));
+        sinv64.alloc(ns * sizeof(double));
+    } else {
+        om32.alloc(nq * sizeof(float));
+        sinv32.alloc(ns * sizeof(float));
+    }
+}
+
+void Problem::ensure_work() {
+    const int64_t n = M.n_u + M.n_psi;
+    const size_t b = n * sizeof(double);
+    u.alloc(M.n_u * sizeof(double));
+    psi.alloc(M.n_psi * sizeof(double));
+    psi_prev.alloc(M.n_psi * sizeof(double));
+    ut.alloc(M.n_u * sizeof(double));
+    pt.alloc(M.n_psi * sizeof(double));
+    u_old.alloc(M.n_u * sizeof(double));
+    R.alloc(b);
+    delta64.alloc(b);
+}
+
+// ---------------------------------------------------------------------------
+void Problem::tstart(const char* grp, hipStream_t s) {
+    if (!timing) return;
+    TimingGroup& g = groups[grp];
+    if (g.used == g.start.size()) {
+        hipEvent_t a, b;
+        HPG_HIP(hipEventCreate(&a));
+        HPG_HIP(hipEventCreate(&b));
+        g.start.push_back(a);
+        g.stop.push_back(b);
+    }
+    HPG_HIP(hipEventRecord(g.start[g.used], s));
+}
+void Problem::tstop(const char* grp, hipStream_t s) {
+    if (!timing) return;
+    TimingGroup& g = groups[grp];
+    HPG_HIP(hipEventRecord(g.stop[g.used], s));
+    g.used++;
+}
+
+void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, hipStream_t s) {
+    alpha = alpha_;
+    beta = beta_;
+    precision = prec;
+    ensure_linearisation_buffers();
+    tstart("setup", s);
+    dev::launch_setup(geo, tab64.view(), cpb_setup, d_psi, alpha, beta, C.as<double>(),
+                      cclass.as<int>(), prec == HPG_FP64 ? om64.as<double>() : nullptr,
+                      prec == HPG_FP64 ? nullptr : om32.as<float>(),
+                      prec == HPG_FP64 ? sinv64.as<double>() : nullptr,
+                      prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
+    tstop("setup", s);
+    HPG_HIP(hipGetLastError());
+    linearised = true;
+}
+
+template <typename T>
+struct Sel;
+template <>
+struct Sel<double> {
+    static const DevRows<double>* rows(const Problem& p) { return p.rows64; }
+    static const DevTabs<double>& tabs(const Problem& p) { return p.tab64; }
+    static const DevFdm<double>& fdm(const Problem& p) { return p.fdm64; }
+    static const double* om(const Problem& p) { return p.om64.as<double>(); }
+    static const double* sinv(const Problem& p) { return p.sinv64.as<double>(); }
+    static KrylovWork<double>& kw(Problem& p) { return p.kw64; }
+    static constexpr int prec = HPG_FP64;
+};
+template <>
+struct Sel<float> {
+    static const DevRows<float>* rows(const Problem& p) { return p.rows32; }
+    static const DevTabs<float>& tabs(const Problem& p) { return p.tab32; }
+    static const DevFdm<float>& fdm(const Problem& p) { return p.fdm32; }
+    static const float* om(const Problem& p) { return p.om32.as<float>(); }
+    static const float* sinv(const Problem& p) { return p.sinv32.as<float>(); }
+    static KrylovWork<float>& kw(Problem& p) { return p.kw32; }
+    static constexpr int prec = HPG_MIXED;
+};
+
+template <typename T>
+void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t s) {
+    if (!linearised || precision != Sel<T>::prec)
+        fail(HPG_ERR_INVALID_ARG, "operator not set up for this precision (call hpg_op_setup)");
+    const DevRows<T>* rw = Sel<T>::rows(*this);
+    dev::URows<T> r[3] = {rw[0].view(), rw[1].view(), rw[2].view()};
+    tstart("apply_G", s);
+    dev::launch_u_side<T>(geo, r, (T)alpha, x, x + M.n_u, nullptr, nullptr, y, part, dn,
+                          dev::MODE_APPLY, s);
+    dev::launch_psi_side<T>(geo, Sel<T>::tabs(*this).view(), cpb_psi, (T)beta, x, x + M.n_u,
+                            Sel<T>::om(*this), nullptr, y + M.n_u, part ? part + np_u : nullptr,
+                            dn, dev::MODE_APPLY, s);
+    tstop("apply_G", s);
+}
+
+template <typename T>
+void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStream_t s) {
+    if (!linearised || precision != Sel<T>::prec)
+        fail(HPG_ERR_INVALID_ARG, "operator not set up for this precision (call hpg_op_setup)");
+    KrylovWork<T>& kw = Sel<T>::kw(*this);
+    kw.ensure(M.n_u + M.n_psi, M.n_u);
+    const DevFdm<T>& F = Sel<T>::fdm(*this);
+    T* t1 = kw.t1.template as<T>();
+    T* t2 = kw.t2.template as<T>();
+    tstart("apply_prec", s);
+    // A-block: z_u = (alpha A)^{-1} r_u by fast diagonalisation, d forward
+    // passes with V^T, eigenvalue division, d backward passes with V
+    const int d = M.d;
+    const T* src = r;
+    int pass = 0;
+    const int npass = 2 * d;
+    for (int ph = 0; ph < 2; ++ph) {
+        for (int k = 0; k < d; ++k) {
+            ++pass;
+            T* dst = (pass == npass) ? z : ((src == t1) ? t2 : t1);
+            const T* Mat = ph == 0 ? F.Vt[k].template as<T>() : F.V[k].template as<T>();
+            const int N = M.n1[k];
+            if (k == 0) {
+                dev::launch_gemm_right<T>(M.n_u / N, N, src, Mat, dst, dn, s);
+            } else {
+                int64_t inner = 1;
+                for (int j = 0; j < k; ++j) inner *= M.n1[j];
+                const int64_t outer = M.n_u / (inner * N);
+                dev::launch_gemm_left<T>(outer, N, inner, src, Mat, dst, dn, s);
+            }
+            src = dst;
+        }
+        if (ph == 0)
+            dev::launch_fdm_scale<T>(geo, F.lam[0].template as<T>(), F.lam[1].template as<T>(),
+                                     F.lam[2].template as<T>(), (T)(1.0 / alpha),
+                                     const_cast<T*>(src), dn, s);
+    }
+    if (part) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
+    dev::launch_prec_psi<T>(M.n_cells, (int)M.Pd, Sel<T>::sinv(*this), r + M.n_u, z + M.n_u,
+                            part ? part + np_dot : nullptr, dn, s);
+    tstop("apply_prec", s);
+}
+
+static double host_sum(const double* d_part, int n, hipStream_t s) {
+    std::vector<double> h(n);
+    HPG_HIP(hipMemcpyAsync(h.data(), d_part, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HPG_HIP(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double v : h) t += v;
+    return t;
+}
+
+template <typename T>
+int Problem::minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s) {
+    const int64_t n = M.n_u + M.n_psi;
+    KrylovWork<T>& kw = Sel<T>::kw(*this);
+    kw.ensure(n, M.n_u);
+    T* z = kw.z.template as<T>();
+    T* vcur = kw.vcur.template as<T>();
+    T* vprev = kw.vprev.template as<T>();
+    T* q = kw.q.template as<T>();
+    T* Gq = kw.Gq.template as<T>();
+    T* wprev = kw.wprev.template as<T>();
+    T* wcur = kw.wcur.template as<T>();
+    double* part = partial.as<double>();
+    auto* st = kstate.as<dev::KState>();
+    int* dn = done.as<int>();
+    HPG_HIP(hipMemsetAsync(dn, 0, sizeof(int), s));
+    // z1 = M^{-1} b, gamma1^2 = <z1, b>
+    apply_prec<T>(b, z, part, dn, s);
+    const int npP = np_dot + (int)((M.n_cells * M.Pd + 255) / 256);
+    dev::launch_kr_init(st, part, npP, rtol, maxit, dn, s);
+    dev::launch_kr_start<T>(n, st, b, z, vcur, vprev, q, wprev, wcur, x, s);
+    HPG_HIP(hipGetLastError());
+    int it = 0;
+    int hdone = 0;
+    while (it < maxit) {
+        const int nc = std::min(chunk, maxit - it);
+        for (int j = 0; j < nc; ++j) {
+            apply_G<T>(q, Gq, part, dn, s);
+            dev::launch_kr_delta(st, part, np_u + np_psi, s);
+            tstart("minres_vec", s);
+            dev::launch_kr_vhat<T>(n, st, Gq, vcur, vprev, dn, s);
+            tstop("minres_vec", s);
+            apply_prec<T>(vprev, z, part, dn, s);
+            dev::launch_kr_rotate(st, part, npP, dn, s);
+            tstart("minres_vec", s);
+            dev::launch_kr_update<T>(n, st, q, wprev, wcur, x, vprev, z, dn, s);
+            tstop("minres_vec", s);
+            dev::launch_kr_finish(st, dn, s);
+            std::swap(vprev, vcur);
+            std::swap(wprev, wcur);
+        }
+        it += nc;
+        HPG_HIP(hipMemcpyAsync(&hdone, dn, sizeof(int), hipMemcpyDeviceToHost, s));
+        HPG_HIP(hipStreamSynchronize(s));
+        if (hdone) break;
+    }
+    HPG_HIP(hipGetLastError());
+    dev::KState hs;
+    HPG_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HPG_HIP(hipStreamSynchronize(s));
+    if (hs.breakdown && hs.iters == 0 && hs.gamma1 != 0.0 && hs.gamma1 == hs.gamma1)
+        fail(HPG_ERR_NUMERIC, "MINRES breakdown");
+    if (!(hs.gamma1 == hs.gamma1)) fail(HPG_ERR_NUMERIC, "MINRES: non-finite right-hand side");
+    return hs.iters;
+}
+
+void Problem::residual(const double* uu, const double* pp, const double* pprev, double alpha_,
+                       double* RR, hipStream_t s, double* nu2, double* np2) {
+    if (!have_f || !have_phi) fail(HPG_ERR_INVALID_ARG, "forcing and obstacle must be set");
+    dev::URows<double> r[3] = {rows64[0].view(), rows64[1].view(), rows64[2].view()};
+    double* part = partial.as<double>();
+    tstart("residual", s);
+    dev::launch_u_side<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR, part, nullptr,
+                               dev::MODE_RES, s);
+    dev::launch_psi_side<double>(geo, tab64.view(), cpb_psi, 0.0, uu, pp, nullptr,
+                                 Phi.as<double>(), RR + M.n_u, part + np_u, nullptr,
+                                 dev::MODE_RES, s);
+    tstop("residual", s);
+    HPG_HIP(hipGetLastError());
+    std::vector<double> h(np_u + np_psi);
+    HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HPG_HIP(hipStreamSynchronize(s));
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < np_u; ++i) a += h[i];
+    for (int i = 0; i < np_psi; ++i) b += h[np_u + i];
+    *nu2 = a;
+    *np2 = b;
+}
+
+double Problem::l2_diff(const double* a, const double* b, double* norm_a, hipStream_t s) {
+    double* part = partial.as<double>();
+    dev::launch_l2(geo, tab64.view(), cpb_l2, a, b, part, s);
+    HPG_HIP(hipGetLastError());
+    const int nb = (int)((M.n_cells + cpb_l2 - 1) / cpb_l2);
+    std::vector<double> h(2 * nb);
+    HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HPG_HIP(hipStreamSynchronize(s));
+    double d2 = 0.0, a2 = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        d2 += h[2 * i];
+        a2 += h[2 * i + 1];
+    }
+    *norm_a = std::sqrt(std::max(a2, 0.0));
+    return std::sqrt(std::max(d2, 0.0));
+}
+
+// ---------------------------------------------------------------------------
+// The proximal-point loop with Newton (paper Sec. 2.1 / Sec. 4; readings on
+// the alpha schedule, the Newton stop, the backtracking line search and the
+// outer stop are the ones documented in the oracle and in hpg.h).
+hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stats* st,
+                          double* d_u_out, double* d_psi_out, double* d_lam_out) {
+    if (!have_f || !have_phi) fail(HPG_ERR_INVALID_ARG, "forcing and obstacle must be set");
+    auto t0 = std::chrono::steady_clock::now();
+    ensure_work();
+    const int64_t n = M.n_u + M.n_psi;
+    const bool mixed = o.precision == HPG_MIXED;
+    if (mixed) {
+        delta32.alloc(n * sizeof(float));
+        rhs32.alloc(n * sizeof(float));
+    } else {
+        xk64.alloc(n * sizeof(double));
+    }
+    double* du = u.as<double>();
+    double* dp = psi.as<double>();
+    double* dpp = psi_prev.as<double>();
+    double* dut = ut.as<double>();
+    double* dpt = pt.as<double>();
+    double* dR = R.as<double>();
+    double* dd = delta64.as<double>();
+    HPG_HIP(hipMemsetAsync(du, 0, M.n_u * sizeof(double), s));
+    HPG_HIP(hipMemsetAsync(dp, 0, M.n_psi * sizeof(double), s));
+    HPG_HIP(hipMemsetAsync(dpp, 0, M.n_psi * sizeof(double), s));
+    hpg_solve_stats S{};
+    S.status = HPG_OK;
+    double alpha_k = o.alpha0;
+    int k = 0;
+    const int kmax = o.fixed_prox_steps > 0 ? o.fixed_prox_steps : o.max_prox;
+    bool ok = true;
+    double last_err = 0.0;
+    double alpha_used = alpha_k;
+    while (k < kmax) {
+        ++k;
+        HPG_HIP(hipMemcpyAsync(u_old.p, du, M.n_u * sizeof(double), hipMemcpyDeviceToDevice, s));
+        // ---- Newton on the subproblem with (alpha_k, psi_prev)
+        bool conv = false;
+        for (int it = 0; it <= o.max_newton; ++it) {
+            double nu2, np2;
+            residual(du, dp, dpp, alpha_k, dR, s, &nu2, &np2);
+            const double err = std::sqrt(nu2) / (alpha_k * normF) + std::sqrt(np2) / normPhi;
+            last_err = err;
+            if (!std::isfinite(err)) break;
+            if (err <= o.newton_tol) {
+                conv = true;
+                break;
+            }
+            if (it == o.max_newton) break;
+            setup(dp, alpha_k, o.beta, mixed ? HPG_MIXED : HPG_FP64, s);
+            int its;
+            if (mixed) {
+                float* b32 = rhs32.as<float>();
+                float* x32 = delta32.as<float>();
+                dev::launch_convert<double, float>(n, dR, b32, -1.0, s);
+                its = minres<float>(b32, x32, o.krylov_rtol, o.max_krylov, o.krylov_chunk, s);
+                dev::launch_convert<float, double>(n, x32, dd, 1.0, s);
+            } else {
+                // b = -R in dd, MINRES into xk64, then delta = xk64
+                dev::launch_convert<double, double>(n, dR, dd, -1.0, s);
+                its = minres<double>(dd, xk64.as<double>(), o.krylov_rtol, o.max_krylov,
+                                     o.krylov_chunk, s);
+                HPG_HIP(hipMemcpyAsync(dd, xk64.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            S.krylov_iters += its;
+            S.newton_iters += 1;
+            // backtracking on ||(R_u / alpha, R_psi)||
+            const double m0 = std::sqrt(nu2 / (alpha_k * alpha_k) + np2);
+            double t = 1.0;
+            bool acc = false;
+            for (int hv = 0; hv <= 30; ++hv) {
+                dev::launch_axpy_to<double>(M.n_u, du, t, dd, dut, s);
+                dev::launch_axpy_to<double>(M.n_psi, dp, t, dd + M.n_u, dpt, s);
+                double a2, b2;
+                residual(dut, dpt, dpp, alpha_k, dR, s, &a2, &b2);
+                const double m1 = std::sqrt(a2 / (alpha_k * alpha_k) + b2);
+                if (m1 <= (1.0 - 1e-4 * t) * m0) {
+                    acc = true;
+                    break;
+                }
+                t *= 0.5;
+                S.line_search_halvings += 1;
+            }
+            if (!acc) {
+                conv = err <= o.stall_tol;
+                break;
+            }
+            std::swap(du, dut);
+            std::swap(dp, dpt);
+        }
+        alpha_used = alpha_k;
+        if (!conv) {
+            ok = false;
+            break;
+        }
+        // lambda_k and psi_prev <- psi
+        const bool last_possible = (k == kmax);
+        double nrm_u;
+        const double diff = l2_diff(du, u_old.as<double>(), &nrm_u, s);
+        const bool stop = o.fixed_prox_steps > 0 ? last_possible
+                                                 : (diff <= o.prox_tol * nrm_u || last_possible);
+        if (stop && d_lam_out)
+            dev::launch_lambda(M.n_psi, dpp, dp, alpha_k, d_lam_out, s);
+        HPG_HIP(hipMemcpyAsync(dpp, dp, M.n_psi * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (stop) break;
+        alpha_k = std::min(alpha_k * o.alpha_factor, o.alpha_max);
+    }
+    // outputs
+    if (d_u_out) HPG_HIP(hipMemcpyAsync(d_u_out, du, M.n_u * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d_psi_out)
+        HPG_HIP(hipMemcpyAsync(d_psi_out, dp, M.n_psi * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HPG_HIP(hipStreamSynchronize(s));
+    // keep the internal buffers pointing at the final iterate
+    if (du != u.as<double>()) std::swap(u.p, ut.p);
+    if (dp != psi.as<double>()) std::swap(psi.p, pt.p);
+    auto t1 = std::chrono::steady_clock::now();
+    S.prox_steps = k;
+    S.newton_error = last_err;
+    S.alpha_last = alpha_used;
+    S.seconds = std::chrono::duration<double>(t1 - t0).count();
+    S.status = ok ? HPG_OK : HPG_NOT_CONVERGED;
+    if (st) *st = S;
+    return S.status;
+}
+
+template void Problem::apply_G<double>(const double*, double*, double*, const int*, hipStream_t);
+template void Problem::apply_G<float>(const float*, float*, double*, const int*, hipStream_t);
+template void Problem::apply_prec<double>(const double*, double*, double*, const int*, hipStream_t);
+template void Problem::apply_prec<float>(const float*, float*, double*, const int*, hipStream_t);
+template int Problem::minres<double>(const double*, double*, double, int, int, hipStream_t);
+template int Problem::minres<float>(const float*, float*, double, int, int, hipStream_t);
+
+}  // namespace hpg

@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libhpg.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts Python/NumPy
+/torch arguments to pointers and sizes and raises on non-OK statuses.  If the
+library has not been built it raises immediately: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpg.so")
+
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
+ERR_INVALID_ARG, ERR_NOMEM, ERR_DEVICE, ERR_NUMERIC, ERR_BUDGET = -1, -2, -3, -4, -5
+OBSTACLE, GRADIENT = 0, 1
+FP64, MIXED = 0, 1
+
+
+class HpgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("hpg status %d: %s" % (status, msg))
+        self.status = status
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("constraint", ctypes.c_int32),
+                ("ncells", ctypes.c_int32 * 3), ("n_cells", ctypes.c_int64),
+                ("n_u", ctypes.c_int64), ("n_psi", ctypes.c_int64), ("n_qp", ctypes.c_int64)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("alpha0", ctypes.c_double),
+                ("alpha_factor", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("max_prox", ctypes.c_int32), ("prox_tol", ctypes.c_double),
+                ("fixed_prox_steps", ctypes.c_int32), ("newton_tol", ctypes.c_double),
+                ("stall_tol", ctypes.c_double), ("max_newton", ctypes.c_int32),
+                ("krylov_rtol", ctypes.c_double), ("max_krylov", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("krylov_chunk", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("prox_steps", ctypes.c_int32),
+                ("newton_iters", ctypes.c_int32), ("line_search_halvings", ctypes.c_int32),
+                ("krylov_iters", ctypes.c_int64), ("newton_error", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("alpha_last", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# every symbol include/hpg.h declares (checked by the CPU test-suite)
+EXPORTS = ["hpg_last_error", "hpg_create_mesh", "hpg_destroy_mesh", "hpg_get_mesh_info",
+           "hpg_quadrature_points", "hpg_create_problem", "hpg_destroy_problem",
+           "hpg_set_forcing", "hpg_set_obstacle", "hpg_default_opts", "hpg_solve",
+           "hpg_solve_device", "hpg_op_setup", "hpg_op_apply_G", "hpg_op_apply_prec",
+           "hpg_op_minres", "hpg_op_residual", "hpg_set_kernel_timing", "hpg_kernel_time"]
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libhpg.so is not built (run paper_2412_13733_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                          ctypes.c_size_t)
+    sig = {
+        "hpg_last_error": ([], ctypes.c_char_p),
+        "hpg_create_mesh": ([ctypes.c_int, P, P, I32, I32, P], ctypes.c_int),
+        "hpg_destroy_mesh": ([P], None),
+        "hpg_get_mesh_info": ([P, P], ctypes.c_int),
+        "hpg_quadrature_points": ([P, P], ctypes.c_int),
+        "hpg_create_problem": ([P, ctypes.c_int, P], ctypes.c_int),
+        "hpg_destroy_problem": ([P], None),
+        "hpg_set_forcing": ([P, P, SZ], ctypes.c_int),
+        "hpg_set_obstacle": ([P, P, SZ], ctypes.c_int),
+        "hpg_default_opts": ([P], None),
+        "hpg_solve": ([P, P, P, P, P, P], ctypes.c_int),
+        "hpg_solve_device": ([P, P, P, P, P, P], ctypes.c_int),
+        "hpg_op_setup": ([P, P, D, D, I32, P], ctypes.c_int),
+        "hpg_op_apply_G": ([P, P, P, P], ctypes.c_int),
+        "hpg_op_apply_prec": ([P, P, P, P], ctypes.c_int),
+        "hpg_op_minres": ([P, P, P, D, I32, P, P], ctypes.c_int),
+        "hpg_op_residual": ([P, P, P, P, D, P, P], ctypes.c_int),
+        "hpg_set_kernel_timing": ([P, I32], ctypes.c_int),
+        "hpg_kernel_time": ([P, ctypes.c_char_p, P, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(st, allow=(OK,)):
+    if st not in allow:
+        raise HpgError(st, load().hpg_last_error().decode())
+    return st
+
+
+def _dptr(a, n=None):
+    """Pointer of a contiguous NumPy array (host)."""
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tptr(t):
+    """Device pointer of a contiguous torch tensor."""
+    assert t.is_contiguous()
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_opts(**kw):
+    o = SolveOpts()
+    load().hpg_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Mesh:
+    def __init__(self, dim, ncells, p, constraint=OBSTACLE, breaks=None):
+        lib = load()
+        vals = [int(v) for v in ncells] + [1] * max(0, 3 - len(ncells))
+        nc = (ctypes.c_int32 * len(vals))(*vals)
+        self._keep = []
+        bp = None
+        if breaks is not None:
+            arrs = [np.ascontiguousarray(b, dtype=np.float64) for b in breaks]
+            self._keep = arrs
+            ptrs = (ctypes.c_void_p * 3)(*([a.ctypes.data for a in arrs] + [None] * (3 - len(arrs))))
+            self._keep.append(ptrs)
+            bp = ctypes.cast(ptrs, ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(lib.hpg_create_mesh(dim, ctypes.cast(nc, ctypes.c_void_p), bp, p, constraint,
+                                   ctypes.byref(h)))
+        self.h = h
+        inf = MeshInfo()
+        _check(lib.hpg_get_mesh_info(h, ctypes.byref(inf)))
+        self.info = inf
+        self.dim, self.p, self.q, self.P = inf.dim, inf.p, inf.q, inf.P
+        self.n_u, self.n_psi, self.n_qp, self.n_cells = inf.n_u, inf.n_psi, inf.n_qp, inf.n_cells
+
+    def quadrature_points(self):
+        x = np.zeros((self.n_qp, self.dim))
+        _check(load().hpg_quadrature_points(self.h, _dptr(x)))
+        return x
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpg_destroy_mesh(self.h)
+            self.h = None
+
+
+class Problem:
+    def __init__(self, mesh, device=0):
+        self.mesh = mesh
+        h = ctypes.c_void_p()
+        _check(load().hpg_create_problem(mesh.h, device, ctypes.byref(h)))
+        self.h = h
+
+    def set_forcing(self, f_qp):
+        f = np.ascontiguousarray(f_qp, dtype=np.float64).reshape(-1)
+        _check(load().hpg_set_forcing(self.h, _dptr(f), f.size))
+
+    def set_obstacle(self, phi_qp):
+        f = np.ascontiguousarray(phi_qp, dtype=np.float64).reshape(-1)
+        _check(load().hpg_set_obstacle(self.h, _dptr(f), f.size))
+
+    def solve(self, opts=None, want_lambda=False):
+        m = self.mesh
+        u = np.zeros(m.n_u)
+        psi = np.zeros(m.n_psi)
+        lam = np.zeros(m.n_psi) if want_lambda else None
+        st = SolveStats()
+        o = opts if opts is not None else default_opts()
+        rc = load().hpg_solve(self.h, ctypes.byref(o), _dptr(u), _dptr(psi),
+                              _dptr(lam) if lam is not None else None, ctypes.byref(st))
+        _check(rc, allow=(OK, NOT_CONVERGED))
+        return u, psi, lam, st
+
+    def solve_device(self, d_u, d_psi, opts=None, stream=None):
+        st = SolveStats()
+        o = opts if opts is not None else default_opts()
+        rc = load().hpg_solve_device(self.h, ctypes.byref(o), _tptr(d_u), _tptr(d_psi),
+                                     ctypes.c_void_p(stream) if stream else None, ctypes.byref(st))
+        _check(rc, allow=(OK, NOT_CONVERGED))
+        return st
+
+    # operator-level calls on torch device tensors
+    def op_setup(self, d_psi, alpha, beta=0.0, precision=FP64, stream=None):
+        _check(load().hpg_op_setup(self.h, _tptr(d_psi), alpha, beta, precision,
+                                   ctypes.c_void_p(stream) if stream else None))
+
+    def op_apply_G(self, x, y, stream=None):
+        _check(load().hpg_op_apply_G(self.h, _tptr(x), _tptr(y),
+                                     ctypes.c_void_p(stream) if stream else None))
+
+    def op_apply_prec(self, r, z, stream=None):
+        _check(load().hpg_op_apply_prec(self.h, _tptr(r), _tptr(z),
+                                        ctypes.c_void_p(stream) if stream else None))
+
+    def op_minres(self, b, x, rtol, max_iters, stream=None):
+        it = ctypes.c_int32(0)
+        _check(load().hpg_op_minres(self.h, _tptr(b), _tptr(x), rtol, max_iters, ctypes.byref(it),
+                                    ctypes.c_void_p(stream) if stream else None))
+        return it.value
+
+    def op_residual(self, u, psi, psi_prev, alpha, R, stream=None):
+        _check(load().hpg_op_residual(self.h, _tptr(u), _tptr(psi), _tptr(psi_prev), alpha,
+                                      _tptr(R), ctypes.c_void_p(stream) if stream else None))
+
+    def set_kernel_timing(self, enable):
+        _check(load().hpg_set_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, group):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(load().hpg_kernel_time(self.h, group.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpg_destroy_problem(self.h)
+            self.h = None

@@ -1,0 +1,160 @@
+"""GPU parity: the HIP operators and solves against the oracle, element by
+element, on seeded inputs.  Sizes span several thread blocks with ragged
+tails; tolerances: FP64 operators 1e-12 relative (max-norm), FP32 operators
+2e-5, FP64 solves 1e-10 relative L2 (the bar stated for the FP64 path)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import lvpp, precond, mesh as OM
+import workloads as W
+
+from gpu_common import build_pair, log, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+OP_CASES = [
+    (1, 16, 4, None),
+    (1, 37, 2, None),
+    (2, 5, 6, None),
+    (2, 9, 3, None),
+    (2, 4, 5, [np.array([0, .1, .45, .7, 1.0]), np.array([0, .3, .55, .9, 1.0])]),
+    (3, 3, 5, None),
+    (3, 5, 2, None),
+]
+
+
+def _data(dim):
+    return W.w1d() if dim == 1 else (W.w2d(0) if dim == 2 else W.w3d())
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+@pytest.mark.parametrize("dim,m,p,breaks", OP_CASES)
+@pytest.mark.parametrize("beta", [0.0, 1e-3])
+def test_apply_G_fp64(dim, m, p, breaks, beta):
+    log("apply_G fp64", dim, m, p, beta)
+    mesh, prob, sysm = build_pair(dim, m, p, _data(dim), breaks)
+    rng = np.random.default_rng(7)
+    psi = 0.7 * rng.standard_normal(mesh.n_psi)
+    alpha = 3.7
+    x = rng.standard_normal(mesh.n_u + mesh.n_psi)
+    prob.op_setup(_dev(psi), alpha, beta, precision=0)
+    y = torch.zeros(mesh.n_u + mesh.n_psi, dtype=torch.float64, device="cuda")
+    prob.op_apply_G(_dev(x), y)
+    yu, yp = precond.apply_G(sysm, psi, alpha, beta, x[:mesh.n_u], x[mesh.n_u:])
+    yg = y.cpu().numpy()
+    assert rel(yg[:mesh.n_u], yu) < 1e-12
+    assert rel(yg[mesh.n_u:], yp) < 1e-12
+
+
+@pytest.mark.parametrize("dim,m,p,breaks", OP_CASES)
+def test_apply_prec_fp64(dim, m, p, breaks):
+    log("apply_prec fp64", dim, m, p)
+    mesh, prob, sysm = build_pair(dim, m, p, _data(dim), breaks)
+    rng = np.random.default_rng(11)
+    psi = 0.5 * rng.standard_normal(mesh.n_psi)
+    alpha, beta = 5.0, 1e-4
+    r = rng.standard_normal(mesh.n_u + mesh.n_psi)
+    prob.op_setup(_dev(psi), alpha, beta, precision=0)
+    z = torch.zeros_like(_dev(r))
+    prob.op_apply_prec(_dev(r), z)
+    zu, zp = precond.apply_prec(sysm, psi, alpha, beta, r[:mesh.n_u], r[mesh.n_u:])
+    zg = z.cpu().numpy()
+    assert rel(zg[:mesh.n_u], zu) < 1e-10
+    assert rel(zg[mesh.n_u:], zp) < 1e-10
+
+
+@pytest.mark.parametrize("dim,m,p,breaks", OP_CASES[::2])
+def test_operators_fp32(dim, m, p, breaks):
+    log("operators fp32", dim, m, p)
+    mesh, prob, sysm = build_pair(dim, m, p, _data(dim), breaks)
+    rng = np.random.default_rng(3)
+    psi = 0.5 * rng.standard_normal(mesh.n_psi)
+    alpha, beta = 2.0, 0.0
+    x = rng.standard_normal(mesh.n_u + mesh.n_psi)
+    prob.op_setup(_dev(psi), alpha, beta, precision=1)
+    y = torch.zeros(mesh.n_u + mesh.n_psi, dtype=torch.float32, device="cuda")
+    prob.op_apply_G(_dev(x, torch.float32), y)
+    yu, yp = precond.apply_G(sysm, psi, alpha, beta, x[:mesh.n_u], x[mesh.n_u:])
+    yg = y.double().cpu().numpy()
+    assert rel(yg[:mesh.n_u], yu) < 2e-5
+    assert rel(yg[mesh.n_u:], yp) < 2e-5
+    z = torch.zeros_like(y)
+    prob.op_apply_prec(_dev(x, torch.float32), z)
+    zu, zp = precond.apply_prec(sysm, psi, alpha, beta, x[:mesh.n_u], x[mesh.n_u:])
+    zg = z.double().cpu().numpy()
+    assert rel(zg[:mesh.n_u], zu) < 1e-4
+    assert rel(zg[mesh.n_u:], zp) < 1e-4
+
+
+@pytest.mark.parametrize("dim,m,p,breaks", OP_CASES)
+def test_residual_fp64(dim, m, p, breaks):
+    log("residual", dim, m, p)
+    mesh, prob, sysm = build_pair(dim, m, p, _data(dim), breaks)
+    rng = np.random.default_rng(5)
+    u = 0.1 * rng.standard_normal(mesh.n_u)
+    psi = 0.8 * rng.standard_normal(mesh.n_psi)
+    psi_prev = 0.8 * rng.standard_normal(mesh.n_psi)
+    alpha = 8.0
+    R = torch.zeros(mesh.n_u + mesh.n_psi, dtype=torch.float64, device="cuda")
+    prob.op_residual(_dev(u), _dev(psi), _dev(psi_prev), alpha, R)
+    Ru, Rp = sysm.residual(u, psi, psi_prev, alpha)
+    Rg = R.cpu().numpy()
+    assert rel(Rg[:mesh.n_u], Ru) < 1e-12
+    assert rel(Rg[mesh.n_u:], Rp) < 1e-12
+
+
+@pytest.mark.parametrize("dim,m,p", [(1, 16, 4), (2, 6, 4), (3, 3, 3)])
+def test_minres_solves_newton_system(dim, m, p):
+    log("minres", dim, m, p)
+    mesh, prob, sysm = build_pair(dim, m, p, _data(dim))
+    rng = np.random.default_rng(9)
+    psi = 0.5 * rng.standard_normal(mesh.n_psi)
+    alpha = 4.0
+    b = rng.standard_normal(mesh.n_u + mesh.n_psi)
+    prob.op_setup(_dev(psi), alpha, 0.0, precision=0)
+    x = torch.zeros_like(_dev(b))
+    its = prob.op_minres(_dev(b), x, 1e-12, 3000)
+    G = sysm.jacobian(psi, alpha, 0.0)
+    xr = spla.spsolve(G, b)
+    xg = x.cpu().numpy()
+    assert 0 < its < 3000
+    assert np.linalg.norm(xg - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+SOLVE_CASES = [
+    (1, 16, 4, "w1d"),
+    (1, 16, 2, "w1d"),
+    (2, 6, 4, "w2d"),
+    (2, 5, 2, "w2d"),
+    (3, 3, 3, "w3d"),
+]
+
+
+@pytest.mark.parametrize("dim,m,p,which", SOLVE_CASES)
+def test_full_solve_matches_oracle_fp64(dim, m, p, which):
+    log("solve fp64", dim, m, p, which)
+    data = {"w1d": W.w1d(), "w2d": W.w2d(0), "w3d": W.w3d()}[which]
+    mesh, prob, sysm = build_pair(dim, m, p, data)
+    ro = lvpp.solve(sysm, lvpp.Options())
+    assert ro.converged
+    opts = prob_opts(fixed=ro.prox_steps)
+    u, psi, lam, st = prob.solve(opts, want_lambda=True)
+    log("  oracle K", ro.prox_steps, "newton", ro.newton, "| gpu", st.as_dict())
+    assert st.status == 0
+    assert st.prox_steps == ro.prox_steps
+    eu = sysm.l2_norm_u(u - ro.u) / sysm.l2_norm_u(ro.u)
+    el = np.linalg.norm(lam - ro.lam) / max(np.linalg.norm(ro.lam), 1e-300)
+    log("  rel L2 u", eu, "rel lambda", el)
+    assert eu < 1e-10
+    assert el < 1e-8
+
+
+def prob_opts(fixed=0, precision=0, **kw):
+    from paper_2412_13733_amd import hpg
+    return hpg.default_opts(fixed_prox_steps=fixed, precision=precision, **kw)

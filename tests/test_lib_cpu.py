@@ -1,0 +1,67 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/hpg.h declares, and its host-only calls (mesh, DOF counts,
+quadrature points, argument validation) behave as documented.  No kernel is
+launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2412_13733_amd import hpg
+from oracle import mesh as OM
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "hpg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(hpg_[A-Za-z_0-9]+)\s*\(", src)
+    return sorted(set(n for n in names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hpg.load()
+    declared = header_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(hpg.EXPORTS) == declared
+
+
+@pytest.mark.parametrize("dim,m,p", [(1, 16, 4), (2, 5, 6), (3, 3, 2), (2, 7, 3)])
+def test_mesh_info_and_counts(dim, m, p):
+    mesh = hpg.Mesh(dim, [m] * dim, p)
+    n1 = m * p - 1
+    assert mesh.n_u == n1 ** dim
+    assert mesh.n_psi == m ** dim * (p - 1) ** dim
+    assert mesh.n_qp == m ** dim * (p + 1) ** dim
+    om = OM.uniform_mesh(dim, m, p)
+    assert (om.n_u, om.n_psi, om.n_qp) == (mesh.n_u, mesh.n_psi, mesh.n_qp)
+
+
+@pytest.mark.parametrize("dim,p", [(1, 4), (2, 3), (3, 2)])
+def test_quadrature_points_match_oracle(dim, p):
+    br = [np.array([0.0, 0.13, 0.5, 1.0]), np.array([0.0, 0.7, 1.0]), np.array([0.0, 0.25, 1.0])][:dim]
+    mesh = hpg.Mesh(dim, [len(b) - 1 for b in br], p, breaks=br)
+    x = mesh.quadrature_points()
+    xo = OM.TensorMesh(br, p).quadrature_points()
+    assert np.max(np.abs(x - xo)) < 2e-16 * 4
+
+
+def test_invalid_arguments_are_rejected():
+    with pytest.raises(hpg.HpgError) as e:
+        hpg.Mesh(2, [4, 4], 1)                  # obstacle needs p >= 2
+    assert e.value.status == hpg.ERR_INVALID_ARG
+    with pytest.raises(hpg.HpgError):
+        hpg.Mesh(4, [2, 2, 2, 2], 3)            # d <= 3
+    with pytest.raises(hpg.HpgError):
+        hpg.Mesh(1, [0], 3)                      # at least one cell
+    with pytest.raises(hpg.HpgError):
+        hpg.Mesh(1, [2], 3, breaks=[np.array([0.0, 0.7, 0.6])])   # not increasing
+    with pytest.raises(hpg.HpgError):
+        hpg.Mesh(1, [2], 3, breaks=[np.array([0.0, 0.5, 2.0])])   # must end at 1
+    m = hpg.Mesh(1, [3], 2, constraint=hpg.GRADIENT)
+    assert m.P == 2 and m.n_psi == 3 * 2
