@@ -121,6 +121,8 @@ typedef struct hpg_solve_opts {
     double beta;            /* E_beta weight, Jacobian only (default 0) */
     int32_t precision;      /* HPG_FP64 or HPG_MIXED */
     int32_t krylov_chunk;   /* iterations enqueued between convergence checks (default 16) */
+    int32_t inexact_newton; /* 1: MINRES tolerance eta_k = clamp(1e-6 err_k, krylov_rtol, 1e-6)
+                               from the current Newton error err_k (default 0: krylov_rtol) */
 } hpg_solve_opts;
 
 void hpg_default_opts(hpg_solve_opts* opts);
@@ -168,12 +170,20 @@ hpg_status hpg_op_minres(hpg_problem* prob, const void* d_b, void* d_x, double r
 hpg_status hpg_op_residual(hpg_problem* prob, const double* d_u, const double* d_psi,
                            const double* d_psi_prev, double alpha, double* d_R, void* stream);
 
+/* L2 norms in function space (Gauss-Legendre, exact for degree 2p):
+ * *diff = ||a_h - b_h||_{L2(Omega)}, *norm_b = ||b_h||_{L2(Omega)} for u
+ * coefficient vectors a, b (device, FP64, n_u). */
+hpg_status hpg_l2_diff(hpg_problem* prob, const double* d_a, const double* d_b, double* diff,
+                       double* norm_b, void* stream);
+
 /* ---- kernel timing (for measurement harnesses) ----------------------------
- * When enabled, the library brackets every launch of the named kernel group
- * ("apply_G", "apply_prec", "minres_vec", "setup", "residual") with HIP events
- * on the stream it is launched on.  hpg_kernel_time returns the number of
- * bracketed launches and their summed duration in milliseconds. */
-hpg_status hpg_set_kernel_timing(hpg_problem* prob, int32_t enable);
+ * group NULL disables timing; "all" times every group; otherwise only the
+ * named group ("apply_G_u", "apply_G_psi", "fdm", "prec_psi", "minres_vec",
+ * "setup", "residual") is timed.  While enabled, every launch of a timed
+ * group is bracketed by HIP events on the stream it is launched on;
+ * hpg_kernel_time returns the number of bracketed launches and their summed
+ * duration in milliseconds.  Enabling resets the counters. */
+hpg_status hpg_set_kernel_timing(hpg_problem* prob, const char* group);
 hpg_status hpg_kernel_time(hpg_problem* prob, const char* group, int64_t* launches,
                            double* total_ms);
 

@@ -224,6 +224,7 @@ void hpg_default_opts(hpg_solve_opts* o) {
     o->beta = 0.0;
     o->precision = HPG_FP64;
     o->krylov_chunk = 16;
+    o->inexact_newton = 0;
 }
 
 static hpg_solve_opts checked_opts(const hpg_solve_opts* in) {
@@ -354,12 +355,24 @@ hpg_status hpg_op_residual(hpg_problem* prob, const double* d_u, const double* d
     });
 }
 
-hpg_status hpg_set_kernel_timing(hpg_problem* prob, int32_t enable) {
+hpg_status hpg_l2_diff(hpg_problem* prob, const double* d_a, const double* d_b, double* diff,
+                       double* norm_b, void* stream) {
+    return guarded([&]() -> hpg_status {
+        check_problem(prob);
+        if (!d_a || !d_b || !diff || !norm_b) fail(HPG_ERR_INVALID_ARG, "NULL argument");
+        Problem& P = prob->P;
+        *diff = P.l2_diff(d_b, d_a, norm_b, P.stream(stream));
+        return HPG_OK;
+    });
+}
+
+hpg_status hpg_set_kernel_timing(hpg_problem* prob, const char* group) {
     return guarded([&]() -> hpg_status {
         check_problem(prob);
         Problem& P = prob->P;
         HPG_HIP(hipDeviceSynchronize());
-        P.timing = enable != 0;
+        P.timing = group != nullptr;
+        P.timing_group = group ? group : "";
         for (auto& kv : P.groups) kv.second.used = 0;
         return HPG_OK;
     });

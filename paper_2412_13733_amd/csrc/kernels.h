@@ -48,54 +48,63 @@ struct PsiTabs {
 
 // MINRES scalar state (device)
 struct KState {
-    double gamma1, gamma, gamma_new, delta;
+    double gamma1, gamma, delta;
     double c, c_prev, s, s_prev, eta;
-    double a1, a2, a3, step;
     double rtol;
     int iters, max_iters, done, breakdown;
 };
 
+// prm (device, may be null): prm[0] = alpha, prm[1] = beta, prm[2] = 1/alpha;
+// when given it overrides the by-value alpha / beta
 template <typename T>
 void launch_u_side(const Geo& g, const URows<T>* r, T alpha, const T* xu, const T* xb,
                    const T* xb_prev, const double* F, T* yu, double* partial, const int* done,
-                   int mode, hipStream_t s);
+                   int mode, hipStream_t s, const double* prm = nullptr);
 template <typename T>
 void launch_psi_side(const Geo& g, const PsiTabs<T>& tb, int cpb, T beta, const T* xu,
                      const T* xpsi, const T* omega, const double* Phi, T* ypsi, double* partial,
-                     const int* done, int mode, hipStream_t s);
+                     const int* done, int mode, hipStream_t s, const double* prm = nullptr);
 size_t setup_smem_per_cell(const Geo& g);
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
                   float* om32, double* s64, float* s32, hipStream_t s);
 template <typename T>
-void launch_prec_psi(int64_t n_cells, int n, const T* sinv, const T* r, T* z, double* partial,
-                     const int* done, hipStream_t s);
+void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
+                     double* partial, const int* done, hipStream_t s);
+// C_b = A_b B_b (row-major, M x K times K x N), batch strides sA, sB, sC,
+// with the optional epilogues of GemmEpi
 template <typename T>
-void launch_gemm_right(int64_t R, int N, const T* X, const T* Mat, T* Y, const int* done,
-                       hipStream_t s);
+struct GemmEpi {
+    int scale_mode;
+    int n0;
+    const T* l0;
+    const T* l1;
+    const T* l2;
+    const double* prm;
+    const T* dotv;
+    double* partial;
+};
 template <typename T>
-void launch_gemm_left(int64_t O, int N, int64_t C, const T* X, const T* Mat, T* Y,
-                      const int* done, hipStream_t s);
+void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,
+                 int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, int batch,
+                 const int* done, const GemmEpi<T>& ep, hipStream_t s);
 template <typename T>
 void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
                       const int* done, hipStream_t s);
 template <typename T>
 void launch_dot(int64_t n, const T* a, const T* b, double* partial, int nblocks, const int* done,
                 hipStream_t s);
-void launch_kr_delta(KState* st, const double* partial, int np, hipStream_t s);
 template <typename T>
-void launch_kr_vhat(int64_t n, const KState* st, const T* Gq, const T* vcur, T* vprev,
-                    const int* done, hipStream_t s);
-void launch_kr_rotate(KState* st, const double* partial, int np, int* done, hipStream_t s);
+void launch_kr_start(int64_t n, KState* st0, const double* partial, int np, double rtol,
+                     int maxit, const T* b, const T* z, T* vcur, T* vprev, T* q, T* wprev,
+                     T* wcur, T* x, hipStream_t s);
 template <typename T>
-void launch_kr_update(int64_t n, const KState* st, T* q, T* wprev, const T* wcur, T* x, T* vprev,
-                      const T* z, const int* done, hipStream_t s);
-void launch_kr_finish(KState* st, int* done, hipStream_t s);
-void launch_kr_init(KState* st, const double* partial, int np, double rtol, int maxit, int* done,
-                    hipStream_t s);
+void launch_kr_vhat(int64_t n, KState* st, const double* partial, int np, const T* Gq,
+                    const T* vcur, T* vprev, hipStream_t s);
 template <typename T>
-void launch_kr_start(int64_t n, const KState* st, const T* b, const T* z, T* vcur, T* vprev,
-                     T* q, T* wprev, T* wcur, T* x, hipStream_t s);
+void launch_kr_update(int64_t n, const KState* st_in, KState* st_out, const double* partial,
+                      int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* z,
+                      hipStream_t s);
 template <typename TI, typename TO>
 void launch_convert(int64_t n, const TI* a, TO* b, double scale, hipStream_t s);
 template <typename T>

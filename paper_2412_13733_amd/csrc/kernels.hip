@@ -16,6 +16,7 @@
 // (paper Sec. 4.3: D_psi = V^T diag(omega) V per cell).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -40,20 +41,59 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// u-side: y_u = alpha A x_u + B x_b  (+ residual epilogue)
+// u-side: y_u = alpha A x_u + B x_b  (+ residual epilogue).  Each thread owns
+// global u unknowns (grid-stride); the sparse 1-D rows of its multi-index are
+// held in registers and the tensor-product sums are unrolled over the fixed
+// row width with predication.
+template <typename T, int W>
+struct Row {
+    int n;
+    int c[W];
+    T a[W], m[W];
+    __device__ inline void load(const URows<T>& r, int g) {
+        n = r.lenM[g];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const bool ok = e < n;
+            c[e] = ok ? r.colM[g * W + e] : 0;
+            a[e] = ok ? r.aM[g * W + e] : (T)0;
+            m[e] = ok ? r.mM[g * W + e] : (T)0;
+        }
+    }
+};
+template <typename T, int W>
+struct BRow {
+    int n;
+    int cell[W], mode[W];
+    T v[W];
+    __device__ inline void load(const URows<T>& r, int g) {
+        n = r.lenB[g];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const bool ok = e < n;
+            cell[e] = ok ? r.cellB[g * W + e] : 0;
+            mode[e] = ok ? r.modeB[g * W + e] : 0;
+            v[e] = ok ? r.vB[g * W + e] : (T)0;
+        }
+    }
+};
+
 template <typename T, int D, int MODE>
-__global__ __launch_bounds__(256) void k_u_side(Geo g, URows<T> r0, URows<T> r1, URows<T> r2,
+__global__ __launch_bounds__(128) void k_u_side(Geo g, URows<T> r0, URows<T> r1, URows<T> r2,
                                                 T alpha, const T* __restrict__ xu,
                                                 const T* __restrict__ xb,
                                                 const T* __restrict__ xb_prev,
                                                 const double* __restrict__ F,
                                                 T* __restrict__ yu, double* __restrict__ partial,
-                                                const int* __restrict__ done) {
-    __shared__ double red[4];
+                                                const int* __restrict__ done,
+                                                const double* __restrict__ prm) {
+    __shared__ double red[2];
     if (done && *done) return;
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (prm) alpha = (T)prm[0];   // linearisation parameters held on the device
+    constexpr int W = URows<T>::WM, WB = URows<T>::WB;
     double part = 0.0;
-    if (I < g.n_u) {
+    for (int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; I < g.n_u;
+         I += (int64_t)gridDim.x * blockDim.x) {
         int gi[3] = {0, 0, 0};
         int64_t t = I;
         gi[0] = (int)(t % g.n1[0]);
@@ -63,96 +103,105 @@ __global__ __launch_bounds__(256) void k_u_side(Geo g, URows<T> r0, URows<T> r1,
             t /= g.n1[1];
         }
         if (D >= 3) gi[2] = (int)t;
-        const int W = URows<T>::WM, WB = URows<T>::WB;
+        Row<T, W> R0;
+        R0.load(r0, gi[0]);
         T acc = 0;
-        // ---- stiffness: alpha sum_k (A1 in k) (x) (M1 elsewhere)
-        const int l0 = r0.lenM[gi[0]];
-        const int* c0 = r0.colM + gi[0] * W;
-        const T* a0 = r0.aM + gi[0] * W;
-        const T* m0 = r0.mM + gi[0] * W;
         if (D == 1) {
-            for (int e = 0; e < l0; ++e) acc += a0[e] * xu[c0[e]];
+#pragma unroll
+            for (int e0 = 0; e0 < W; ++e0)
+                if (e0 < R0.n) acc += R0.a[e0] * xu[R0.c[e0]];
         } else if (D == 2) {
-            const int l1 = r1.lenM[gi[1]];
-            const int* c1 = r1.colM + gi[1] * W;
-            const T* a1 = r1.aM + gi[1] * W;
-            const T* m1 = r1.mM + gi[1] * W;
-            for (int e1 = 0; e1 < l1; ++e1) {
-                const T* row = xu + (int64_t)c1[e1] * g.n1[0];
-                for (int e0 = 0; e0 < l0; ++e0)
-                    acc += (a0[e0] * m1[e1] + m0[e0] * a1[e1]) * row[c0[e0]];
+            Row<T, W> R1;
+            R1.load(r1, gi[1]);
+#pragma unroll
+            for (int e1 = 0; e1 < W; ++e1) {
+                if (e1 < R1.n) {
+                    const T* row = xu + (int64_t)R1.c[e1] * g.n1[0];
+                    const T m1 = R1.m[e1], a1 = R1.a[e1];
+#pragma unroll
+                    for (int e0 = 0; e0 < W; ++e0)
+                        if (e0 < R0.n) acc += (R0.a[e0] * m1 + R0.m[e0] * a1) * row[R0.c[e0]];
+                }
             }
         } else {
-            const int l1 = r1.lenM[gi[1]];
-            const int* c1 = r1.colM + gi[1] * W;
-            const T* a1 = r1.aM + gi[1] * W;
-            const T* m1 = r1.mM + gi[1] * W;
-            const int l2 = r2.lenM[gi[2]];
-            const int* c2 = r2.colM + gi[2] * W;
-            const T* a2 = r2.aM + gi[2] * W;
-            const T* m2 = r2.mM + gi[2] * W;
-            for (int e2 = 0; e2 < l2; ++e2)
-                for (int e1 = 0; e1 < l1; ++e1) {
-                    const T* row = xu + ((int64_t)c2[e2] * g.n1[1] + c1[e1]) * g.n1[0];
-                    const T am = a1[e1] * m2[e2], ma = m1[e1] * a2[e2], mm = m1[e1] * m2[e2];
-                    for (int e0 = 0; e0 < l0; ++e0)
-                        acc += (a0[e0] * mm + m0[e0] * (am + ma)) * row[c0[e0]];
+            Row<T, W> R1, R2;
+            R1.load(r1, gi[1]);
+            R2.load(r2, gi[2]);
+#pragma unroll
+            for (int e2 = 0; e2 < W; ++e2) {
+                if (e2 >= R2.n) continue;
+#pragma unroll
+                for (int e1 = 0; e1 < W; ++e1) {
+                    if (e1 >= R1.n) continue;
+                    const T* row = xu + ((int64_t)R2.c[e2] * g.n1[1] + R1.c[e1]) * g.n1[0];
+                    const T am = R1.a[e1] * R2.m[e2] + R1.m[e1] * R2.a[e2];
+                    const T mm = R1.m[e1] * R2.m[e2];
+#pragma unroll
+                    for (int e0 = 0; e0 < W; ++e0)
+                        if (e0 < R0.n) acc += (R0.a[e0] * mm + R0.m[e0] * am) * row[R0.c[e0]];
                 }
+            }
         }
         acc *= alpha;
-        // ---- Gram: (x)_k B1 applied to x_b = x_psi (or psi - psi_prev)
-        const int b0 = r0.lenB[gi[0]];
-        const int* cc0 = r0.cellB + gi[0] * WB;
-        const int* md0 = r0.modeB + gi[0] * WB;
-        const T* v0 = r0.vB + gi[0] * WB;
+        // Gram: (x)_k B1 applied to x_b = x_psi (or psi - psi_prev)
+        BRow<T, WB> B0;
+        B0.load(r0, gi[0]);
         const int P = g.P;
         if (D == 1) {
-            for (int e0 = 0; e0 < b0; ++e0) {
-                const int64_t j = (int64_t)cc0[e0] * g.Pd + md0[e0];
-                T xv = xb[j];
-                if (MODE == MODE_RES) xv -= xb_prev[j];
-                acc += v0[e0] * xv;
-            }
-        } else if (D == 2) {
-            const int b1 = r1.lenB[gi[1]];
-            const int* cc1 = r1.cellB + gi[1] * WB;
-            const int* md1 = r1.modeB + gi[1] * WB;
-            const T* v1 = r1.vB + gi[1] * WB;
-            for (int e1 = 0; e1 < b1; ++e1)
-                for (int e0 = 0; e0 < b0; ++e0) {
-                    const int64_t cell = (int64_t)cc1[e1] * g.m[0] + cc0[e0];
-                    const int64_t j = cell * g.Pd + md1[e1] * P + md0[e0];
+#pragma unroll
+            for (int e0 = 0; e0 < WB; ++e0)
+                if (e0 < B0.n) {
+                    const int64_t j = (int64_t)B0.cell[e0] * g.Pd + B0.mode[e0];
                     T xv = xb[j];
                     if (MODE == MODE_RES) xv -= xb_prev[j];
-                    acc += v0[e0] * v1[e1] * xv;
+                    acc += B0.v[e0] * xv;
                 }
-        } else {
-            const int b1 = r1.lenB[gi[1]];
-            const int* cc1 = r1.cellB + gi[1] * WB;
-            const int* md1 = r1.modeB + gi[1] * WB;
-            const T* v1 = r1.vB + gi[1] * WB;
-            const int b2 = r2.lenB[gi[2]];
-            const int* cc2 = r2.cellB + gi[2] * WB;
-            const int* md2 = r2.modeB + gi[2] * WB;
-            const T* v2 = r2.vB + gi[2] * WB;
-            for (int e2 = 0; e2 < b2; ++e2)
-                for (int e1 = 0; e1 < b1; ++e1)
-                    for (int e0 = 0; e0 < b0; ++e0) {
-                        const int64_t cell =
-                            ((int64_t)cc2[e2] * g.m[1] + cc1[e1]) * g.m[0] + cc0[e0];
-                        const int64_t j = cell * g.Pd + (md2[e2] * P + md1[e1]) * P + md0[e0];
+        } else if (D == 2) {
+            BRow<T, WB> B1;
+            B1.load(r1, gi[1]);
+#pragma unroll
+            for (int e1 = 0; e1 < WB; ++e1) {
+                if (e1 >= B1.n) continue;
+                const int64_t cbase = (int64_t)B1.cell[e1] * g.m[0];
+                const int mbase = B1.mode[e1] * P;
+#pragma unroll
+                for (int e0 = 0; e0 < WB; ++e0)
+                    if (e0 < B0.n) {
+                        const int64_t j = (cbase + B0.cell[e0]) * g.Pd + mbase + B0.mode[e0];
                         T xv = xb[j];
                         if (MODE == MODE_RES) xv -= xb_prev[j];
-                        acc += v0[e0] * v1[e1] * v2[e2] * xv;
+                        acc += B0.v[e0] * B1.v[e1] * xv;
                     }
+            }
+        } else {
+            BRow<T, WB> B1, B2;
+            B1.load(r1, gi[1]);
+            B2.load(r2, gi[2]);
+#pragma unroll
+            for (int e2 = 0; e2 < WB; ++e2)
+#pragma unroll
+                for (int e1 = 0; e1 < WB; ++e1) {
+                    if (e2 >= B2.n || e1 >= B1.n) continue;
+                    const int64_t cbase = ((int64_t)B2.cell[e2] * g.m[1] + B1.cell[e1]) * g.m[0];
+                    const int mbase = (B2.mode[e2] * P + B1.mode[e1]) * P;
+                    const T v12 = B1.v[e1] * B2.v[e2];
+#pragma unroll
+                    for (int e0 = 0; e0 < WB; ++e0)
+                        if (e0 < B0.n) {
+                            const int64_t j = (cbase + B0.cell[e0]) * g.Pd + mbase + B0.mode[e0];
+                            T xv = xb[j];
+                            if (MODE == MODE_RES) xv -= xb_prev[j];
+                            acc += B0.v[e0] * v12 * xv;
+                        }
+                }
         }
         if (MODE == MODE_RES) {
             const double r = (double)acc - (double)alpha * F[I];
             yu[I] = (T)r;
-            part = r * r;
+            part += r * r;
         } else {
             yu[I] = acc;
-            part = (double)acc * (double)xu[I];
+            part += (double)acc * (double)xu[I];
         }
     }
     if (partial) {
@@ -267,10 +316,12 @@ __global__ __launch_bounds__(256) void k_psi_side(Geo g, PsiTabs<T> tb, int cpb,
                                                   const double* __restrict__ Phi,
                                                   T* __restrict__ ypsi,
                                                   double* __restrict__ partial,
-                                                  const int* __restrict__ done) {
+                                                  const int* __restrict__ done,
+                                                  const double* __restrict__ prm) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
     if (done && *done) return;
+    if (prm) beta = (T)prm[1];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const int S = g.S;   // per-cell buffer stride (max(p+1, q)^D)
     T* bU = sm;
@@ -278,9 +329,12 @@ __global__ __launch_bounds__(256) void k_psi_side(Geo g, PsiTabs<T> tb, int cpb,
     T* bT = sm + 2 * cpb * S;
     T* bA = sm + 3 * cpb * S;
     T* bB = sm + 4 * cpb * S;
-    const int64_t cell0 = (int64_t)blockIdx.x * cpb;
-    const int ncell = (int)min((int64_t)cpb, g.n_cells - cell0);
     const int L = g.p + 1, P = g.P, q = g.q;
+    double part = 0.0;
+    const int64_t ngroups = (g.n_cells + cpb - 1) / cpb;
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t cell0 = grp * cpb;
+    const int ncell = (int)min((int64_t)cpb, g.n_cells - cell0);
     gather_u<T, D>(g, xu, bU, S, cell0, ncell);
     for (int e = threadIdx.x; e < ncell * g.Pd; e += blockDim.x) {
         const int ci = e / g.Pd, a = e - ci * g.Pd;
@@ -321,7 +375,6 @@ __global__ __launch_bounds__(256) void k_psi_side(Geo g, PsiTabs<T> tb, int cpb,
     }
     __syncthreads();
     T* dx = contract_all<T, D>(vq, other, S, ncell, q, P, tb.Vpsi, P, true);
-    double part = 0.0;
     for (int e = threadIdx.x; e < ncell * g.Pd; e += blockDim.x) {
         const int ci = e / g.Pd, a = e - ci * g.Pd;
         const int64_t cell = cell0 + ci;
@@ -341,6 +394,8 @@ __global__ __launch_bounds__(256) void k_psi_side(Geo g, PsiTabs<T> tb, int cpb,
             part += (double)y * (double)bX[ci * S + a];
         }
         ypsi[cell * g.Pd + a] = y;
+    }
+    __syncthreads();   // the LDS buffers are reused by the next cell group
     }
     if (partial) {
         double s = block_sum(part, red);
@@ -519,124 +574,161 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
 }
 
 // ---------------------------------------------------------------------------
-// psi-block of the preconditioner: z_psi = (-S_hat_K)^{-1} r_psi per cell;
-// one thread per (cell, row); the block is symmetric, so thread i reads
-// column i (coalesced across threads).  Partial dot <z, r> fused.
+// psi-block of the preconditioner: z_psi = (-S_hat_K)^{-1} r_psi per cell.
+// A block copies the contiguous inverse blocks of cpb cells into LDS with
+// coalesced loads, then one thread per (cell, row) forms the row product
+// (the blocks are symmetric, so row i is read as column i: conflict-free).
+// Partial dot <z, r> fused.
 template <typename T>
-__global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n,
+__global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cpb,
                                                   const T* __restrict__ sinv,
                                                   const T* __restrict__ r, T* __restrict__ z,
                                                   double* __restrict__ partial,
                                                   const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
     if (done && *done) return;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    T* Sb = reinterpret_cast<T*>(smem_raw);
+    const int nn = n * n;
+    T* Rb = Sb + cpb * nn;
     double part = 0.0;
-    if (e < n_cells * n) {
-        const int64_t cell = e / n;
-        const int i = (int)(e - cell * n);
-        const T* Sb = sinv + cell * (int64_t)n * n;
-        const T* rb = r + cell * n;
-        T acc = 0;
-        for (int j = 0; j < n; ++j) acc += Sb[(int64_t)j * n + i] * rb[j];
-        z[e] = acc;
-        part = (double)acc * (double)r[e];
+    const int64_t ngroups = (n_cells + cpb - 1) / cpb;
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int64_t cell0 = grp * cpb;
+        const int nc = (int)min((int64_t)cpb, n_cells - cell0);
+        const T* src = sinv + cell0 * (int64_t)nn;
+        const int tot = nc * nn;
+        int e = threadIdx.x;
+        for (; e + 3 * 256 < tot; e += 4 * 256) {
+            const T v0 = src[e], v1 = src[e + 256], v2 = src[e + 512], v3 = src[e + 768];
+            Sb[e] = v0;
+            Sb[e + 256] = v1;
+            Sb[e + 512] = v2;
+            Sb[e + 768] = v3;
+        }
+        for (; e < tot; e += 256) Sb[e] = src[e];
+        for (int i = threadIdx.x; i < nc * n; i += 256) Rb[i] = r[cell0 * n + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc * n; i += 256) {
+            const int ci = i / n, row = i - ci * n;
+            const T* S = Sb + ci * nn;
+            const T* rr = Rb + ci * n;
+            T acc = 0;
+            for (int j = 0; j < n; ++j) acc += S[j * n + row] * rr[j];
+            z[cell0 * n + i] = acc;
+            part += (double)acc * (double)rr[row];
+        }
+        __syncthreads();
     }
     if (partial) {
-        double s = block_sum(part, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        double s2 = block_sum(part, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s2;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Tensor-axis GEMMs of the fast-diagonalisation A-block inverse.
-// right:  Y[r][i] = sum_j X[r][j] Mat[i][j]         (axis 0; rows = other axes)
-// left :  Y[o][i][c] = sum_j Mat[i][j] X[o][j][c]   (axis k > 0; o outer, c inner)
-// 64x64 output tiles, 16-deep K slabs staged in LDS, 4x4 outputs per thread.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_right(int64_t R, int N, const T* __restrict__ X,
-                                                    const T* __restrict__ Mat,
-                                                    T* __restrict__ Y,
-                                                    const int* __restrict__ done) {
-    __shared__ T sx[16][64 + 1];
-    __shared__ T sm[16][64 + 1];
-    if (done && *done) return;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int64_t r0 = (int64_t)blockIdx.y * 64;
-    const int i0 = blockIdx.x * 64;
-    T acc[4][4] = {};
-    for (int k0 = 0; k0 < N; k0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = e % 16, rr = e / 16;
-            const int64_t row = r0 + rr;
-            const int col = k0 + kk;
-            sx[kk][rr] = (row < R && col < N) ? X[row * N + col] : (T)0;
-            const int irow = i0 + rr;
-            sm[kk][rr] = (irow < N && col < N) ? Mat[(int64_t)irow * N + col] : (T)0;
-        }
-        __syncthreads();
-        for (int kk = 0; kk < 16; ++kk) {
-            T a[4], b[4];
-            for (int u = 0; u < 4; ++u) a[u] = sx[kk][ty * 4 + u];
-            for (int v = 0; v < 4; ++v) b[v] = sm[kk][tx * 4 + v];
-            for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-        }
-        __syncthreads();
-    }
-    for (int u = 0; u < 4; ++u) {
-        const int64_t row = r0 + ty * 4 + u;
-        if (row >= R) continue;
-        for (int v = 0; v < 4; ++v) {
-            const int col = i0 + tx * 4 + v;
-            if (col < N) Y[row * N + col] = acc[u][v];
-        }
-    }
-}
+// Tensor-axis GEMMs of the fast-diagonalisation A-block inverse on the matrix
+// cores: C_b = A_b (M x K) B_b (K x N), row-major, batch b = blockIdx.z.
+// One block of 4 waves owns a 16x16 tile of C; the waves split K in slabs of
+// 4 (v_mfma_*_16x16x4 operands: lane l supplies A[l%16][k+l/16] and
+// B[k+l/16][l%16]; the 16x16 result sits 4 values per lane at positions the
+// kernel reads off two index-valued MFMAs) and the four partial tiles are
+// summed in LDS in a fixed order.
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_left(int64_t O, int N, int64_t C,
-                                                   const T* __restrict__ X,
-                                                   const T* __restrict__ Mat,
-                                                   T* __restrict__ Y,
-                                                   const int* __restrict__ done) {
-    __shared__ T sm[16][64 + 1];
-    __shared__ T sx[16][64 + 1];
-    if (done && *done) return;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int64_t o = blockIdx.z;
-    const int i0 = blockIdx.y * 64;
-    const int64_t c0 = (int64_t)blockIdx.x * 64;
-    const T* Xo = X + o * (int64_t)N * C;
-    T* Yo = Y + o * (int64_t)N * C;
-    T acc[4][4] = {};
-    for (int k0 = 0; k0 < N; k0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kk = e % 16, ii = e / 16;
-            const int irow = i0 + ii, col = k0 + kk;
-            sm[kk][ii] = (irow < N && col < N) ? Mat[(int64_t)irow * N + col] : (T)0;
-            const int cc = e % 64, kk2 = e / 64;
-            const int krow = k0 + kk2;
-            const int64_t ccol = c0 + cc;
-            sx[kk2][cc] = (krow < N && ccol < C) ? Xo[(int64_t)krow * C + ccol] : (T)0;
-        }
-        __syncthreads();
-        for (int kk = 0; kk < 16; ++kk) {
-            T a[4], b[4];
-            for (int u = 0; u < 4; ++u) a[u] = sm[kk][ty * 4 + u];
-            for (int v = 0; v < 4; ++v) b[v] = sx[kk][tx * 4 + v];
-            for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-        }
-        __syncthreads();
+struct Mfma;
+template <>
+struct Mfma<double> {
+    using V = v4d;
+    static __device__ inline V op(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    for (int u = 0; u < 4; ++u) {
-        const int irow = i0 + ty * 4 + u;
-        if (irow >= N) continue;
-        for (int v = 0; v < 4; ++v) {
-            const int64_t ccol = c0 + tx * 4 + v;
-            if (ccol < C) Yo[(int64_t)irow * C + ccol] = acc[u][v];
+};
+template <>
+struct Mfma<float> {
+    using V = v4f;
+    static __device__ inline V op(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// optional epilogues of a pass: divide by alpha (lam_k[row] + inner
+// eigenvalues) (the eigen-space division of the fast diagonalisation) and/or
+// accumulate <C, dotv> per block into partial[block]
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T* __restrict__ A,
+                                                   int64_t lda, int64_t sA,
+                                                   const T* __restrict__ B, int64_t ldb,
+                                                   int64_t sB, T* __restrict__ C, int64_t ldc,
+                                                   int64_t sC, const int* __restrict__ done,
+                                                   GemmEpi<T> ep) {
+    __shared__ T red[4][256];
+    __shared__ double rsum[4];
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t b = blockIdx.z;
+    A += b * sA;
+    B += b * sB;
+    C += b * sC;
+    const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+    const int ar = i0 + (lane & 15), kk = lane >> 4, bc = j0 + (lane & 15);
+    const bool rok = ar < M, cok = bc < N;
+    typename Mfma<T>::V acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    // wave w takes the K slabs k0 = 4 w + 16 i; the operands of twelve slabs
+    // are loaded before their MFMAs, so K <= 192 costs one round trip
+    for (int k0 = 4 * w; k0 < K; k0 += 16 * 12) {
+        T a[12], bb[12];
+#pragma unroll
+        for (int u = 0; u < 12; ++u) {
+            const int ka = k0 + 16 * u + kk;
+            a[u] = (rok && ka < K) ? A[(int64_t)ar * lda + ka] : (T)0;
+            bb[u] = (cok && ka < K) ? B[(int64_t)ka * ldb + bc] : (T)0;
         }
+#pragma unroll
+        for (int u = 0; u < 12; u += 2) {
+            acc0 = Mfma<T>::op(a[u], bb[u], acc0);
+            acc1 = Mfma<T>::op(a[u + 1], bb[u + 1], acc1);
+        }
+    }
+    // where each of the 4 result values of this lane sits in the 16x16 tile:
+    // one MFMA with A[i][0] = i, B[0][j] = 1 gives D[i][j] = i, one with
+    // A[i][0] = 1, B[0][j] = j gives D[i][j] = j (exact small integers)
+    typename Mfma<T>::V zero = {0, 0, 0, 0};
+    const typename Mfma<T>::V rid =
+        Mfma<T>::op(kk == 0 ? (T)(lane & 15) : (T)0, kk == 0 ? (T)1 : (T)0, zero);
+    const typename Mfma<T>::V cid =
+        Mfma<T>::op(kk == 0 ? (T)1 : (T)0, kk == 0 ? (T)(lane & 15) : (T)0, zero);
+    for (int v = 0; v < 4; ++v) {
+        const int ri = (int)rid[v] & 15, ci = (int)cid[v] & 15;
+        red[w][ri * 16 + ci] = acc0[v] + acc1[v];
+    }
+    __syncthreads();
+    const int t = threadIdx.x, r = t >> 4, c = t & 15;
+    T s = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    const int row = i0 + r, col = j0 + c;
+    const bool in = row < M && col < N;
+    double part = 0.0;
+    if (in) {
+        if (ep.scale_mode) {
+            T lam;
+            if (ep.scale_mode == 1)
+                lam = ep.l0[col];
+            else if (ep.scale_mode == 2)
+                lam = ep.l1[row] + ep.l0[col];
+            else
+                lam = ep.l2[row] + ep.l0[col % ep.n0] + ep.l1[col / ep.n0];
+            s = s * (T)ep.prm[2] / lam;
+        }
+        C[(int64_t)row * ldc + col] = s;
+        if (ep.dotv) part = (double)s * (double)ep.dotv[b * sC + (int64_t)row * ldc + col];
+    }
+    if (ep.partial) {
+        const double tot = block_sum(part, rsum);
+        if (threadIdx.x == 0)
+            ep.partial[blockIdx.x + gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = tot;
     }
 }
 
@@ -663,131 +755,138 @@ __global__ __launch_bounds__(256) void k_fdm_scale(Geo g, const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// MINRES scalar recurrences and vector updates (preconditioned MINRES for a
-// symmetric indefinite G with an SPD preconditioner M).
-__device__ inline double sum_partials(const double* p, int n) {
+// Preconditioned MINRES for the symmetric indefinite G with an SPD
+// preconditioner M (Lanczos on M^{-1} G in the M-inner product, QR of the
+// tridiagonal by Givens rotations).  The scalar recurrences are folded into
+// the vector kernels: every block reduces the partial sums of the preceding
+// dot product itself, in one fixed order, so all blocks hold bit-identical
+// scalars; block 0 stores them.  The state is double-buffered by iteration
+// parity (iteration j reads st[j&1] and writes st[(j+1)&1]), so no block
+// reads a field that another block of the same kernel writes.  Once a state
+// is marked done every later kernel of the loop returns at once.
+
+// fixed-order sum of np partials, identical in every block (valid in all threads)
+__device__ inline double reduce_partials(const double* __restrict__ p, int np, double* red,
+                                         double* bcast) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += p[i];
-    return s;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += p[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *bcast = s;
+    __syncthreads();
+    return *bcast;
 }
 
-// after <G q, q>: delta
-__global__ void k_kr_delta(KState* st, const double* partial, int np) {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || st->done) return;
-    st->delta = sum_partials(partial, np);
-}
-
-// vhat = Gq - delta v_cur - gamma v_prev   (written over v_prev)
+// start: gamma1 = sqrt(<z1, b>), v_cur = b/gamma1, q = z1/gamma1, w = v_prev = x = 0
 template <typename T>
-__global__ __launch_bounds__(256) void k_kr_vhat(int64_t n, const KState* st, const T* Gq,
-                                                 const T* vcur, T* vprev,
-                                                 const int* __restrict__ done) {
-    if (*done) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const T dl = (T)st->delta, gm = (T)st->gamma;
-    vprev[i] = Gq[i] - dl * vcur[i] - gm * vprev[i];
-}
-
-// after <z, vhat>: new gamma, Givens rotation, convergence test
-__global__ void k_kr_rotate(KState* st, const double* partial, int np, int* done) {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || st->done) return;
-    double g2 = sum_partials(partial, np);
-    const double gnew = sqrt(g2 > 0.0 ? g2 : 0.0);
-    const double delta = st->delta, gcur = st->gamma;
-    const double a0 = st->c * delta - st->c_prev * st->s * gcur;
-    const double a1 = sqrt(a0 * a0 + gnew * gnew);
-    const double a2 = st->s * delta + st->c_prev * st->c * gcur;
-    const double a3 = st->s_prev * gcur;
-    st->c_prev = st->c;
-    st->s_prev = st->s;
-    if (a1 == 0.0 || !(a1 == a1)) {   // breakdown or NaN: stop
-        st->done = 1;
-        st->breakdown = 1;
-        *done = 1;
-        st->a1 = 1.0;
-        st->a2 = 0.0;
-        st->a3 = 0.0;
-        st->step = 0.0;
-        return;
-    }
-    st->c = a0 / a1;
-    st->s = gnew / a1;
-    st->a1 = a1;
-    st->a2 = a2;
-    st->a3 = a3;
-    st->step = st->c * st->eta;
-    st->eta = -st->s * st->eta;
-    st->gamma_new = gnew;
-    st->iters += 1;
-    if (fabs(st->eta) <= st->rtol * st->gamma1 || st->iters >= st->max_iters || gnew == 0.0) {
-        st->done = 1;
-    }
-}
-
-// w_new = (q - a3 w_prev - a2 w_cur) / a1 (over w_prev); x += step w_new;
-// v_prev <- vhat / gamma_new (vhat lives in v_prev, v_cur kept for the swap),
-// q <- z / gamma_new
-template <typename T>
-__global__ __launch_bounds__(256) void k_kr_update(int64_t n, const KState* st, T* q,
-                                                   T* wprev, const T* wcur, T* x, T* vprev,
-                                                   const T* z, const int* __restrict__ done) {
-    if (*done) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double ia1 = 1.0 / st->a1;
-    const T a2 = (T)st->a2, a3 = (T)st->a3;
-    const T wn = (T)((double)(q[i] - a3 * wprev[i] - a2 * wcur[i]) * ia1);
-    wprev[i] = wn;
-    x[i] += (T)st->step * wn;
-    const double gn = st->gamma_new;
-    const double ig = gn > 0.0 ? 1.0 / gn : 0.0;
-    vprev[i] = (T)((double)vprev[i] * ig);
-    q[i] = (T)((double)z[i] * ig);
-}
-
-// finish an iteration: gamma <- gamma_new; raise the host-visible flag
-__global__ void k_kr_finish(KState* st, int* done) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (*done) return;
-    st->gamma = st->gamma_new;
-    if (st->done) *done = 1;
-}
-
-// initialisation: gamma1 = sqrt(<z1, b>), v_cur = b / gamma1, q = z1 / gamma1
-__global__ void k_kr_init(KState* st, const double* partial, int np, double rtol, int maxit,
-                          int* done) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double g2 = sum_partials(partial, np);
-    const double g1 = sqrt(g2 > 0.0 ? g2 : 0.0);
-    st->gamma1 = g1;
-    st->gamma = g1;
-    st->gamma_new = g1;
-    st->eta = g1;
-    st->c = st->c_prev = 1.0;
-    st->s = st->s_prev = 0.0;
-    st->iters = 0;
-    st->max_iters = maxit;
-    st->rtol = rtol;
-    st->breakdown = 0;
-    st->done = (g1 == 0.0 || !(g1 == g1)) ? 1 : 0;
-    *done = st->done;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_kr_start(int64_t n, const KState* st, const T* b,
+__global__ __launch_bounds__(256) void k_kr_start(int64_t n, KState* st0, const double* partial,
+                                                  int np, double rtol, int maxit, const T* b,
                                                   const T* z, T* vcur, T* vprev, T* q, T* wprev,
                                                   T* wcur, T* x) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double g1 = st->gamma1;
+    __shared__ double red[4];
+    __shared__ double bc;
+    const double g2 = reduce_partials(partial, np, red, &bc);
+    const double g1 = sqrt(g2 > 0.0 ? g2 : 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        KState s;
+        s.gamma1 = g1;
+        s.gamma = g1;
+        s.delta = 0.0;
+        s.c = s.c_prev = 1.0;
+        s.s = s.s_prev = 0.0;
+        s.eta = g1;
+        s.rtol = rtol;
+        s.iters = 0;
+        s.max_iters = maxit;
+        s.breakdown = 0;
+        s.done = (g1 > 0.0 && g1 == g1) ? 0 : 1;
+        *st0 = s;
+    }
     const double ig = g1 > 0.0 ? 1.0 / g1 : 0.0;
-    vcur[i] = (T)((double)b[i] * ig);
-    q[i] = (T)((double)z[i] * ig);
-    vprev[i] = 0;
-    wprev[i] = 0;
-    wcur[i] = 0;
-    x[i] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        vcur[i] = (T)((double)b[i] * ig);
+        q[i] = (T)((double)z[i] * ig);
+        vprev[i] = 0;
+        wprev[i] = 0;
+        wcur[i] = 0;
+        x[i] = 0;
+    }
+}
+
+// delta = <G q, q>;  vhat = G q - delta v_cur - gamma v_prev   (over v_prev)
+template <typename T>
+__global__ __launch_bounds__(256) void k_kr_vhat(int64_t n, KState* st, const double* partial,
+                                                 int np, const T* Gq, const T* vcur, T* vprev) {
+    __shared__ double red[4];
+    __shared__ double bc;
+    if (st->done) return;
+    const double delta = reduce_partials(partial, np, red, &bc);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->delta = delta;
+    const T dl = (T)delta, gm = (T)st->gamma;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        vprev[i] = Gq[i] - dl * vcur[i] - gm * vprev[i];
+}
+
+// gamma_new = sqrt(<z, vhat>), Givens rotation, then
+// w_new = (q - a3 w_prev - a2 w_cur)/a1 (over w_prev), x += c_new eta w_new,
+// v_prev <- vhat / gamma_new, q <- z / gamma_new; the new state goes to st_out
+template <typename T>
+__global__ __launch_bounds__(256) void k_kr_update(int64_t n, const KState* st_in, KState* st_out,
+                                                   const double* partial, int np, T* q, T* wprev,
+                                                   const T* wcur, T* x, T* vprev, const T* z) {
+    __shared__ double red[4];
+    __shared__ double bc;
+    __shared__ double sc[6];   // a1, a2, a3, step, 1/gamma_new, skip
+    if (st_in->done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *st_out = *st_in;
+        return;
+    }
+    const double g2 = reduce_partials(partial, np, red, &bc);
+    if (threadIdx.x == 0) {
+        KState s = *st_in;
+        const double gnew = sqrt(g2 > 0.0 ? g2 : 0.0);
+        const double delta = s.delta, gcur = s.gamma;
+        const double a0 = s.c * delta - s.c_prev * s.s * gcur;
+        const double a1 = sqrt(a0 * a0 + gnew * gnew);
+        const double a2 = s.s * delta + s.c_prev * s.c * gcur;
+        const double a3 = s.s_prev * gcur;
+        if (a1 == 0.0 || !(a1 == a1)) {   // breakdown or NaN: stop without an update
+            s.done = 1;
+            s.breakdown = 1;
+            sc[5] = 1.0;
+        } else {
+            s.c_prev = s.c;
+            s.s_prev = s.s;
+            s.c = a0 / a1;
+            s.s = gnew / a1;
+            sc[0] = a1;
+            sc[1] = a2;
+            sc[2] = a3;
+            sc[3] = s.c * s.eta;
+            sc[4] = gnew > 0.0 ? 1.0 / gnew : 0.0;
+            sc[5] = 0.0;
+            s.eta = -s.s * s.eta;
+            s.gamma = gnew;
+            s.iters += 1;
+            if (fabs(s.eta) <= s.rtol * s.gamma1 || s.iters >= s.max_iters || gnew == 0.0)
+                s.done = 1;
+        }
+        if (blockIdx.x == 0) *st_out = s;
+    }
+    __syncthreads();
+    if (sc[5] != 0.0) return;
+    const double ia1 = 1.0 / sc[0];
+    const T a2 = (T)sc[1], a3 = (T)sc[2], step = (T)sc[3];
+    const double ig = sc[4];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T wn = (T)((double)(q[i] - a3 * wprev[i] - a2 * wcur[i]) * ia1);
+        wprev[i] = wn;
+        x[i] += step * wn;
+        vprev[i] = (T)((double)vprev[i] * ig);
+        q[i] = (T)((double)z[i] * ig);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -881,11 +980,11 @@ static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b -
 template <typename T>
 void launch_u_side(const Geo& g, const URows<T>* r, T alpha, const T* xu, const T* xb,
                    const T* xb_prev, const double* F, T* yu, double* partial, const int* done,
-                   int mode, hipStream_t s) {
-    dim3 grid(nblk(g.n_u)), blk(256);
+                   int mode, hipStream_t s, const double* prm) {
+    dim3 grid((unsigned)std::min<int64_t>((g.n_u + 127) / 128, 1024)), blk(128);
 #define HPG_U(DD, MM)                                                                       \
     hipLaunchKernelGGL((k_u_side<T, DD, MM>), grid, blk, 0, s, g, r[0], r[1], r[2], alpha, \
-                       xu, xb, xb_prev, F, yu, partial, done)
+                       xu, xb, xb_prev, F, yu, partial, done, prm)
     if (mode == MODE_APPLY) {
         if (g.d == 1) HPG_U(1, MODE_APPLY);
         else if (g.d == 2) HPG_U(2, MODE_APPLY);
@@ -901,12 +1000,12 @@ void launch_u_side(const Geo& g, const URows<T>* r, T alpha, const T* xu, const 
 template <typename T>
 void launch_psi_side(const Geo& g, const PsiTabs<T>& tb, int cpb, T beta, const T* xu,
                      const T* xpsi, const T* omega, const double* Phi, T* ypsi, double* partial,
-                     const int* done, int mode, hipStream_t s) {
-    dim3 grid(nblk(g.n_cells, cpb)), blk(256);
+                     const int* done, int mode, hipStream_t s, const double* prm) {
+    dim3 grid((unsigned)std::min<int64_t>((g.n_cells + cpb - 1) / cpb, 1024)), blk(256);
     size_t shm = (size_t)5 * cpb * g.S * sizeof(T);
 #define HPG_P(DD, MM)                                                                      \
     hipLaunchKernelGGL((k_psi_side<T, DD, MM>), grid, blk, shm, s, g, tb, cpb, beta, xu, \
-                       xpsi, omega, Phi, ypsi, partial, done)
+                       xpsi, omega, Phi, ypsi, partial, done, prm)
     if (mode == MODE_APPLY) {
         if (g.d == 1) HPG_P(1, MODE_APPLY);
         else if (g.d == 2) HPG_P(2, MODE_APPLY);
@@ -941,24 +1040,21 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, const double
 }
 
 template <typename T>
-void launch_prec_psi(int64_t n_cells, int n, const T* sinv, const T* r, T* z, double* partial,
-                     const int* done, hipStream_t s) {
-    hipLaunchKernelGGL((k_prec_psi<T>), dim3(nblk(n_cells * n)), dim3(256), 0, s, n_cells, n,
-                       sinv, r, z, partial, done);
+void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
+                     double* partial, const int* done, hipStream_t s) {
+    const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
+    const unsigned grid = (unsigned)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
+    hipLaunchKernelGGL((k_prec_psi<T>), dim3(grid), dim3(256), shm, s, n_cells, n,
+                       cpb, sinv, r, z, partial, done);
 }
 
 template <typename T>
-void launch_gemm_right(int64_t R, int N, const T* X, const T* Mat, T* Y, const int* done,
-                       hipStream_t s) {
-    dim3 grid((N + 63) / 64, (unsigned)((R + 63) / 64));
-    hipLaunchKernelGGL((k_gemm_right<T>), grid, dim3(256), 0, s, R, N, X, Mat, Y, done);
-}
-
-template <typename T>
-void launch_gemm_left(int64_t O, int N, int64_t C, const T* X, const T* Mat, T* Y,
-                      const int* done, hipStream_t s) {
-    dim3 grid((unsigned)((C + 63) / 64), (N + 63) / 64, (unsigned)O);
-    hipLaunchKernelGGL((k_gemm_left<T>), grid, dim3(256), 0, s, O, N, C, X, Mat, Y, done);
+void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,
+                 int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, int batch,
+                 const int* done, const GemmEpi<T>& ep, hipStream_t s) {
+    dim3 grid((N + 15) / 16, (M + 15) / 16, batch);
+    hipLaunchKernelGGL((k_gemm_mfma<T>), grid, dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB,
+                       C, ldc, sC, done, ep);
 }
 
 template <typename T>
@@ -982,36 +1078,28 @@ void launch_dot(int64_t n, const T* a, const T* b, double* partial, int nblocks,
     hipLaunchKernelGGL((k_dot<T>), dim3(nblocks), dim3(256), 0, s, n, a, b, partial, done);
 }
 
-void launch_kr_delta(KState* st, const double* partial, int np, hipStream_t s) {
-    hipLaunchKernelGGL(k_kr_delta, dim3(1), dim3(64), 0, s, st, partial, np);
+static inline unsigned vec_grid(int64_t n) {
+    return (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
 }
 template <typename T>
-void launch_kr_vhat(int64_t n, const KState* st, const T* Gq, const T* vcur, T* vprev,
-                    const int* done, hipStream_t s) {
-    hipLaunchKernelGGL((k_kr_vhat<T>), dim3(nblk(n)), dim3(256), 0, s, n, st, Gq, vcur, vprev,
-                       done);
-}
-void launch_kr_rotate(KState* st, const double* partial, int np, int* done, hipStream_t s) {
-    hipLaunchKernelGGL(k_kr_rotate, dim3(1), dim3(64), 0, s, st, partial, np, done);
+void launch_kr_start(int64_t n, KState* st0, const double* partial, int np, double rtol,
+                     int maxit, const T* b, const T* z, T* vcur, T* vprev, T* q, T* wprev,
+                     T* wcur, T* x, hipStream_t s) {
+    hipLaunchKernelGGL((k_kr_start<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st0, partial, np,
+                       rtol, maxit, b, z, vcur, vprev, q, wprev, wcur, x);
 }
 template <typename T>
-void launch_kr_update(int64_t n, const KState* st, T* q, T* wprev, const T* wcur, T* x, T* vprev,
-                      const T* z, const int* done, hipStream_t s) {
-    hipLaunchKernelGGL((k_kr_update<T>), dim3(nblk(n)), dim3(256), 0, s, n, st, q, wprev, wcur,
-                       x, vprev, z, done);
-}
-void launch_kr_finish(KState* st, int* done, hipStream_t s) {
-    hipLaunchKernelGGL(k_kr_finish, dim3(1), dim3(64), 0, s, st, done);
-}
-void launch_kr_init(KState* st, const double* partial, int np, double rtol, int maxit, int* done,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_kr_init, dim3(1), dim3(64), 0, s, st, partial, np, rtol, maxit, done);
+void launch_kr_vhat(int64_t n, KState* st, const double* partial, int np, const T* Gq,
+                    const T* vcur, T* vprev, hipStream_t s) {
+    hipLaunchKernelGGL((k_kr_vhat<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st, partial, np, Gq,
+                       vcur, vprev);
 }
 template <typename T>
-void launch_kr_start(int64_t n, const KState* st, const T* b, const T* z, T* vcur, T* vprev,
-                     T* q, T* wprev, T* wcur, T* x, hipStream_t s) {
-    hipLaunchKernelGGL((k_kr_start<T>), dim3(nblk(n)), dim3(256), 0, s, n, st, b, z, vcur, vprev,
-                       q, wprev, wcur, x);
+void launch_kr_update(int64_t n, const KState* st_in, KState* st_out, const double* partial,
+                      int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* z,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((k_kr_update<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st_in, st_out,
+                       partial, np, q, wprev, wcur, x, vprev, z);
 }
 template <typename TI, typename TO>
 void launch_convert(int64_t n, const TI* a, TO* b, double scale, hipStream_t s) {
@@ -1039,24 +1127,24 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
 
 #define HPG_INST(T)                                                                              \
     template void launch_u_side<T>(const Geo&, const URows<T>*, T, const T*, const T*, const T*, \
-                                   const double*, T*, double*, const int*, int, hipStream_t);   \
+                                   const double*, T*, double*, const int*, int, hipStream_t,    \
+                                   const double*);                                               \
     template void launch_psi_side<T>(const Geo&, const PsiTabs<T>&, int, T, const T*, const T*, \
                                      const T*, const double*, T*, double*, const int*, int,     \
-                                     hipStream_t);                                               \
-    template void launch_prec_psi<T>(int64_t, int, const T*, const T*, T*, double*, const int*, \
-                                     hipStream_t);                                               \
-    template void launch_gemm_right<T>(int64_t, int, const T*, const T*, T*, const int*,        \
-                                       hipStream_t);                                             \
-    template void launch_gemm_left<T>(int64_t, int, int64_t, const T*, const T*, T*, const int*, \
-                                      hipStream_t);                                              \
+                                     hipStream_t, const double*);                                \
+    template void launch_prec_psi<T>(int64_t, int, int, const T*, const T*, T*, double*,         \
+                                     const int*, hipStream_t);                                   \
+    template void launch_gemm<T>(int, int, int, const T*, int64_t, int64_t, const T*, int64_t,    \
+                                 int64_t, T*, int64_t, int64_t, int, const int*,                 \
+                                 const GemmEpi<T>&, hipStream_t);                                \
     template void launch_fdm_scale<T>(const Geo&, const T*, const T*, const T*, T, T*,          \
                                       const int*, hipStream_t);                                  \
-    template void launch_kr_vhat<T>(int64_t, const KState*, const T*, const T*, T*, const int*, \
+    template void launch_kr_start<T>(int64_t, KState*, const double*, int, double, int, const T*, \
+                                     const T*, T*, T*, T*, T*, T*, T*, hipStream_t);             \
+    template void launch_kr_vhat<T>(int64_t, KState*, const double*, int, const T*, const T*, T*, \
                                     hipStream_t);                                                \
-    template void launch_kr_update<T>(int64_t, const KState*, T*, T*, const T*, T*, T*,         \
-                                      const T*, const int*, hipStream_t);                        \
-    template void launch_kr_start<T>(int64_t, const KState*, const T*, const T*, T*, T*, T*, T*, \
-                                     T*, T*, hipStream_t);                                       \
+    template void launch_kr_update<T>(int64_t, const KState*, KState*, const double*, int, T*, T*, \
+                                      const T*, T*, T*, const T*, hipStream_t);                  \
     template void launch_axpy_to<T>(int64_t, const double*, double, const T*, double*,          \
                                     hipStream_t);                                                \
     template void launch_dot<T>(int64_t, const T*, const T*, double*, int, const int*, hipStream_t);

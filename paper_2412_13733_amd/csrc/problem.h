@@ -1,7 +1,9 @@
 // Problem state of the hpG library: device tables, data and work buffers.
 #pragma once
 
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "hpg_internal.h"
@@ -56,12 +58,28 @@ struct TimingGroup {
     size_t used = 0;
 };
 
+struct GraphKey {
+    int prec, chunk;
+    const void* b;
+    const void* x;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(prec, chunk, b, x) < std::tie(o.prec, o.chunk, o.b, o.x);
+    }
+};
+
 struct Problem {
     Mesh M;
     int device = 0;
     hipStream_t own_stream = nullptr;
+    hipStream_t side = nullptr;            // second stream for the concurrent psi-side work
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_enter = nullptr, ev_leave = nullptr;
+    bool use_graphs = true;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    bool fdm_dot_fused = true;
+    DBuf params;                           // alpha, beta, 1/alpha of the linearisation
+    double hparams[4] = {1.0, 0.0, 1.0, 0.0};
     dev::Geo geo{};
-    int cpb_psi = 1, cpb_setup = 1, cpb_l2 = 1;
+    int cpb_psi = 1, cpb_setup = 1, cpb_l2 = 1, cpb_prec = 1;
     DevRows<double> rows64[3];
     DevRows<float> rows32[3];
     DevTabs<double> tab64;
@@ -82,12 +100,13 @@ struct Problem {
     // Krylov
     KrylovWork<double> kw64;
     KrylovWork<float> kw32;
-    DBuf partial, kstate, done;
-    int np_u = 0, np_psi = 0, np_dot = 0, np_cap = 0;
+    DBuf partial, kstate;
+    int np_u = 0, np_psi = 0, np_dot = 0, np_prec = 0, np_cap = 0;
     // Newton state
     DBuf u, psi, psi_prev, ut, pt, R, u_old, delta64, delta32, rhs32, xk64;
     // timing
     bool timing = false;
+    std::string timing_group;
     std::map<std::string, TimingGroup> groups;
 
     // device-buffer calls run on the caller's stream; NULL is the HIP null stream
@@ -106,6 +125,13 @@ struct Problem {
     void apply_prec(const T* r, T* z, double* partial, const int* done, hipStream_t s);
     template <typename T>
     int minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s);
+    template <typename T>
+    int minres_on(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s);
+    template <typename T>
+    void minres_iterations(int count, int par0, T*& vcur, T*& vprev, T*& wprev, T*& wcur, T* q,
+                           T* Gq, T* z, T* x, hipStream_t s);
+    void fork(hipStream_t s);
+    void join(hipStream_t s);
     // residual into R; returns (||R_u||^2, ||R_psi||^2) (synchronises)
     void residual(const double* u, const double* psi, const double* psi_prev, double alpha,
                   double* R, hipStream_t s, double* nu2, double* np2);

@@ -86,6 +86,12 @@ void KrylovWork<T>::ensure(int64_t n_, int64_t n_u) {
 }
 
 Problem::~Problem() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_enter) (void)hipEventDestroy(ev_enter);
+    if (ev_leave) (void)hipEventDestroy(ev_leave);
     for (auto& kv : groups) {
         for (auto e : kv.second.start) (void)hipEventDestroy(e);
         for (auto e : kv.second.stop) (void)hipEventDestroy(e);
@@ -229,6 +235,11 @@ void Problem::build(const Mesh& mesh, int dev_) {
     if (device < 0 || device >= ndev) fail(HPG_ERR_INVALID_ARG, "no such HIP device");
     HPG_HIP(hipSetDevice(device));
     HPG_HIP(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+    HPG_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HPG_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    HPG_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    HPG_HIP(hipEventCreateWithFlags(&ev_enter, hipEventDisableTiming));
+    HPG_HIP(hipEventCreateWithFlags(&ev_leave, hipEventDisableTiming));
     {
         hipDeviceProp_t prop;
         HPG_HIP(hipGetDeviceProperties(&prop, device));
@@ -264,6 +275,11 @@ void Problem::build(const Mesh& mesh, int dev_) {
         fail(HPG_ERR_INVALID_ARG, "P^d too large for the in-LDS Schur block inverse");
     cpb_setup = std::max(1, std::min(256 / std::max(1, geo.Pd), (int)(lds_max / setup_cell)));
     while (cpb_setup > 1 && setup_cell * cpb_setup > std::min<size_t>(64 * 1024, lds_max)) --cpb_setup;
+    // psi-block preconditioner: ~16 KB of inverse blocks per block of 256 threads
+    cpb_prec = std::max(1, (int)(2048 / std::max<int64_t>(1, M.Pd * M.Pd)));
+    while (cpb_prec > 1 && (size_t)cpb_prec * (M.Pd * M.Pd + M.Pd) * 8 > 48 * 1024) --cpb_prec;
+    if ((size_t)(M.Pd * M.Pd + M.Pd) * 8 > lds_max)
+        fail(HPG_ERR_INVALID_ARG, "P^d too large for the LDS-staged preconditioner blocks");
     // 1-D rows per direction
     for (int k = 0; k < 3; ++k) {
         Rows1D R;
@@ -365,15 +381,28 @@ void Problem::build(const Mesh& mesh, int dev_) {
     upload(C, Call);
     upload(cclass, cc);
     // reduction scratch
-    np_u = (int)((M.n_u + 255) / 256);
-    np_psi = (int)((M.n_cells + cpb_psi - 1) / cpb_psi);
-    np_dot = 512;
+    np_u = (int)std::min<int64_t>((M.n_u + 127) / 128, 1024);
+    np_psi = (int)std::min<int64_t>((M.n_cells + cpb_psi - 1) / cpb_psi, 1024);
+    // partial sums of <z_u, r_u>: fused into the last fast-diagonalisation pass
+    // when that pass has few enough blocks, else a separate 512-block kernel
+    {
+        int64_t nb_last;
+        if (M.d == 1) {
+            nb_last = (M.n1[0] + 15) / 16;
+        } else {
+            int64_t inner = 1;
+            for (int j = 0; j < M.d - 1; ++j) inner *= M.n1[j];
+            nb_last = ((inner + 15) / 16) * ((M.n1[M.d - 1] + 15) / 16);
+        }
+        fdm_dot_fused = nb_last <= 2048;
+        np_dot = fdm_dot_fused ? (int)nb_last : 512;
+    }
     const int np_l2 = 2 * (int)((M.n_cells + cpb_l2 - 1) / cpb_l2);
-    np_cap = std::max({np_u + np_psi, np_dot + (int)((M.n_cells * M.Pd + 255) / 256), np_l2});
+    np_prec = (int)std::min<int64_t>((M.n_cells + cpb_prec - 1) / cpb_prec, 1024);
+    np_cap = std::max({np_u + np_psi, np_dot + np_prec, np_l2});
     partial.alloc((size_t)np_cap * sizeof(double));
-    kstate.alloc(sizeof(dev::KState));
-    done.alloc(sizeof(int));
-    HPG_HIP(hipMemset(done.p, 0, sizeof(int)));
+    params.alloc(4 * sizeof(double));
+    kstate.alloc(2 * sizeof(dev::KState));
 }
 
 // F_i = (f, v_i), Phi_i = (phi, zeta_i) by the Gauss-Legendre rule (sum-factorised)
@@ -479,8 +508,12 @@ void Problem::ensure_work() {
 }
 
 // ---------------------------------------------------------------------------
+static bool timed(const Problem& P, const char* grp) {
+    return P.timing && (P.timing_group == "all" || P.timing_group == grp);
+}
+
 void Problem::tstart(const char* grp, hipStream_t s) {
-    if (!timing) return;
+    if (!timed(*this, grp)) return;
     TimingGroup& g = groups[grp];
     if (g.used == g.start.size()) {
         hipEvent_t a, b;
@@ -492,7 +525,7 @@ void Problem::tstart(const char* grp, hipStream_t s) {
     HPG_HIP(hipEventRecord(g.start[g.used], s));
 }
 void Problem::tstop(const char* grp, hipStream_t s) {
-    if (!timing) return;
+    if (!timed(*this, grp)) return;
     TimingGroup& g = groups[grp];
     HPG_HIP(hipEventRecord(g.stop[g.used], s));
     g.used++;
@@ -503,6 +536,10 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
     beta = beta_;
     precision = prec;
     ensure_linearisation_buffers();
+    hparams[0] = alpha;
+    hparams[1] = beta;
+    hparams[2] = 1.0 / alpha;
+    HPG_HIP(hipMemcpyAsync(params.p, hparams, sizeof(hparams), hipMemcpyHostToDevice, s));
     tstart("setup", s);
     dev::launch_setup(geo, tab64.view(), cpb_setup, d_psi, alpha, beta, C.as<double>(),
                       cclass.as<int>(), prec == HPG_FP64 ? om64.as<double>() : nullptr,
@@ -537,19 +574,37 @@ struct Sel<float> {
     static constexpr int prec = HPG_MIXED;
 };
 
+// fork work onto the side stream: everything enqueued on s2 after fork()
+// runs concurrently with s until join()
+void Problem::fork(hipStream_t s) {
+    HPG_HIP(hipEventRecord(ev_fork, s));
+    HPG_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+}
+void Problem::join(hipStream_t s) {
+    HPG_HIP(hipEventRecord(ev_join, side));
+    HPG_HIP(hipStreamWaitEvent(s, ev_join, 0));
+}
+
 template <typename T>
 void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t s) {
     if (!linearised || precision != Sel<T>::prec)
         fail(HPG_ERR_INVALID_ARG, "operator not set up for this precision (call hpg_op_setup)");
     const DevRows<T>* rw = Sel<T>::rows(*this);
     dev::URows<T> r[3] = {rw[0].view(), rw[1].view(), rw[2].view()};
-    tstart("apply_G", s);
-    dev::launch_u_side<T>(geo, r, (T)alpha, x, x + M.n_u, nullptr, nullptr, y, part, dn,
-                          dev::MODE_APPLY, s);
+    const double* prm = params.as<double>();
+    const bool par = !timing;   // timed runs keep every launch on one stream
+    hipStream_t s_psi = par ? side : s;
+    if (par) fork(s);
+    tstart("apply_G_psi", s_psi);
     dev::launch_psi_side<T>(geo, Sel<T>::tabs(*this).view(), cpb_psi, (T)beta, x, x + M.n_u,
                             Sel<T>::om(*this), nullptr, y + M.n_u, part ? part + np_u : nullptr,
-                            dn, dev::MODE_APPLY, s);
-    tstop("apply_G", s);
+                            dn, dev::MODE_APPLY, s_psi, prm);
+    tstop("apply_G_psi", s_psi);
+    tstart("apply_G_u", s);
+    dev::launch_u_side<T>(geo, r, (T)alpha, x, x + M.n_u, nullptr, nullptr, y, part, dn,
+                          dev::MODE_APPLY, s, prm);
+    tstop("apply_G_u", s);
+    if (par) join(s);
 }
 
 template <typename T>
@@ -561,38 +616,62 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
     const DevFdm<T>& F = Sel<T>::fdm(*this);
     T* t1 = kw.t1.template as<T>();
     T* t2 = kw.t2.template as<T>();
-    tstart("apply_prec", s);
-    // A-block: z_u = (alpha A)^{-1} r_u by fast diagonalisation, d forward
-    // passes with V^T, eigenvalue division, d backward passes with V
+    const double* prm = params.as<double>();
+    const bool par = !timing;
+    hipStream_t s_psi = par ? side : s;
+    if (par) fork(s);
+    // psi-block: z_psi = (-S_hat_K)^{-1} r_psi, concurrently with the A-block
+    tstart("prec_psi", s_psi);
+    dev::launch_prec_psi<T>(M.n_cells, (int)M.Pd, cpb_prec, Sel<T>::sinv(*this), r + M.n_u,
+                            z + M.n_u, part ? part + np_dot : nullptr, dn, s_psi);
+    tstop("prec_psi", s_psi);
+    // A-block: z_u = (alpha A)^{-1} r_u by fast diagonalisation: d forward
+    // passes with V^T (the last one divides by alpha (lam_0 + ... )), then d
+    // backward passes with V (the last one forms the partial sums of <z_u, r_u>)
+    tstart("fdm", s);
     const int d = M.d;
     const T* src = r;
     int pass = 0;
     const int npass = 2 * d;
+    const bool fuse_dot = part && fdm_dot_fused;
     for (int ph = 0; ph < 2; ++ph) {
         for (int k = 0; k < d; ++k) {
             ++pass;
             T* dst = (pass == npass) ? z : ((src == t1) ? t2 : t1);
-            const T* Mat = ph == 0 ? F.Vt[k].template as<T>() : F.V[k].template as<T>();
+            dev::GemmEpi<T> ep{};
+            if (ph == 0 && k == d - 1) {
+                ep.scale_mode = d;   // 1, 2, 3 as documented in the kernel
+                ep.n0 = M.n1[0];
+                ep.l0 = F.lam[0].template as<T>();
+                ep.l1 = F.lam[1].template as<T>();
+                ep.l2 = F.lam[2].template as<T>();
+                ep.prm = prm;
+            }
+            if (pass == npass && fuse_dot) {
+                ep.dotv = r;
+                ep.partial = part;
+            }
             const int N = M.n1[k];
             if (k == 0) {
-                dev::launch_gemm_right<T>(M.n_u / N, N, src, Mat, dst, dn, s);
+                // Y (R x N) = X (R x N) Mat^T with Mat = V^T (forward) / V (backward)
+                const T* Bm = ph == 0 ? F.V[k].template as<T>() : F.Vt[k].template as<T>();
+                const int R = (int)(M.n_u / N);
+                dev::launch_gemm<T>(R, N, N, src, N, 0, Bm, N, 0, dst, N, 0, 1, dn, ep, s);
             } else {
+                // Y_o (N x inner) = Mat (N x N) X_o (N x inner)
+                const T* Am = ph == 0 ? F.Vt[k].template as<T>() : F.V[k].template as<T>();
                 int64_t inner = 1;
                 for (int j = 0; j < k; ++j) inner *= M.n1[j];
                 const int64_t outer = M.n_u / (inner * N);
-                dev::launch_gemm_left<T>(outer, N, inner, src, Mat, dst, dn, s);
+                dev::launch_gemm<T>(N, (int)inner, N, Am, N, 0, src, inner, (int64_t)N * inner, dst,
+                                    inner, (int64_t)N * inner, (int)outer, dn, ep, s);
             }
             src = dst;
         }
-        if (ph == 0)
-            dev::launch_fdm_scale<T>(geo, F.lam[0].template as<T>(), F.lam[1].template as<T>(),
-                                     F.lam[2].template as<T>(), (T)(1.0 / alpha),
-                                     const_cast<T*>(src), dn, s);
     }
-    if (part) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
-    dev::launch_prec_psi<T>(M.n_cells, (int)M.Pd, Sel<T>::sinv(*this), r + M.n_u, z + M.n_u,
-                            part ? part + np_dot : nullptr, dn, s);
-    tstop("apply_prec", s);
+    if (part && !fuse_dot) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
+    tstop("fdm", s);
+    if (par) join(s);
 }
 
 static double host_sum(const double* d_part, int n, hipStream_t s) {
@@ -605,7 +684,50 @@ static double host_sum(const double* d_part, int n, hipStream_t s) {
 }
 
 template <typename T>
-int Problem::minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s) {
+void Problem::minres_iterations(int count, int par0, T*& vcur, T*& vprev, T*& wprev, T*& wcur,
+                                T* q, T* Gq, T* z, T* x, hipStream_t s) {
+    auto* st = kstate.as<dev::KState>();
+    double* part = partial.as<double>();
+    const int64_t n = M.n_u + M.n_psi;
+    const int npG = np_u + np_psi, npP = np_dot + np_prec;
+    int par = par0;
+    for (int j = 0; j < count; ++j) {
+        dev::KState* cur = st + par;
+        dev::KState* nxt = st + (1 - par);
+        const int* dn = &cur->done;
+        apply_G<T>(q, Gq, part, dn, s);
+        tstart("minres_vec", s);
+        dev::launch_kr_vhat<T>(n, cur, part, npG, Gq, vcur, vprev, s);
+        tstop("minres_vec", s);
+        apply_prec<T>(vprev, z, part, dn, s);
+        tstart("minres_vec", s);
+        dev::launch_kr_update<T>(n, cur, nxt, part, npP, q, wprev, wcur, x, vprev, z, s);
+        tstop("minres_vec", s);
+        std::swap(vprev, vcur);
+        std::swap(wprev, wcur);
+        par = 1 - par;
+    }
+}
+
+template <typename T>
+int Problem::minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t caller) {
+    // run on the library's own stream (capturable, unlike the legacy null
+    // stream), ordered after the caller's earlier work and before its later work
+    hipStream_t s = own_stream;
+    if (caller != s) {
+        HPG_HIP(hipEventRecord(ev_enter, caller));
+        HPG_HIP(hipStreamWaitEvent(s, ev_enter, 0));
+    }
+    const int iters = minres_on(b, x, rtol, maxit, chunk, s);
+    if (caller != s) {
+        HPG_HIP(hipEventRecord(ev_leave, s));
+        HPG_HIP(hipStreamWaitEvent(caller, ev_leave, 0));
+    }
+    return iters;
+}
+
+template <typename T>
+int Problem::minres_on(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s) {
     const int64_t n = M.n_u + M.n_psi;
     KrylovWork<T>& kw = Sel<T>::kw(*this);
     kw.ensure(n, M.n_u);
@@ -617,46 +739,56 @@ int Problem::minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStre
     T* wprev = kw.wprev.template as<T>();
     T* wcur = kw.wcur.template as<T>();
     double* part = partial.as<double>();
-    auto* st = kstate.as<dev::KState>();
-    int* dn = done.as<int>();
-    HPG_HIP(hipMemsetAsync(dn, 0, sizeof(int), s));
+    auto* st = kstate.as<dev::KState>();   // st[0], st[1]: state by iteration parity
+    const int npP = np_dot + np_prec;
     // z1 = M^{-1} b, gamma1^2 = <z1, b>
-    apply_prec<T>(b, z, part, dn, s);
-    const int npP = np_dot + (int)((M.n_cells * M.Pd + 255) / 256);
-    dev::launch_kr_init(st, part, npP, rtol, maxit, dn, s);
-    dev::launch_kr_start<T>(n, st, b, z, vcur, vprev, q, wprev, wcur, x, s);
+    apply_prec<T>(b, z, part, nullptr, s);
+    dev::launch_kr_start<T>(n, st, part, npP, rtol, maxit, b, z, vcur, vprev, q, wprev, wcur, x,
+                            s);
     HPG_HIP(hipGetLastError());
-    int it = 0;
-    int hdone = 0;
-    while (it < maxit) {
-        const int nc = std::min(chunk, maxit - it);
-        for (int j = 0; j < nc; ++j) {
-            apply_G<T>(q, Gq, part, dn, s);
-            dev::launch_kr_delta(st, part, np_u + np_psi, s);
-            tstart("minres_vec", s);
-            dev::launch_kr_vhat<T>(n, st, Gq, vcur, vprev, dn, s);
-            tstop("minres_vec", s);
-            apply_prec<T>(vprev, z, part, dn, s);
-            dev::launch_kr_rotate(st, part, npP, dn, s);
-            tstart("minres_vec", s);
-            dev::launch_kr_update<T>(n, st, q, wprev, wcur, x, vprev, z, dn, s);
-            tstop("minres_vec", s);
-            dev::launch_kr_finish(st, dn, s);
-            std::swap(vprev, vcur);
-            std::swap(wprev, wcur);
+    chunk = std::max(2, chunk + (chunk & 1));   // even: buffer roles and parity repeat
+    // a chunk of iterations is captured once per (precision, b, x) and replayed;
+    // timed runs launch directly so each kernel can be bracketed by events
+    hipGraphExec_t exec = nullptr;
+    if (use_graphs && !timing) {
+        const GraphKey key{Sel<T>::prec, chunk, (const void*)b, (const void*)x};
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            T *vc = vcur, *vp = vprev, *wp = wprev, *wc = wcur;
+            hipGraph_t g;
+            HPG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            minres_iterations<T>(chunk, 0, vc, vp, wp, wc, q, Gq, z, x, s);
+            HPG_HIP(hipStreamEndCapture(s, &g));
+            HPG_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+            HPG_HIP(hipGraphDestroy(g));
+            graphs[key] = exec;
+        } else {
+            exec = it->second;
         }
-        it += nc;
-        HPG_HIP(hipMemcpyAsync(&hdone, dn, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    int it = 0;
+    dev::KState hs;
+    while (it < maxit) {
+        if (exec) {
+            HPG_HIP(hipGraphLaunch(exec, s));
+            it += chunk;
+        } else {
+            const int nc = std::min(chunk, maxit - it);
+            minres_iterations<T>(nc, 0, vcur, vprev, wprev, wcur, q, Gq, z, x, s);
+            it += nc;
+            if (nc & 1) {   // odd tail: the state of the last iteration sits in st[1]
+                HPG_HIP(hipMemcpyAsync(&hs, st + 1, sizeof(hs), hipMemcpyDeviceToHost, s));
+                HPG_HIP(hipStreamSynchronize(s));
+                break;
+            }
+        }
+        HPG_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
         HPG_HIP(hipStreamSynchronize(s));
-        if (hdone) break;
+        if (hs.done) break;
     }
     HPG_HIP(hipGetLastError());
-    dev::KState hs;
-    HPG_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-    HPG_HIP(hipStreamSynchronize(s));
-    if (hs.breakdown && hs.iters == 0 && hs.gamma1 != 0.0 && hs.gamma1 == hs.gamma1)
-        fail(HPG_ERR_NUMERIC, "MINRES breakdown");
     if (!(hs.gamma1 == hs.gamma1)) fail(HPG_ERR_NUMERIC, "MINRES: non-finite right-hand side");
+    if (hs.breakdown && hs.iters == 0 && hs.gamma1 != 0.0) fail(HPG_ERR_NUMERIC, "MINRES breakdown");
     return hs.iters;
 }
 
@@ -752,18 +884,24 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
             }
             if (it == o.max_newton) break;
             setup(dp, alpha_k, o.beta, mixed ? HPG_MIXED : HPG_FP64, s);
+            // inexact Newton (optional): a linear-solve tolerance proportional
+            // to the current error.  MINRES measures the residual in the
+            // preconditioner's norm, which is much looser than the Newton
+            // error measure, hence the small factor.
+            const double eta = o.inexact_newton
+                                   ? std::min(1e-6, std::max(o.krylov_rtol, 1e-6 * err))
+                                   : o.krylov_rtol;
             int its;
             if (mixed) {
                 float* b32 = rhs32.as<float>();
                 float* x32 = delta32.as<float>();
                 dev::launch_convert<double, float>(n, dR, b32, -1.0, s);
-                its = minres<float>(b32, x32, o.krylov_rtol, o.max_krylov, o.krylov_chunk, s);
+                its = minres<float>(b32, x32, eta, o.max_krylov, o.krylov_chunk, s);
                 dev::launch_convert<float, double>(n, x32, dd, 1.0, s);
             } else {
                 // b = -R in dd, MINRES into xk64, then delta = xk64
                 dev::launch_convert<double, double>(n, dR, dd, -1.0, s);
-                its = minres<double>(dd, xk64.as<double>(), o.krylov_rtol, o.max_krylov,
-                                     o.krylov_chunk, s);
+                its = minres<double>(dd, xk64.as<double>(), eta, o.max_krylov, o.krylov_chunk, s);
                 HPG_HIP(hipMemcpyAsync(dd, xk64.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             }
             S.krylov_iters += its;
@@ -832,6 +970,12 @@ template void Problem::apply_G<float>(const float*, float*, double*, const int*,
 template void Problem::apply_prec<double>(const double*, double*, double*, const int*, hipStream_t);
 template void Problem::apply_prec<float>(const float*, float*, double*, const int*, hipStream_t);
 template int Problem::minres<double>(const double*, double*, double, int, int, hipStream_t);
+template int Problem::minres_on<double>(const double*, double*, double, int, int, hipStream_t);
+template int Problem::minres_on<float>(const float*, float*, double, int, int, hipStream_t);
+template void Problem::minres_iterations<double>(int, int, double*&, double*&, double*&, double*&,
+                                                 double*, double*, double*, double*, hipStream_t);
+template void Problem::minres_iterations<float>(int, int, float*&, float*&, float*&, float*&,
+                                                float*, float*, float*, float*, hipStream_t);
 template int Problem::minres<float>(const float*, float*, double, int, int, hipStream_t);
 
 }  // namespace hpg

@@ -39,7 +39,7 @@ class SolveOpts(ctypes.Structure):
                 ("stall_tol", ctypes.c_double), ("max_newton", ctypes.c_int32),
                 ("krylov_rtol", ctypes.c_double), ("max_krylov", ctypes.c_int32),
                 ("beta", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("krylov_chunk", ctypes.c_int32)]
+                ("krylov_chunk", ctypes.c_int32), ("inexact_newton", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -57,7 +57,8 @@ EXPORTS = ["hpg_last_error", "hpg_create_mesh", "hpg_destroy_mesh", "hpg_get_mes
            "hpg_quadrature_points", "hpg_create_problem", "hpg_destroy_problem",
            "hpg_set_forcing", "hpg_set_obstacle", "hpg_default_opts", "hpg_solve",
            "hpg_solve_device", "hpg_op_setup", "hpg_op_apply_G", "hpg_op_apply_prec",
-           "hpg_op_minres", "hpg_op_residual", "hpg_set_kernel_timing", "hpg_kernel_time"]
+           "hpg_op_minres", "hpg_op_residual", "hpg_l2_diff", "hpg_set_kernel_timing",
+           "hpg_kernel_time"]
 
 _lib = None
 
@@ -89,7 +90,8 @@ def load():
         "hpg_op_apply_prec": ([P, P, P, P], ctypes.c_int),
         "hpg_op_minres": ([P, P, P, D, I32, P, P], ctypes.c_int),
         "hpg_op_residual": ([P, P, P, P, D, P, P], ctypes.c_int),
-        "hpg_set_kernel_timing": ([P, I32], ctypes.c_int),
+        "hpg_l2_diff": ([P, P, P, P, P, P], ctypes.c_int),
+        "hpg_set_kernel_timing": ([P, ctypes.c_char_p], ctypes.c_int),
         "hpg_kernel_time": ([P, ctypes.c_char_p, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -220,8 +222,17 @@ class Problem:
         _check(load().hpg_op_residual(self.h, _tptr(u), _tptr(psi), _tptr(psi_prev), alpha,
                                       _tptr(R), ctypes.c_void_p(stream) if stream else None))
 
-    def set_kernel_timing(self, enable):
-        _check(load().hpg_set_kernel_timing(self.h, 1 if enable else 0))
+    def l2_diff(self, a, b, stream=None):
+        """(||a_h - b_h||_L2, ||b_h||_L2) for device u vectors a, b."""
+        d = ctypes.c_double(0.0)
+        nb = ctypes.c_double(0.0)
+        _check(load().hpg_l2_diff(self.h, _tptr(a), _tptr(b), ctypes.byref(d), ctypes.byref(nb),
+                                  ctypes.c_void_p(stream) if stream else None))
+        return d.value, nb.value
+
+    def set_kernel_timing(self, group):
+        """group: None (off), "all", or one kernel group name."""
+        _check(load().hpg_set_kernel_timing(self.h, group.encode() if group else None))
 
     def kernel_time(self, group):
         n = ctypes.c_int64(0)

@@ -158,3 +158,19 @@ def test_full_solve_matches_oracle_fp64(dim, m, p, which):
 def prob_opts(fixed=0, precision=0, **kw):
     from paper_2412_13733_amd import hpg
     return hpg.default_opts(fixed_prox_steps=fixed, precision=precision, **kw)
+
+
+@pytest.mark.parametrize("dim,m,p,which", SOLVE_CASES)
+def test_full_solve_mixed_precision(dim, m, p, which):
+    # FP32 operator/preconditioner in MINRES, FP64 residual, exp and update:
+    # the Newton loop refines the FP32 Krylov solutions to the FP64 answer
+    log("solve mixed", dim, m, p, which)
+    data = {"w1d": W.w1d(), "w2d": W.w2d(0), "w3d": W.w3d()}[which]
+    mesh, prob, sysm = build_pair(dim, m, p, data)
+    ro = lvpp.solve(sysm, lvpp.Options())
+    opts = prob_opts(fixed=ro.prox_steps, precision=1, newton_tol=1e-10, krylov_rtol=1e-6)
+    u, psi, lam, st = prob.solve(opts, want_lambda=True)
+    eu = sysm.l2_norm_u(u - ro.u) / sysm.l2_norm_u(ro.u)
+    log("  gpu", st.as_dict(), "rel L2 u", eu)
+    assert st.status == 0
+    assert eu < 1e-8
