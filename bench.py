@@ -1,18 +1,25 @@
 """Benchmark of the hpG hot path on one MI355X.
 
 One step = one complete hpG solve (proximal-point loop, Newton, MINRES with
-the block preconditioner, all on the GPU) of the 2-D obstacle workload:
+the block preconditioner P_D, all on the GPU) of the 2-D obstacle workload:
 unit square, 32 x 32 cells, p = 6, f = sum_{i,j<=4} c_ij sin(i pi x) sin(j pi y)
 (c_ij ~ N(0,1) 20/(i^2+j^2), seed 0), phi = 0.05 + 0.3 |x - (1/2,1/2)|^2,
 alpha_k = 2^k, outer tolerance 1e-10.  Inputs are resident in HBM before the
 timed region; each solve writes u and psi into device buffers.
 
-Reported: DOF * Krylov iterations per second (value), solves/s and p50/p99
-solve latency, the roofline position of the dominant kernel (HIP events
-around its launches inside the timed region, algorithmic bytes per launch),
-and the CPU oracle's throughput on a bounded sample (cpu_baseline).
+Timed regions (each bracketed by torch.cuda.synchronize()):
+  1. K solves per precision path (FP64; mixed = FP32 Krylov + FP64 Newton),
+     MINRES chunks replayed as HIP graphs: value, solves/s, p50/p99 latency.
+  2. the same K solves of the headline path with HIP events around every
+     launch of each kernel group (graphs off, so each launch can be
+     bracketed): per-group average durations, from which the roofline
+     position of the dominant group is computed.
+  3. apply_G alone on the large low-p mesh (2-D 4096 x 4096 cells, p = 2:
+     2.55 GB of algorithmic traffic per FP64 apply), HIP events per launch:
+     the HBM-roofline position of the operator apply.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-probe]
 """
 import argparse
 import json
@@ -26,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 
 
 def parse():
@@ -39,28 +47,38 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-newton-sample", type=int, default=2)
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--probe-m", type=int, default=4096)
+    ap.add_argument("--probe-p", type=int, default=2)
+    ap.add_argument("--probe-launches", type=int, default=20)
     return ap.parse_args()
 
 
-def algorithmic_bytes(group, mesh, b):
-    """Bytes a launch of the kernel group must move (each input read once,
-    each output written once)."""
+GROUPS = ["apply_G_u", "apply_G_psi", "fdm", "prec_psi", "minres_vec", "setup", "residual"]
+
+
+def group_work(mesh, b):
+    """Algorithmic work of one launch of each kernel group: bytes each input
+    is read once and each output written once, or flops for the MFMA passes."""
     n_u, n_psi, N = mesh.n_u, mesh.n_psi, mesh.n_cells
     Pd, Qd = mesh.P ** mesh.dim, mesh.q ** mesh.dim
-    if group == "prec_psi":        # Sinv blocks, r_psi in, z_psi out
-        return b * (N * Pd * Pd + 2 * n_psi)
-    if group == "apply_G":         # x in, omega in, y out
-        return b * (2 * n_u + 2 * n_psi + N * Qd)
-    if group == "apply_prec":      # r in, z out, Sinv blocks (FDM factors stay in cache)
-        return b * (2 * n_u + 2 * n_psi + N * Pd * Pd)
-    raise KeyError(group)
+    n1 = mesh.info.ncells[0] * mesh.p - 1
+    d = mesh.dim
+    return {
+        # u-side: x_u, x_psi in, y_u out
+        "apply_G_u": ("hbm", b * (2 * n_u + n_psi)),
+        # psi-side: x_u, x_psi, omega in, y_psi out
+        "apply_G_psi": ("hbm", b * (n_u + 2 * n_psi + N * Qd)),
+        # 2d tensor-axis passes, each 2 n1^(d+1) flops
+        "fdm": ("mfma", 2 * d * 2.0 * n1 ** (d + 1)),
+        # inverse blocks, r_psi in, z_psi out
+        "prec_psi": ("hbm", b * (N * Pd * Pd + 2 * n_psi)),
+    }
 
 
 def run_solves(prob, d_u, d_psi, opts, steps, torch, group=None):
     lat = []
-    kry = 0
-    newton = 0
-    prox = 0
+    kry = newton = prox = 0
     if group:
         prob.set_kernel_timing(group)
     torch.cuda.synchronize()
@@ -75,17 +93,19 @@ def run_solves(prob, d_u, d_psi, opts, steps, torch, group=None):
         assert st.status == 0, st.as_dict()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = None
+    kt = {}
     if group:
-        kt = prob.kernel_time(group)
+        for g in GROUPS:
+            kt[g] = prob.kernel_time(g)
         prob.set_kernel_timing(None)
     return dict(seconds=t1 - t0, lat=lat, krylov=kry, newton=newton, prox=prox, ktime=kt)
 
 
 def cpu_baseline(args, newton_per_solve):
     """The oracle as it stands, on a bounded sample: a few Newton steps of the
-    first proximal subproblem of the same workload (sparse LU of G each step),
-    one thread; extrapolated to solves/s with the Newton count of a solve."""
+    first proximal subproblem of the same workload (sparse LU of the full
+    saddle matrix G each step), one thread; extrapolated to solves/s with the
+    Newton count of one solve of the same discrete problem."""
     from threadpoolctl import threadpool_limits
     from oracle import assemble, lvpp, mesh as OM
     import workloads as W
@@ -99,8 +119,7 @@ def cpu_baseline(args, newton_per_solve):
         res = lvpp.Result()
         res.newton = 0
         res.lu_seconds = 0.0
-        k = args.cpu_newton_sample
-        opts = lvpp.Options(max_newton=k)
+        opts = lvpp.Options(max_newton=args.cpu_newton_sample)
         z = np.zeros(om.n_psi)
         t1 = time.perf_counter()
         lvpp.newton_subproblem(sysm, np.zeros(om.n_u), z, z.copy(), 2.0, opts, res)
@@ -110,15 +129,56 @@ def cpu_baseline(args, newton_per_solve):
     return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": "%d Newton steps (sparse LU of the full saddle matrix, %d DOF) of the "
                       "first proximal subproblem, %.1f s, plus assembly %.1f s; extrapolated "
-                      "with the GPU solve's %d Newton steps per solve; 1 thread"
+                      "with %d Newton steps per solve; 1 thread"
                       % (res.newton, om.n_u + om.n_psi, dt, t_asm, newton_per_solve),
             "seconds_per_newton_step": per_newton}
+
+
+def apply_probe(args, torch, hpg):
+    """HBM roofline of the operator apply on a large low-p mesh (FP64)."""
+    m, p = args.probe_m, args.probe_p
+    mesh = hpg.Mesh(2, [m, m], p)
+    prob = hpg.Problem(mesh, device=0)
+    n = mesh.n_u + mesh.n_psi
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    psi = 0.5 * torch.randn(mesh.n_psi, dtype=torch.float64, device="cuda", generator=gen)
+    x = torch.randn(n, dtype=torch.float64, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    prob.op_setup(psi, 4.0, 0.0, precision=hpg.FP64)
+    for _ in range(3):
+        prob.op_apply_G(x, y)
+    prob.set_kernel_timing("all")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.probe_launches):
+        prob.op_apply_G(x, y)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.probe_launches
+    nu, msu = prob.kernel_time("apply_G_u")
+    npx, msp = prob.kernel_time("apply_G_psi")
+    prob.set_kernel_timing(None)
+    Qd = mesh.q ** 2
+    alg = 8 * (2 * mesh.n_u + 2 * mesh.n_psi + mesh.n_cells * Qd)
+    t_apply = (msu / nu + msp / npx) * 1e-3
+    ach = alg / t_apply / 1e9
+    work = group_work(mesh, 8)
+    out = {"workload": "apply_G, 2-D %dx%d cells, p=%d, FP64" % (m, m, p),
+           "algorithmic_bytes": alg, "apply_us": t_apply * 1e6,
+           "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
+           "u_side_us": msu / nu * 1e3, "psi_side_us": msp / npx * 1e3,
+           "u_side_GBs": work["apply_G_u"][1] / (msu / nu * 1e-3) / 1e9,
+           "psi_side_GBs": work["apply_G_psi"][1] / (msp / npx * 1e-3) / 1e9,
+           "wall_us_per_call": wall * 1e6, "launches": nu}
+    del prob, mesh, x, y, psi
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the hpG path here is a single-GPU build "
+        print("bench.py runs on one GPU only: this hpG build is single-GPU "
               "(no collectives); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
@@ -137,9 +197,8 @@ def main():
     d_psi = torch.zeros(mesh.n_psi, dtype=torch.float64, device="cuda")
     d_u64 = torch.zeros_like(d_u)
 
-    results = {}
-    group = "prec_psi"
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    results = {}
     for prec in precs:
         opts = hpg.default_opts(precision=hpg.FP64 if prec == "fp64" else hpg.MIXED)
         if prec == "mixed":
@@ -147,10 +206,10 @@ def main():
             opts.krylov_rtol = 1e-6
         for _ in range(args.warmup):
             prob.solve_device(d_u, d_psi, opts)
-        r = run_solves(prob, d_u, d_psi, opts, args.steps, torch, group=group)
+        r = run_solves(prob, d_u, d_psi, opts, args.steps, torch)
         if prec == "fp64":
             d_u64.copy_(d_u)
-        else:
+        elif "fp64" in precs:
             diff, nrm = prob.l2_diff(d_u, d_u64)
             r["rel_l2_vs_fp64"] = diff / nrm
         r["opts"] = opts
@@ -158,6 +217,47 @@ def main():
         print("[bench] %s: %d solves in %.3f s, krylov %d, newton %d, prox %d"
               % (prec, args.steps, r["seconds"], r["krylov"], r["newton"], r["prox"]),
               file=sys.stderr, flush=True)
+
+    # headline: the faster path whose solution meets rel-L2 1e-8 (vs FP64)
+    best = precs[0]
+    if "mixed" in results and "fp64" in results:
+        if results["mixed"].get("rel_l2_vs_fp64", 1.0) <= 1e-8 and \
+                results["mixed"]["seconds"] < results["fp64"]["seconds"]:
+            best = "mixed"
+    rb = results[best]
+    # timed region 2: per-group kernel durations of the headline path
+    rt = run_solves(prob, d_u, d_psi, rb["opts"], args.steps, torch, group="all")
+    print("[bench] kernel timing pass (%s): %.3f s" % (best, rt["seconds"]), file=sys.stderr,
+          flush=True)
+    b = 8 if best == "fp64" else 4
+    work = group_work(mesh, b)
+    groups = {}
+    for g, (nl, ms) in rt["ktime"].items():
+        if nl == 0:
+            continue
+        ent = {"launches": nl, "total_ms": ms, "avg_us": 1e3 * ms / nl}
+        if g in work:
+            kind, amount = work[g]
+            if kind == "hbm":
+                ent["achieved_GBs"] = amount / (ms / nl * 1e-3) / 1e9
+            else:
+                ent["achieved_TFLOPs"] = amount / (ms / nl * 1e-3) / 1e12
+        groups[g] = ent
+    dom = max((g for g in groups if g in work), key=lambda g: groups[g]["total_ms"])
+    kind, amount = work[dom]
+    avg_s = groups[dom]["avg_us"] * 1e-6
+    if kind == "hbm":
+        ach = amount / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": amount}
+    else:
+        ach = amount / avg_s / 1e12
+        pk = MFMA_PEAK_TFLOPS[best]
+        roof = {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": pk, "unit": "TFLOP/s",
+                "frac": ach / pk, "traffic": None, "flops_per_launch": amount}
+    roof["avg_launch_us"] = groups[dom]["avg_us"]
+    roof["launches"] = groups[dom]["launches"]
 
     def summary(r):
         return dict(dof_krylov_per_s=n_dof * r["krylov"] / r["seconds"],
@@ -169,20 +269,7 @@ def main():
                     newton_per_solve=r["newton"] / args.steps,
                     prox_per_solve=r["prox"] / args.steps)
 
-    # the headline line: the faster path whose solution meets rel-L2 1e-8
-    best = "fp64"
-    if "mixed" in results and results["mixed"].get("rel_l2_vs_fp64", 1.0) <= 1e-8:
-        if "fp64" not in results or results["mixed"]["seconds"] < results["fp64"]["seconds"]:
-            best = "mixed"
-    if "fp64" not in results:
-        best = precs[0]
-    rb = results[best]
     sb = summary(rb)
-    b = 8 if best == "fp64" else 4
-    nl, ms = rb["ktime"]
-    avg = ms / max(nl, 1)
-    byts = algorithmic_bytes(group, mesh, b)
-    achieved = byts / (avg * 1e-3) / 1e9
     out = {
         "metric": "DOF·Krylov-iters/s",
         "value": sb["dof_krylov_per_s"],
@@ -197,7 +284,8 @@ def main():
         "dtype": "f64" if best == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "2-D obstacle, unit square %dx%d cells, p=%d, sine forcing seed %d, "
-                               "paraboloid obstacle, alpha_k=2^k, tol 1e-10" % (args.m, args.m, args.p, args.seed),
+                               "paraboloid obstacle, alpha_k=2^k, tol 1e-10, one full solve per step"
+                               % (args.m, args.m, args.p, args.seed),
                    "n_dof": n_dof, "n_u": mesh.n_u, "n_psi": mesh.n_psi, "path": best},
         "solves_per_s": sb["solves_per_s"],
         "p50_ms": sb["p50_ms"],
@@ -205,17 +293,21 @@ def main():
         "krylov_per_solve": sb["krylov_per_solve"],
         "newton_per_solve": sb["newton_per_solve"],
         "prox_per_solve": sb["prox_per_solve"],
-        "roofline": {"bound": "hbm", "kernel": group, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": byts, "avg_launch_us": avg * 1e3, "launches": nl},
+        "roofline": roof,
+        "kernel_groups": groups,
     }
     for prec, r in results.items():
         s = summary(r)
-        s.pop("dof_krylov_per_s")
-        s["dof_krylov_per_s"] = n_dof * r["krylov"] / r["seconds"]
         if "rel_l2_vs_fp64" in r:
             s["rel_l2_vs_fp64"] = r["rel_l2_vs_fp64"]
         out["path_" + prec] = s
+    if not args.no_probe:
+        del prob
+        torch.cuda.empty_cache()
+        out["apply_G_probe"] = apply_probe(args, torch, hpg)
+        print("[bench] apply_G probe: %.1f us, %.0f GB/s" % (out["apply_G_probe"]["apply_us"],
+                                                            out["apply_G_probe"]["achieved_GBs"]),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, int(round(results[precs[0]]["newton"] / args.steps)))
     print(json.dumps(out), flush=True)

@@ -79,7 +79,7 @@ struct Rows1D {
     std::vector<double> vG;
     std::vector<double> Adense, Mdense;   // n x n global 1-D stiffness and mass (for FDM)
 };
-void build_rows(const Mesh& M, int k, Rows1D& R);
+void build_rows(const Mesh& M, int k, Rows1D& R, bool dense = false);
 
 // Fast diagonalisation (Lynch-Rice-Thomas): A1 V = M1 V Lambda, V^T M1 V = I.
 void generalized_eig(int n, const std::vector<double>& A, const std::vector<double>& B,

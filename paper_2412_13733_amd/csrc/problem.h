@@ -116,6 +116,8 @@ struct Problem {
     void set_data(const double* f, const double* phi);
     void ensure_work();
     void ensure_linearisation_buffers();
+    bool fdm_ready = false;
+    void ensure_fdm();
 
     // operations (all enqueue on stream s)
     void setup(const double* d_psi, double alpha, double beta, int precision, hipStream_t s);

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <tuple>
 
 #include "problem.h"
@@ -316,23 +318,6 @@ void Problem::build(const Mesh& mesh, int dev_) {
         upload(rows32[k].cellB, cellB);
         upload(rows32[k].modeB, modeB);
         upload(rows32[k].vB, cast<float>(R.vB));
-        // fast diagonalisation of the 1-D pair (A1, M1)
-        std::vector<double> V, lam;
-        if (k < M.d) {
-            generalized_eig(R.n, R.Adense, R.Mdense, V, lam);
-        } else {
-            V = {1.0};
-            lam = {0.0};
-        }
-        std::vector<double> Vt(V.size());
-        for (int i = 0; i < R.n; ++i)
-            for (int j = 0; j < R.n; ++j) Vt[(size_t)i * R.n + j] = V[(size_t)j * R.n + i];
-        upload(fdm64.V[k], V);
-        upload(fdm64.Vt[k], Vt);
-        upload(fdm64.lam[k], lam);
-        upload(fdm32.V[k], cast<float>(V));
-        upload(fdm32.Vt[k], cast<float>(Vt));
-        upload(fdm32.lam[k], cast<float>(lam));
     }
     // reference tables
     const RefTables& T = M.ref;
@@ -355,28 +340,49 @@ void Problem::build(const Mesh& mesh, int dev_) {
         upload(tab64.h[k], hv);
         upload(tab32.h[k], cast<float>(hv));
     }
-    // C_K per distinct cell shape
-    std::map<std::tuple<double, double, double>, int> cls;
-    std::vector<int32_t> cc(M.n_cells);
+    // C_K per distinct cell shape: distinct widths per direction, class =
+    // mixed-radix index of the width indices (one class on uniform meshes)
+    std::vector<int> widx[3];
+    std::vector<double> wval[3];
+    for (int k = 0; k < 3; ++k) {
+        if (k >= M.d) {
+            widx[k] = {0};
+            wval[k] = {2.0};
+            continue;
+        }
+        std::map<double, int> seen;
+        widx[k].resize(M.m[k]);
+        for (int c = 0; c < M.m[k]; ++c) {
+            const double hk = M.h(k, c);
+            auto it = seen.find(hk);
+            if (it == seen.end()) {
+                const int id = (int)wval[k].size();
+                seen[hk] = id;
+                wval[k].push_back(hk);
+                widx[k][c] = id;
+            } else {
+                widx[k][c] = it->second;
+            }
+        }
+    }
+    const int nw0 = (int)wval[0].size(), nw1 = (int)wval[1].size(), nw2 = (int)wval[2].size();
     std::vector<double> Call;
+    for (int i2 = 0; i2 < nw2; ++i2)
+        for (int i1 = 0; i1 < nw1; ++i1)
+            for (int i0 = 0; i0 < nw0; ++i0) {
+                const double hk[3] = {wval[0][i0], wval[1][i1], wval[2][i2]};
+                std::vector<double> Cb = schur_block(M, hk);
+                Call.insert(Call.end(), Cb.begin(), Cb.end());
+            }
+    std::vector<int32_t> cc(M.n_cells);
     for (int64_t c = 0; c < M.n_cells; ++c) {
         int64_t t = c;
-        double hk[3] = {2.0, 2.0, 2.0};
+        int ci[3] = {0, 0, 0};
         for (int k = 0; k < M.d; ++k) {
-            hk[k] = M.h(k, (int)(t % M.m[k]));
+            ci[k] = widx[k][(int)(t % M.m[k])];
             t /= M.m[k];
         }
-        auto key = std::make_tuple(hk[0], hk[1], hk[2]);
-        auto it = cls.find(key);
-        if (it == cls.end()) {
-            int id = (int)cls.size();
-            cls[key] = id;
-            std::vector<double> C = schur_block(M, hk);
-            Call.insert(Call.end(), C.begin(), C.end());
-            cc[c] = id;
-        } else {
-            cc[c] = it->second;
-        }
+        cc[c] = ci[0] + nw0 * (ci[1] + nw1 * ci[2]);
     }
     upload(C, Call);
     upload(cclass, cc);
@@ -403,6 +409,56 @@ void Problem::build(const Mesh& mesh, int dev_) {
     partial.alloc((size_t)np_cap * sizeof(double));
     params.alloc(4 * sizeof(double));
     kstate.alloc(2 * sizeof(dev::KState));
+}
+
+// Fast diagonalisation of the 1-D pairs (A1, M1) per direction, built on the
+// first preconditioner apply (an O(n1^3) host eigen-decomposition, cached
+// process-wide by (p, breakpoints) so repeated meshes reuse it).
+namespace {
+struct FdmEntry {
+    std::vector<double> V, lam;
+};
+std::mutex g_fdm_mutex;
+std::map<std::pair<int, std::vector<double>>, std::shared_ptr<FdmEntry>> g_fdm_cache;
+}  // namespace
+
+void Problem::ensure_fdm() {
+    if (fdm_ready) return;
+    for (int k = 0; k < 3; ++k) {
+        std::shared_ptr<FdmEntry> e;
+        int n = 1;
+        if (k < M.d) {
+            n = M.n1[k];
+            auto key = std::make_pair(M.p, M.breaks[k]);
+            {
+                std::lock_guard<std::mutex> lk(g_fdm_mutex);
+                auto it = g_fdm_cache.find(key);
+                if (it != g_fdm_cache.end()) e = it->second;
+            }
+            if (!e) {
+                Rows1D R;
+                build_rows(M, k, R, true);
+                e = std::make_shared<FdmEntry>();
+                generalized_eig(R.n, R.Adense, R.Mdense, e->V, e->lam);
+                std::lock_guard<std::mutex> lk(g_fdm_mutex);
+                g_fdm_cache[key] = e;
+            }
+        } else {
+            e = std::make_shared<FdmEntry>();
+            e->V = {1.0};
+            e->lam = {0.0};
+        }
+        std::vector<double> Vt(e->V.size());
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Vt[(size_t)i * n + j] = e->V[(size_t)j * n + i];
+        upload(fdm64.V[k], e->V);
+        upload(fdm64.Vt[k], Vt);
+        upload(fdm64.lam[k], e->lam);
+        upload(fdm32.V[k], cast<float>(e->V));
+        upload(fdm32.Vt[k], cast<float>(Vt));
+        upload(fdm32.lam[k], cast<float>(e->lam));
+    }
+    fdm_ready = true;
 }
 
 // F_i = (f, v_i), Phi_i = (phi, zeta_i) by the Gauss-Legendre rule (sum-factorised)
@@ -613,6 +669,7 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
         fail(HPG_ERR_INVALID_ARG, "operator not set up for this precision (call hpg_op_setup)");
     KrylovWork<T>& kw = Sel<T>::kw(*this);
     kw.ensure(M.n_u + M.n_psi, M.n_u);
+    ensure_fdm();
     const DevFdm<T>& F = Sel<T>::fdm(*this);
     T* t1 = kw.t1.template as<T>();
     T* t2 = kw.t2.template as<T>();

@@ -126,7 +126,7 @@ void RefTables::build(int p_, int P_, int q_) {
 // Global 1-D rows in direction k.  1-D unknown of local function l of cell c:
 // g = c p + l - 1 (l = 0 left hat, l = p right hat, else bubble l-1), valid
 // when 0 <= g < n1 (the hats of the two boundary vertices are absent).
-void build_rows(const Mesh& M, int k, Rows1D& R) {
+void build_rows(const Mesh& M, int k, Rows1D& R, bool dense) {
     const int p = M.p, P = M.P, m = M.m[k], n1 = M.n1[k];
     const int L = p + 1;
     const RefTables& T = M.ref;
@@ -166,8 +166,10 @@ void build_rows(const Mesh& M, int k, Rows1D& R) {
     R.lenG.assign(n1, 0);
     R.colG.assign(n1 * Rows1D::WB, 0);
     R.vG.assign(n1 * Rows1D::WB, 0.0);
-    R.Adense.assign((size_t)n1 * n1, 0.0);
-    R.Mdense.assign((size_t)n1 * n1, 0.0);
+    if (dense) {
+        R.Adense.assign((size_t)n1 * n1, 0.0);
+        R.Mdense.assign((size_t)n1 * n1, 0.0);
+    }
     for (int g = 0; g < n1; ++g) {
         if ((int)am[g].size() > Rows1D::WM || (int)bm[g].size() > Rows1D::WB ||
             (int)gm[g].size() > Rows1D::WB)
@@ -177,8 +179,10 @@ void build_rows(const Mesh& M, int k, Rows1D& R) {
             R.colM[g * Rows1D::WM + e] = kv.first;
             R.aM[g * Rows1D::WM + e] = kv.second.first;
             R.mM[g * Rows1D::WM + e] = kv.second.second;
-            R.Adense[(size_t)g * n1 + kv.first] = kv.second.first;
-            R.Mdense[(size_t)g * n1 + kv.first] = kv.second.second;
+            if (dense) {
+                R.Adense[(size_t)g * n1 + kv.first] = kv.second.first;
+                R.Mdense[(size_t)g * n1 + kv.first] = kv.second.second;
+            }
             ++e;
         }
         R.lenM[g] = e;
