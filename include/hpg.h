@@ -178,8 +178,9 @@ hpg_status hpg_l2_diff(hpg_problem* prob, const double* d_a, const double* d_b, 
 
 /* ---- kernel timing (for measurement harnesses) ----------------------------
  * group NULL disables timing; "all" times every group; otherwise only the
- * named group ("apply_G_u", "apply_G_psi", "fdm", "prec_psi", "minres_vec",
- * "setup", "residual") is timed.  While enabled, every launch of a timed
+ * named group ("apply_G" (fused tiled apply), "apply_G_u", "apply_G_psi" (the
+ * two-kernel apply used where no tiled variant exists), "fdm", "prec_psi",
+ * "minres_vec", "setup", "residual") is timed.  While enabled, every launch of a timed
  * group is bracketed by HIP events on the stream it is launched on;
  * hpg_kernel_time returns the number of bracketed launches and their summed
  * duration in milliseconds.  Enabling resets the counters. */

@@ -351,6 +351,8 @@ hpg_status hpg_op_residual(hpg_problem* prob, const double* d_u, const double* d
         Problem& P = prob->P;
         double a, b;
         P.residual(d_u, d_psi, d_psi_prev, alpha, d_R, P.stream(stream), &a, &b);
+        (void)a;
+        (void)b;
         return HPG_OK;
     });
 }

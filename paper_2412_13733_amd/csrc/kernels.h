@@ -33,6 +33,10 @@ struct URows {
     const int32_t* cellB;
     const int32_t* modeB;
     const T* vB;
+    // p <= 3: dense windows per 1-D unknown g, stored from row g + 1 (row 0 and
+    // the tail are zero): stiffness and mass at columns g - p .. g + p, then the
+    // psi coupling of cells g / p and g / p + 1 (P modes each)
+    const T* win;
 };
 
 // 1-D reference tables and cell widths
@@ -64,6 +68,17 @@ template <typename T>
 void launch_psi_side(const Geo& g, const PsiTabs<T>& tb, int cpb, T beta, const T* xu,
                      const T* xpsi, const T* omega, const double* Phi, T* ypsi, double* partial,
                      const int* done, int mode, hipStream_t s, const double* prm = nullptr);
+// fused LDS-tiled G apply / residual with compile-time p (tile.hip); returns
+// false when (d, p) has no compiled variant.  Partials: APPLY one per block
+// (<x, Gx>-type sums), RES two per block (||R_u||^2, ||R_psi||^2).
+bool tile_supported(const Geo& g);
+int tile_grid(const Geo& g);          // capped grid (bounded partial count)
+int64_t tile_count(const Geo& g);     // number of tiles
+template <typename T>
+bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
+                 const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
+                 const double* F, const double* Phi, T* yu, T* ypsi, double* partial,
+                 const int* done, int mode, hipStream_t s);
 size_t setup_smem_per_cell(const Geo& g);
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,

@@ -30,7 +30,7 @@ struct DBuf {
 
 template <typename T>
 struct DevRows {
-    DBuf lenM, colM, aM, mM, lenB, cellB, modeB, vB;
+    DBuf lenM, colM, aM, mM, lenB, cellB, modeB, vB, win;
     dev::URows<T> view() const;
 };
 
@@ -74,6 +74,7 @@ struct Problem {
     hipStream_t side = nullptr;            // second stream for the concurrent psi-side work
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_enter = nullptr, ev_leave = nullptr;
     bool use_graphs = true;
+    bool use_tile = false;                 // fused tiled G apply / residual available for (d, p)
     std::map<GraphKey, hipGraphExec_t> graphs;
     bool fdm_dot_fused = true;
     DBuf params;                           // alpha, beta, 1/alpha of the linearisation

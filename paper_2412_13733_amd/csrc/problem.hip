@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -46,6 +47,33 @@ static std::vector<TO> cast(const std::vector<double>& v) {
     return std::vector<TO>(v.begin(), v.end());
 }
 
+// Dense-window form of the 1-D rows for p <= 3 (the fused apply's low-degree
+// path): row g + 1 holds the stiffness and mass entries of columns g - p .. g + p,
+// then the psi coupling of cells g / p and g / p + 1; row 0 and 16 p + 2 tail
+// rows stay zero so that every tile's owned rows read in bounds.
+static std::vector<double> dense_windows(const Mesh& M, const Rows1D& R) {
+    const int p = M.p, P = std::max(1, M.P), WN = 2 * p + 1, WS = 2 * WN + 2 * P;
+    if (p > 3 || M.P != p - 1) return std::vector<double>(1, 0.0);   // obstacle pairing only
+    const int n = R.n;
+    std::vector<double> w((size_t)(n + 1 + 16 * p + 2) * WS, 0.0);
+    for (int gi = 0; gi < n; ++gi) {
+        double* row = w.data() + (size_t)(gi + 1) * WS;
+        for (int j = 0; j < R.lenM[gi]; ++j) {
+            const int off = R.colM[(size_t)gi * Rows1D::WM + j] - gi + p;
+            if (off < 0 || off >= WN) fail(HPG_ERR_NUMERIC, "1-D row wider than its window");
+            row[off] = R.aM[(size_t)gi * Rows1D::WM + j];
+            row[WN + off] = R.mM[(size_t)gi * Rows1D::WM + j];
+        }
+        for (int j = 0; j < R.lenB[gi]; ++j) {
+            const int col = R.colB[(size_t)gi * Rows1D::WB + j];
+            const int sc = col / P - gi / p, a = col % P;
+            if (sc < 0 || sc > 1) fail(HPG_ERR_NUMERIC, "1-D psi coupling outside cells g/p, g/p+1");
+            row[2 * WN + sc * P + a] = R.vB[(size_t)gi * Rows1D::WB + j];
+        }
+    }
+    return w;
+}
+
 template <typename T>
 dev::URows<T> DevRows<T>::view() const {
     dev::URows<T> r;
@@ -57,6 +85,7 @@ dev::URows<T> DevRows<T>::view() const {
     r.cellB = cellB.as<int32_t>();
     r.modeB = modeB.as<int32_t>();
     r.vB = vB.as<T>();
+    r.win = win.as<T>();
     return r;
 }
 template <typename T>
@@ -318,6 +347,9 @@ void Problem::build(const Mesh& mesh, int dev_) {
         upload(rows32[k].cellB, cellB);
         upload(rows32[k].modeB, modeB);
         upload(rows32[k].vB, cast<float>(R.vB));
+        const std::vector<double> win = dense_windows(M, R);
+        upload(rows64[k].win, win);
+        upload(rows32[k].win, cast<float>(win));
     }
     // reference tables
     const RefTables& T = M.ref;
@@ -405,7 +437,8 @@ void Problem::build(const Mesh& mesh, int dev_) {
     }
     const int np_l2 = 2 * (int)((M.n_cells + cpb_l2 - 1) / cpb_l2);
     np_prec = (int)std::min<int64_t>((M.n_cells + cpb_prec - 1) / cpb_prec, 1024);
-    np_cap = std::max({np_u + np_psi, np_dot + np_prec, np_l2});
+    use_tile = dev::tile_supported(geo) && std::getenv("HPG_GENERIC_APPLY") == nullptr;
+    np_cap = std::max({np_u + np_psi, np_dot + np_prec, np_l2, 2 * dev::tile_grid(geo)});
     partial.alloc((size_t)np_cap * sizeof(double));
     params.alloc(4 * sizeof(double));
     kstate.alloc(2 * sizeof(dev::KState));
@@ -648,6 +681,15 @@ void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t
     const DevRows<T>* rw = Sel<T>::rows(*this);
     dev::URows<T> r[3] = {rw[0].view(), rw[1].view(), rw[2].view()};
     const double* prm = params.as<double>();
+    if (use_tile) {
+        // one fused LDS-tiled launch for both sides of G
+        tstart("apply_G", s);
+        dev::launch_tile<T>(geo, r, Sel<T>::tabs(*this).view(), (T)alpha, (T)beta, prm, x,
+                            x + M.n_u, nullptr, Sel<T>::om(*this), nullptr, nullptr, y, y + M.n_u,
+                            part, dn, dev::MODE_APPLY, s);
+        tstop("apply_G", s);
+        return;
+    }
     const bool par = !timing;   // timed runs keep every launch on one stream
     hipStream_t s_psi = par ? side : s;
     if (par) fork(s);
@@ -746,7 +788,7 @@ void Problem::minres_iterations(int count, int par0, T*& vcur, T*& vprev, T*& wp
     auto* st = kstate.as<dev::KState>();
     double* part = partial.as<double>();
     const int64_t n = M.n_u + M.n_psi;
-    const int npG = np_u + np_psi, npP = np_dot + np_prec;
+    const int npG = use_tile ? dev::tile_grid(geo) : np_u + np_psi, npP = np_dot + np_prec;
     int par = par0;
     for (int j = 0; j < count; ++j) {
         dev::KState* cur = st + par;
@@ -855,19 +897,35 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
     dev::URows<double> r[3] = {rows64[0].view(), rows64[1].view(), rows64[2].view()};
     double* part = partial.as<double>();
     tstart("residual", s);
-    dev::launch_u_side<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR, part, nullptr,
-                               dev::MODE_RES, s);
-    dev::launch_psi_side<double>(geo, tab64.view(), cpb_psi, 0.0, uu, pp, nullptr,
-                                 Phi.as<double>(), RR + M.n_u, part + np_u, nullptr,
-                                 dev::MODE_RES, s);
-    tstop("residual", s);
-    HPG_HIP(hipGetLastError());
-    std::vector<double> h(np_u + np_psi);
-    HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HPG_HIP(hipStreamSynchronize(s));
     double a = 0.0, b = 0.0;
-    for (int i = 0; i < np_u; ++i) a += h[i];
-    for (int i = 0; i < np_psi; ++i) b += h[np_u + i];
+    if (use_tile) {
+        dev::launch_tile<double>(geo, r, tab64.view(), alpha_, 0.0, nullptr, uu, pp, pprev, nullptr,
+                                 F.as<double>(), Phi.as<double>(), RR, RR + M.n_u, part, nullptr,
+                                 dev::MODE_RES, s);
+        tstop("residual", s);
+        HPG_HIP(hipGetLastError());
+        const int nb = dev::tile_grid(geo);
+        std::vector<double> h(2 * nb);
+        HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HPG_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < nb; ++i) {
+            a += h[2 * i];
+            b += h[2 * i + 1];
+        }
+    } else {
+        dev::launch_u_side<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR, part, nullptr,
+                                   dev::MODE_RES, s);
+        dev::launch_psi_side<double>(geo, tab64.view(), cpb_psi, 0.0, uu, pp, nullptr,
+                                     Phi.as<double>(), RR + M.n_u, part + np_u, nullptr,
+                                     dev::MODE_RES, s);
+        tstop("residual", s);
+        HPG_HIP(hipGetLastError());
+        std::vector<double> h(np_u + np_psi);
+        HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HPG_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < np_u; ++i) a += h[i];
+        for (int i = 0; i < np_psi; ++i) b += h[np_u + i];
+    }
     *nu2 = a;
     *np2 = b;
 }

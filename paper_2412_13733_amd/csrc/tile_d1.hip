@@ -1,0 +1,11 @@
+// Fused tiled G apply / residual instantiated for d = 1 (see tile_impl.h).
+#include "tile_impl.h"
+
+namespace hpg {
+namespace dev {
+HPG_TILE_INST(double, 1, MODE_APPLY)
+HPG_TILE_INST(double, 1, MODE_RES)
+HPG_TILE_INST(float, 1, MODE_APPLY)
+HPG_TILE_INST(float, 1, MODE_RES)
+}  // namespace dev
+}  // namespace hpg

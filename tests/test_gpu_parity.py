@@ -23,6 +23,13 @@ OP_CASES = [
     (2, 4, 5, [np.array([0, .1, .45, .7, 1.0]), np.array([0, .3, .55, .9, 1.0])]),
     (3, 3, 5, None),
     (3, 5, 2, None),
+    # several tiles with a ragged tail on the dense low-degree path
+    (1, 40, 3, None),
+    (2, 37, 2, None),
+    (2, 19, 3, None),
+    (2, 21, 2, [np.sort(np.r_[0.0, np.random.default_rng(7).uniform(0.02, 0.98, 20), 1.0]),
+                np.linspace(0.0, 1.0, 22) ** 1.3]),
+    (3, 9, 2, None),
 ]
 
 
