@@ -184,70 +184,115 @@ __global__ __launch_bounds__(256) void k_apply_tile(Geo g, URows<T> r0, URows<T>
         ntile[k] = (g.m[k] + TC - 1) / TC;
         ntot *= ntile[k];
     }
-    // workgroups go round-robin to the 8 XCDs: give each XCD a contiguous run of
-    // tiles so that neighbouring tiles share halo lines in the same L2
+    // each block takes a contiguous run of tiles; workgroups go round-robin to
+    // the 8 XCDs, so consecutive runs are given to blocks of the same XCD and
+    // neighbouring tiles share halo lines in one L2
     const int nb = (int)gridDim.x;
     const int xcd = (int)blockIdx.x & 7, slot = (int)blockIdx.x >> 3;
     const int base_q = nb >> 3, base_r = nb & 7;
-    const int first = xcd * base_q + (xcd < base_r ? xcd : base_r) + slot;
-    double part_u = 0.0, part_p = 0.0;
-    for (int tile = first; tile < ntot; tile += nb) {
-        int tt[3] = {0, 0, 0};
-        {
-            int t = tile;
-            for (int k = 0; k < D; ++k) {
-                tt[k] = t % ntile[k];
-                t /= ntile[k];
-            }
+    const int lb = xcd * base_q + (xcd < base_r ? xcd : base_r) + slot;
+    const int per = (ntot + nb - 1) / nb;
+    const int t_begin = lb * per, t_end = min(ntot, t_begin + per);
+    const int tid = (int)threadIdx.x;
+    // origins of a tile: first owned 1-D index o0, box origin x0, first psi cell c0
+    const int gn1[3] = {g.n1[0], g.n1[1], g.n1[2]};
+    const int gm[3] = {g.m[0], g.m[1], g.m[2]};
+    const T* const xu_l = xu;
+    const T* const xpsi_l = xpsi;
+    const T* const xprev_l = xpsi_prev;
+    auto origins = [&](int tile, int* x0, int* o0, int* c0) {
+        int t = tile;
+        for (int k = 0; k < 3; ++k) {
+            const int tk = k < D ? t % ntile[k] : 0;
+            if (k < D) t /= ntile[k];
+            o0[k] = k < D ? tk * OW - 1 : 0;
+            x0[k] = k < D ? o0[k] - PP : 0;
+            c0[k] = k < D ? tk * TC - 1 : 0;
         }
-        int x0[3] = {0, 0, 0}, o0[3] = {0, 0, 0}, c0[3] = {0, 0, 0};
-        for (int k = 0; k < D; ++k) {
-            o0[k] = tt[k] * OW - 1;   // first owned 1-D index
-            x0[k] = o0[k] - PP;       // box origin
-            c0[k] = tt[k] * TC - 1;   // first psi cell (left halo)
+    };
+    // the next tile's x_u box, psi and row windows are loaded into registers
+    // while the current tile computes
+    constexpr int NTH = 256;
+    constexpr int NXR = (C::XS + NTH - 1) / NTH;
+    constexpr int NPR = (C::CS * C::PD + NTH - 1) / NTH;
+    constexpr int NWK = C::DENSE ? (OW * C::WS + NTH - 1) / NTH : 0;   // per direction
+    constexpr int NWR = D * NWK;
+    T xr[NXR], pr[NPR], wr[NWR > 0 ? NWR : 1];
+    const T* const win0 = r0.win;
+    const T* const win1 = r1.win;
+    const T* const win2 = r2.win;
+    auto fetch = [&](int tile) {
+        int fx0[3], fo0[3], fc0[3];
+        origins(tile, fx0, fo0, fc0);
+#pragma unroll
+        for (int r = 0; r < NXR; ++r) {
+            const int e = tid + r * NTH;
+            const int b0 = e % XW, b1 = (e / XW) % XW, b2 = e / (XW * XW);
+            const int g0 = fx0[0] + b0, g1 = fx0[1] + b1, g2 = fx0[2] + b2;
+            bool ok = e < C::XS && g0 >= 0 && g0 < gn1[0];
+            if (D > 1) ok = ok && g1 >= 0 && g1 < gn1[1];
+            if (D > 2) ok = ok && g2 >= 0 && g2 < gn1[2];
+            int64_t flat = g0;
+            if (D > 1) flat += (int64_t)g1 * gn1[0];
+            if (D > 2) flat += (int64_t)g2 * gn1[0] * gn1[1];
+            xr[r] = ok ? xu_l[flat] : (T)0;
         }
-        __syncthreads();   // previous tile done with LDS
-        // ---- stage x_u box
-        for (int e = threadIdx.x; e < C::XS; e += blockDim.x) {
-            int b[3] = {e % XW, (e / XW) % XW, e / (XW * XW)};
-            int64_t flat = 0, st = 1;
-            bool ok = true;
-            for (int k = 0; k < D; ++k) {
-                const int gk = x0[k] + b[k];
-                ok = ok && gk >= 0 && gk < g.n1[k];
-                flat += (int64_t)gk * st;
-                st *= g.n1[k];
-            }
-            X[e] = ok ? xu[flat] : (T)0;
-        }
-        // ---- stage psi (or psi - psi_prev) of cells c0 .. c0 + CW - 1
-        for (int e = threadIdx.x; e < C::CS * C::PD; e += blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < NPR; ++r) {
+            const int e = tid + r * NTH;
             const int cl = e / C::PD, a = e - cl * C::PD;
-            int cc[3] = {cl % CW, (cl / CW) % CW, cl / (CW * CW)};
-            int64_t cell = 0, st = 1;
-            bool ok = true;
-            for (int k = 0; k < D; ++k) {
-                const int ck = c0[k] + cc[k];
-                ok = ok && ck >= 0 && ck < g.m[k];
-                cell += (int64_t)ck * st;
-                st *= g.m[k];
-            }
+            const int k0 = fc0[0] + cl % CW, k1 = fc0[1] + (cl / CW) % CW, k2 = fc0[2] + cl / (CW * CW);
+            bool ok = e < C::CS * C::PD && k0 >= 0 && k0 < gm[0];
+            if (D > 1) ok = ok && k1 >= 0 && k1 < gm[1];
+            if (D > 2) ok = ok && k2 >= 0 && k2 < gm[2];
+            int64_t cell = k0;
+            if (D > 1) cell += (int64_t)k1 * gm[0];
+            if (D > 2) cell += (int64_t)k2 * gm[0] * gm[1];
             T v = 0;
             if (ok) {
-                v = xpsi[cell * C::PD + a];
-                if (MODE == MODE_RES) v -= xpsi_prev[cell * C::PD + a];
+                v = xpsi_l[cell * C::PD + a];
+                if (MODE == MODE_RES) v -= xprev_l[cell * C::PD + a];
             }
-            PS[e] = v;
+            pr[r] = v;
         }
         if constexpr (C::DENSE) {
-            // ---- stage the owned rows' dense windows: one contiguous run per
-            // direction (the global tables carry one zero row in front)
-            for (int e = threadIdx.x; e < D * OW * C::WS; e += blockDim.x) {
-                const int k = e / (OW * C::WS), o = e - k * (OW * C::WS);
-                const URows<T>& R = k == 0 ? r0 : (k == 1 ? r1 : r2);
-                WIN[e] = R.win[(int64_t)(o0[k] + 1) * C::WS + o];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const T* wk = k == 0 ? win0 : (k == 1 ? win1 : win2);
+                const int64_t base = (int64_t)(fo0[k] + 1) * C::WS;
+#pragma unroll
+                for (int r = 0; r < NWK; ++r) {
+                    const int o = tid + r * NTH;
+                    wr[k * NWK + r] = o < OW * C::WS ? wk[base + o] : (T)0;
+                }
             }
-        } else {
+        }
+    };
+    // the low-degree path prefetches; at higher degree the registers are worth
+    // more to occupancy and the staging is synchronous
+    constexpr bool PREFETCH = C::DENSE;
+    double part_u = 0.0, part_p = 0.0;
+    if (PREFETCH && t_begin < t_end) fetch(t_begin);
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        int x0[3], o0[3], c0[3];
+        origins(tile, x0, o0, c0);
+        if (!PREFETCH) fetch(tile);
+        __syncthreads();   // previous tile done with LDS
+#pragma unroll
+        for (int r = 0; r < NXR; ++r)
+            if (tid + r * NTH < C::XS) X[tid + r * NTH] = xr[r];
+#pragma unroll
+        for (int r = 0; r < NPR; ++r)
+            if (tid + r * NTH < C::CS * C::PD) PS[tid + r * NTH] = pr[r];
+        if constexpr (C::DENSE) {
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+#pragma unroll
+                for (int r = 0; r < NWK; ++r)
+                    if (tid + r * NTH < OW * C::WS) WIN[k * OW * C::WS + tid + r * NTH] = wr[k * NWK + r];
+        }
+        if (PREFETCH && tile + 1 < t_end) fetch(tile + 1);
+        if constexpr (!C::DENSE) {
             // ---- stage owned 1-D rows (columns relative to the box / cell origin);
             // the owned rows of a direction are contiguous in the global tables, so
             // one thread per row entry reads them coalesced
@@ -516,7 +561,10 @@ __global__ __launch_bounds__(256) void k_apply_tile(Geo g, URows<T> r0, URows<T>
                 }
                 T pk[C::PD];
 #pragma unroll
-                for (int a = 0; a < C::PD; ++a) pk[a] = xpsi[cell * C::PD + a];
+                for (int a = 0; a < C::PD; ++a)
+                    pk[a] = MODE == MODE_APPLY
+                                ? PS[((D > 1 ? (c_1 + 1) * CW : 0) + c_0 + 1) * C::PD + a]
+                                : xpsi[cell * C::PD + a];
                 // psi_h at the Gauss points, weight, back-projection
                 T dx[C::PD];
 #pragma unroll
@@ -719,9 +767,11 @@ void launch_tile_impl(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T a
                              const double* Phi, T* yu, T* ypsi, double* partial, const int* done,
                              hipStream_t s) {
     constexpr int TC = tile_cells(D, PP);
-    // the apply takes one block per tile; the residual keeps a capped grid so
-    // that its per-block partial sums fit the reduction buffer
-    const unsigned grid = partial ? (unsigned)tile_grid(g) : (unsigned)tile_count(g);
+    // the prefetching path runs persistent blocks over contiguous runs of tiles;
+    // otherwise one block per tile, unless per-block partial sums are written
+    // (their count must fit the reduction buffer)
+    const unsigned grid = (TileCfg<D, PP, TC>::DENSE || partial) ? (unsigned)tile_grid(g)
+                                                                 : (unsigned)tile_count(g);
     hipLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), dim3(grid), dim3(256), 0, s, g,
                        r[0], r[1], r[2], tb, alpha, beta, prm, xu, xpsi, xpsi_prev, omega, F, Phi,
                        yu, ypsi, partial, done);
