@@ -96,6 +96,9 @@ hpg_status hpg_quadrature_points(const hpg_mesh* mesh, double* xyz);
  * (HPG_ERR_NOMEM / HPG_ERR_DEVICE on failure).  The mesh may be destroyed
  * afterwards (the problem keeps its own copy). */
 hpg_status hpg_create_problem(const hpg_mesh* mesh, int device, hpg_problem** out);
+/* Waits for the problem's own streams; work the caller enqueued on its own
+ * streams through hpg_op_* must be complete before this call (the problem's
+ * device buffers are handed to later problems of the process). */
 void hpg_destroy_problem(hpg_problem* prob);
 
 /* f and phi at the n_qp quadrature points (host arrays).  Non-finite values
@@ -187,6 +190,66 @@ hpg_status hpg_l2_diff(hpg_problem* prob, const double* d_a, const double* d_b, 
 hpg_status hpg_set_kernel_timing(hpg_problem* prob, const char* group);
 hpg_status hpg_kernel_time(hpg_problem* prob, const char* group, int64_t* launches,
                            double* total_ms);
+
+/* ---- serving: continuous batching of independent solves on one GPU --------
+ * A request is one whole LVPP solve (the problem statement of Sec. 2 on its
+ * own mesh, degree and constraint).  The server admits requests in arrival
+ * order while both a slot and HBM are free: the sum of the admitted requests'
+ * footprints (hpg_problem_footprint) stays within hbm_budget and at most
+ * max_slots solves run at once.  Each admitted request gets its own device
+ * buffers and HIP streams and runs on its own worker thread, so requests that
+ * arrive while others are on the GPU start as soon as a slot and memory free
+ * up and their kernels overlap on the device.  The result of a request does
+ * not depend on what else runs (every reduction has a fixed order).
+ *
+ * hpg_problem_footprint: upper estimate, in bytes, of the device memory a
+ *   solve on `mesh` at `precision` (HPG_FP64 / HPG_MIXED) allocates.
+ * hpg_server_create: `device` is the HIP device; hbm_budget in bytes (0 = 90%
+ *   of the device's free memory at creation); max_slots >= 1 worker threads.
+ * hpg_server_submit: copies the mesh, f and phi at the mesh's n_qp quadrature
+ *   points (hpg_quadrature_points) and the options; returns a ticket.  The
+ *   caller may free its inputs on return.  HPG_ERR_BUDGET if the request's
+ *   footprint alone exceeds the budget; HPG_ERR_INVALID_ARG for bad input.
+ * hpg_server_poll: HPG_PENDING while the request is queued or running.  Once
+ *   done it writes u_out[n_u], psi_out[n_psi], *stats and *info (each may be
+ *   NULL), releases the ticket and returns the solve's status; a later call
+ *   with the same ticket is HPG_ERR_INVALID_ARG.  A solve that failed returns
+ *   its error status and hpg_last_error() its message.
+ * hpg_server_wait: as poll, blocking until the request is done.
+ * hpg_server_stats: counts, latency percentiles (submission to completion)
+ *   and throughput over the requests completed so far.
+ * hpg_server_destroy: drops queued requests, waits for running ones. */
+typedef struct hpg_server hpg_server;
+
+typedef struct hpg_request_info {
+    double queue_s;           /* submission to admission */
+    double run_s;             /* admission to completion */
+    double latency_s;         /* submission to completion */
+    uint64_t footprint;       /* bytes reserved at admission */
+    uint64_t device_bytes;    /* bytes the solve actually allocated */
+} hpg_request_info;
+
+typedef struct hpg_serving_stats {
+    int64_t submitted, completed, failed, queued, running;
+    int32_t max_running;      /* most solves on the device at once */
+    double p50_latency_s, p99_latency_s, mean_latency_s, max_latency_s;
+    double span_s;            /* first submission to last completion */
+    double solves_per_s;      /* completed / span_s */
+    double dof_krylov_per_s;  /* sum over completed of (n_u + n_psi) * Krylov iterations / span_s */
+    uint64_t hbm_budget, hbm_reserved, hbm_peak_reserved;
+} hpg_serving_stats;
+
+hpg_status hpg_problem_footprint(const hpg_mesh* mesh, int32_t precision, uint64_t* bytes);
+hpg_status hpg_server_create(int device, uint64_t hbm_budget, int32_t max_slots,
+                             hpg_server** out);
+hpg_status hpg_server_submit(hpg_server* srv, const hpg_mesh* mesh, const double* f_qp,
+                             const double* phi_qp, const hpg_solve_opts* opts, uint64_t* ticket);
+hpg_status hpg_server_poll(hpg_server* srv, uint64_t ticket, double* u_out, double* psi_out,
+                           hpg_solve_stats* stats, hpg_request_info* info);
+hpg_status hpg_server_wait(hpg_server* srv, uint64_t ticket, double* u_out, double* psi_out,
+                           hpg_solve_stats* stats, hpg_request_info* info);
+hpg_status hpg_server_stats(hpg_server* srv, hpg_serving_stats* out);
+void hpg_server_destroy(hpg_server* srv);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libhpg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["tables.cpp", "kernels.hip", "tile.hip", "tile_d1.hip", "tile_d2.hip", "tile_d3.hip",
-           "problem.hip", "api.cpp"]
+           "problem.hip", "api.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed-fp32 instructions are disabled for all device code
@@ -40,7 +40,7 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))

@@ -14,25 +14,29 @@ static thread_local std::string g_last_error;
 void set_last_error(const std::string& m) { g_last_error = m; }
 [[noreturn]] void fail(hpg_status code, const std::string& msg) { throw Error{code, msg}; }
 
-template <typename F>
-static hpg_status guarded(F&& fn) {
-    try {
-        return fn();
-    } catch (const Error& e) {
-        set_last_error(e.msg);
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        set_last_error("host allocation failed");
-        return HPG_ERR_NOMEM;
-    } catch (...) {
-        set_last_error("unexpected internal error");
-        return HPG_ERR_DEVICE;
-    }
-}
-
 static void check_problem(hpg_problem* p) {
     if (!p) fail(HPG_ERR_INVALID_ARG, "problem handle is NULL");
     HPG_HIP(hipSetDevice(p->P.device));
+}
+
+hpg_solve_opts checked_opts(const hpg_solve_opts* in) {
+    hpg_solve_opts o;
+    hpg_default_opts(&o);
+    if (in) {
+        if (in->size != (int32_t)sizeof(hpg_solve_opts))
+            fail(HPG_ERR_INVALID_ARG, "hpg_solve_opts.size mismatch");
+        o = *in;
+    }
+    if (!(o.alpha0 > 0) || !(o.alpha_factor >= 1.0) || !(o.alpha_max > 0))
+        fail(HPG_ERR_INVALID_ARG, "alpha schedule must be positive and non-decreasing");
+    if (o.max_prox < 1 || o.max_newton < 1 || o.max_krylov < 1 || o.krylov_chunk < 1)
+        fail(HPG_ERR_INVALID_ARG, "iteration caps must be >= 1");
+    if (!(o.newton_tol > 0) || !(o.krylov_rtol > 0) || !(o.prox_tol >= 0))
+        fail(HPG_ERR_INVALID_ARG, "tolerances must be positive");
+    if (o.precision != HPG_FP64 && o.precision != HPG_MIXED)
+        fail(HPG_ERR_INVALID_ARG, "precision must be HPG_FP64 or HPG_MIXED");
+    if (!(o.beta >= 0)) fail(HPG_ERR_INVALID_ARG, "beta must be >= 0");
+    return o;
 }
 
 }  // namespace hpg
@@ -227,25 +231,6 @@ void hpg_default_opts(hpg_solve_opts* o) {
     o->inexact_newton = 0;
 }
 
-static hpg_solve_opts checked_opts(const hpg_solve_opts* in) {
-    hpg_solve_opts o;
-    hpg_default_opts(&o);
-    if (in) {
-        if (in->size != (int32_t)sizeof(hpg_solve_opts))
-            fail(HPG_ERR_INVALID_ARG, "hpg_solve_opts.size mismatch");
-        o = *in;
-    }
-    if (!(o.alpha0 > 0) || !(o.alpha_factor >= 1.0) || !(o.alpha_max > 0))
-        fail(HPG_ERR_INVALID_ARG, "alpha schedule must be positive and non-decreasing");
-    if (o.max_prox < 1 || o.max_newton < 1 || o.max_krylov < 1 || o.krylov_chunk < 1)
-        fail(HPG_ERR_INVALID_ARG, "iteration caps must be >= 1");
-    if (!(o.newton_tol > 0) || !(o.krylov_rtol > 0) || !(o.prox_tol >= 0))
-        fail(HPG_ERR_INVALID_ARG, "tolerances must be positive");
-    if (o.precision != HPG_FP64 && o.precision != HPG_MIXED)
-        fail(HPG_ERR_INVALID_ARG, "precision must be HPG_FP64 or HPG_MIXED");
-    if (!(o.beta >= 0)) fail(HPG_ERR_INVALID_ARG, "beta must be >= 0");
-    return o;
-}
 
 hpg_status hpg_solve(hpg_problem* prob, const hpg_solve_opts* opts, double* u_out,
                      double* psi_out, double* lam_out, hpg_solve_stats* stats) {

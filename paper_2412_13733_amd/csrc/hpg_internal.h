@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,22 @@ struct Error {
 };
 [[noreturn]] void fail(hpg_status code, const std::string& msg);
 void set_last_error(const std::string& msg);
+// run fn, turning an hpg::Error or an allocation failure into a status code
+template <typename F>
+hpg_status guarded(F&& fn) {
+    try {
+        return fn();
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return HPG_ERR_NOMEM;
+    } catch (...) {
+        set_last_error("unexpected internal error");
+        return HPG_ERR_DEVICE;
+    }
+}
 #define HPG_HIP(call)                                                              \
     do {                                                                           \
         hipError_t e_ = (call);                                                    \

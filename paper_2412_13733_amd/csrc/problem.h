@@ -2,8 +2,10 @@
 #pragma once
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "hpg_internal.h"
@@ -19,10 +21,17 @@ namespace hpg {
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    int device = 0;
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf();
+    // exchange the underlying blocks (pointer, size and device together)
+    void swap(DBuf& o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(device, o.device);
+    }
     void alloc(size_t b);
     template <typename T>
     T* as() const { return reinterpret_cast<T*>(p); }
@@ -147,6 +156,19 @@ struct Problem {
     ~Problem();
 };
 
+}  // namespace hpg
+
+namespace hpg {
+// bytes hipMalloc'ed by DBuf on the calling thread (accounting for the server)
+size_t& device_bytes_counter();
+// serialises the calls that act on the whole device (allocation, synchronous
+// copies, stream/graph creation and destruction) with graph capture, so that
+// problems solved on several host threads never invalidate each other's capture
+std::recursive_mutex& device_api_mutex();
+// device memory of one problem's solve at the given precision (upper estimate)
+size_t footprint_bytes(const Mesh& M, int precision);
+// solve options with defaults filled in and validated (throws Error)
+hpg_solve_opts checked_opts(const hpg_solve_opts* in);
 }  // namespace hpg
 
 struct hpg_problem {

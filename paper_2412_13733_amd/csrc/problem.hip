@@ -17,28 +17,126 @@
 namespace hpg {
 
 // ---------------------------------------------------------------------------
+// Device buffers come from a per-device cache of freed blocks, so problems that
+// are created and destroyed while other solves run (the server) reuse memory
+// without a hipFree between them.  Blocks freed while the cache holds more than
+// a quarter of the device's memory go back to HIP.
+namespace {
+struct BlockCache {
+    std::mutex mu;
+    std::multimap<size_t, void*> blocks;
+    size_t cached = 0, cap = 0;
+};
+BlockCache& block_cache(int device) {
+    static BlockCache caches[64];
+    return caches[device & 63];
+}
+size_t round_block(size_t b) {
+    const size_t small = 256, big = (size_t)2 << 20;
+    return b < ((size_t)1 << 20) ? (b + small - 1) / small * small : (b + big - 1) / big * big;
+}
+}  // namespace
+
+std::recursive_mutex& device_api_mutex() {
+    static std::recursive_mutex m;
+    return m;
+}
+
+size_t& device_bytes_counter() {
+    static thread_local size_t n = 0;
+    return n;
+}
+
+static void release_block(int device, void* p, size_t bytes) {
+    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
+    BlockCache& c = block_cache(device);
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        if (c.cap == 0) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess) c.cap = tot / 4;
+        }
+        if (c.cached + bytes <= c.cap) {
+            c.blocks.emplace(bytes, p);
+            c.cached += bytes;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+
 DBuf::~DBuf() {
-    if (p) (void)hipFree(p);
+    if (p) release_block(device, p, bytes);
 }
 void DBuf::alloc(size_t b) {
     if (p && bytes >= b) return;
+    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
     if (p) {
-        (void)hipFree(p);
+        release_block(device, p, bytes);
         p = nullptr;
     }
     bytes = 0;
     if (b == 0) b = 16;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-        p = nullptr;
-        fail(e == hipErrorOutOfMemory ? HPG_ERR_NOMEM : HPG_ERR_DEVICE,
-             std::string("hipMalloc: ") + hipGetErrorString(e));
+    const size_t rb = round_block(b);
+    int dev = 0;
+    HPG_HIP(hipGetDevice(&dev));
+    BlockCache& c = block_cache(dev);
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.blocks.lower_bound(rb);
+        if (it != c.blocks.end() && it->first <= 2 * rb) {
+            p = it->second;
+            bytes = it->first;
+            c.cached -= it->first;
+            c.blocks.erase(it);
+        }
     }
-    bytes = b;
+    if (!p) {
+        hipError_t e = hipMalloc(&p, rb);
+        if (e != hipSuccess) {
+            p = nullptr;
+            fail(e == hipErrorOutOfMemory ? HPG_ERR_NOMEM : HPG_ERR_DEVICE,
+                 std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        bytes = rb;
+    }
+    device = dev;
+    device_bytes_counter() += bytes;
+}
+
+// Device memory one problem needs for a solve at the given precision: the
+// buffers allocated by build, set_data, the linearisation, the Newton state,
+// the Krylov work vectors and the fast-diagonalisation factors, plus a margin
+// for allocation granularity.
+size_t footprint_bytes(const Mesh& M, int precision) {
+    const double n = (double)(M.n_u + M.n_psi), nu = (double)M.n_u;
+    const double nc = (double)M.n_cells;
+    double b = 0.0;
+    for (int k = 0; k < M.d; ++k) {
+        const double n1 = M.n1[k];
+        b += n1 * 2.0 * (4 + Rows1D::WM * 20.0 + 4 + Rows1D::WB * 20.0);   // sparse rows, 2 precisions
+        b += (n1 + 16.0 * M.p + 3) * (2 * (2 * M.p + 1) + 2 * M.P) * 12.0;    // dense windows
+        b += n1 * n1 * 24.0 + n1 * 12.0;                                       // FDM factors
+        b += M.m[k] * 12.0;
+    }
+    b += 16.0 * n;                        // F, Phi
+    b += 40.0 * n;                        // Newton state: u, psi, psi_prev, ut, pt, u_old, R, delta
+    b += 8.0 * 2 * 4096 * 2;              // partial sums, parameters, Krylov scalars
+    if (precision == HPG_FP64) {
+        b += 8.0 * n;                                                  // Krylov solution
+        b += 8.0 * (7 * n + 2 * nu);                                   // Krylov work vectors
+        b += 8.0 * nc * (double)M.Qd + 8.0 * nc * (double)M.Pd * M.Pd; // weights, psi blocks
+    } else {
+        b += 8.0 * n;                                                  // FP32 rhs and correction
+        b += 4.0 * (7 * n + 2 * nu);
+        b += 4.0 * nc * (double)M.Qd + 4.0 * nc * (double)M.Pd * M.Pd;
+    }
+    return (size_t)(1.15 * b) + ((size_t)8 << 20);
 }
 
 template <typename T>
 static void upload(DBuf& d, const std::vector<T>& h) {
+    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
     d.alloc(h.size() * sizeof(T));
     if (!h.empty()) HPG_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
 }
@@ -117,6 +215,11 @@ void KrylovWork<T>::ensure(int64_t n_, int64_t n_u) {
 }
 
 Problem::~Problem() {
+    // device buffers return to the block cache when the members are destroyed:
+    // the problem's own work must be finished first
+    if (own_stream) (void)hipStreamSynchronize(own_stream);
+    if (side) (void)hipStreamSynchronize(side);
+    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (side) (void)hipStreamDestroy(side);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -259,6 +362,7 @@ static int pick_cpb(int per_cell_elems, int elem_bytes, int work_per_cell, size_
 }
 
 void Problem::build(const Mesh& mesh, int dev_) {
+    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
     M = mesh;
     device = dev_;
     int ndev = 0;
@@ -456,6 +560,7 @@ std::map<std::pair<int, std::vector<double>>, std::shared_ptr<FdmEntry>> g_fdm_c
 }  // namespace
 
 void Problem::ensure_fdm() {
+    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
     if (fdm_ready) return;
     for (int k = 0; k < 3; ++k) {
         std::shared_ptr<FdmEntry> e;
@@ -855,6 +960,7 @@ int Problem::minres_on(const T* b, T* x, double rtol, int maxit, int chunk, hipS
         if (it == graphs.end()) {
             T *vc = vcur, *vp = vprev, *wp = wprev, *wc = wcur;
             hipGraph_t g;
+            std::lock_guard<std::recursive_mutex> api(device_api_mutex());
             HPG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             minres_iterations<T>(chunk, 0, vc, vp, wp, wc, q, Gq, z, x, s);
             HPG_HIP(hipStreamEndCapture(s, &g));
@@ -1068,8 +1174,8 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
         HPG_HIP(hipMemcpyAsync(d_psi_out, dp, M.n_psi * sizeof(double), hipMemcpyDeviceToDevice, s));
     HPG_HIP(hipStreamSynchronize(s));
     // keep the internal buffers pointing at the final iterate
-    if (du != u.as<double>()) std::swap(u.p, ut.p);
-    if (dp != psi.as<double>()) std::swap(psi.p, pt.p);
+    if (du != u.as<double>()) u.swap(ut);
+    if (dp != psi.as<double>()) psi.swap(pt);
     auto t1 = std::chrono::steady_clock::now();
     S.prox_steps = k;
     S.newton_error = last_err;

@@ -58,7 +58,31 @@ EXPORTS = ["hpg_last_error", "hpg_create_mesh", "hpg_destroy_mesh", "hpg_get_mes
            "hpg_set_forcing", "hpg_set_obstacle", "hpg_default_opts", "hpg_solve",
            "hpg_solve_device", "hpg_op_setup", "hpg_op_apply_G", "hpg_op_apply_prec",
            "hpg_op_minres", "hpg_op_residual", "hpg_l2_diff", "hpg_set_kernel_timing",
-           "hpg_kernel_time"]
+           "hpg_kernel_time", "hpg_problem_footprint", "hpg_server_create", "hpg_server_submit",
+           "hpg_server_poll", "hpg_server_wait", "hpg_server_stats", "hpg_server_destroy"]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("queue_s", ctypes.c_double), ("run_s", ctypes.c_double),
+                ("latency_s", ctypes.c_double), ("footprint", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServingStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("max_running", ctypes.c_int32),
+                ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("mean_latency_s", ctypes.c_double), ("max_latency_s", ctypes.c_double),
+                ("span_s", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("dof_krylov_per_s", ctypes.c_double), ("hbm_budget", ctypes.c_uint64),
+                ("hbm_reserved", ctypes.c_uint64), ("hbm_peak_reserved", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 _lib = None
 
@@ -93,6 +117,13 @@ def load():
         "hpg_l2_diff": ([P, P, P, P, P, P], ctypes.c_int),
         "hpg_set_kernel_timing": ([P, ctypes.c_char_p], ctypes.c_int),
         "hpg_kernel_time": ([P, ctypes.c_char_p, P, P], ctypes.c_int),
+        "hpg_problem_footprint": ([P, I32, P], ctypes.c_int),
+        "hpg_server_create": ([ctypes.c_int, ctypes.c_uint64, I32, P], ctypes.c_int),
+        "hpg_server_submit": ([P, P, P, P, P, P], ctypes.c_int),
+        "hpg_server_poll": ([P, ctypes.c_uint64, P, P, P, P], ctypes.c_int),
+        "hpg_server_wait": ([P, ctypes.c_uint64, P, P, P, P], ctypes.c_int),
+        "hpg_server_stats": ([P, P], ctypes.c_int),
+        "hpg_server_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -152,6 +183,12 @@ class Mesh:
         self.info = inf
         self.dim, self.p, self.q, self.P = inf.dim, inf.p, inf.q, inf.P
         self.n_u, self.n_psi, self.n_qp, self.n_cells = inf.n_u, inf.n_psi, inf.n_qp, inf.n_cells
+
+    def footprint(self, precision=FP64):
+        """Upper estimate of the device bytes one solve on this mesh allocates."""
+        b = ctypes.c_uint64(0)
+        _check(load().hpg_problem_footprint(self.h, precision, ctypes.byref(b)))
+        return b.value
 
     def quadrature_points(self):
         x = np.zeros((self.n_qp, self.dim))
@@ -244,3 +281,59 @@ class Problem:
         if getattr(self, "h", None) and _lib is not None:
             _lib.hpg_destroy_problem(self.h)
             self.h = None
+
+
+class Server:
+    """Continuous batching of independent solves on one device (hpg_server_*)."""
+
+    def __init__(self, device=0, hbm_budget=0, max_slots=4):
+        h = ctypes.c_void_p()
+        _check(load().hpg_server_create(device, int(hbm_budget), max_slots, ctypes.byref(h)))
+        self.h = h
+        self._sizes = {}
+
+    def submit(self, mesh, f_qp, phi_qp, opts=None):
+        f = np.ascontiguousarray(f_qp, dtype=np.float64).reshape(-1)
+        ph = np.ascontiguousarray(phi_qp, dtype=np.float64).reshape(-1)
+        if f.size != mesh.n_qp or ph.size != mesh.n_qp:
+            raise ValueError("f and phi must be given at the mesh's n_qp quadrature points")
+        t = ctypes.c_uint64(0)
+        o = opts if opts is not None else default_opts()
+        _check(load().hpg_server_submit(self.h, mesh.h, _dptr(f), _dptr(ph), ctypes.byref(o),
+                                        ctypes.byref(t)))
+        self._sizes[t.value] = (mesh.n_u, mesh.n_psi)
+        return t.value
+
+    def _result(self, fn, ticket):
+        sizes = self._sizes.get(ticket)
+        u = np.zeros(sizes[0]) if sizes else None
+        psi = np.zeros(sizes[1]) if sizes else None
+        st = SolveStats()
+        info = RequestInfo()
+        rc = fn(self.h, ticket, _dptr(u) if sizes else None, _dptr(psi) if sizes else None,
+                ctypes.byref(st), ctypes.byref(info))
+        if rc == PENDING:
+            return None
+        self._sizes.pop(ticket, None)
+        _check(rc, allow=(OK, NOT_CONVERGED))
+        return u, psi, st, info
+
+    def poll(self, ticket):
+        """None while pending, else (u, psi, SolveStats, RequestInfo)."""
+        return self._result(load().hpg_server_poll, ticket)
+
+    def wait(self, ticket):
+        return self._result(load().hpg_server_wait, ticket)
+
+    def stats(self):
+        s = ServingStats()
+        _check(load().hpg_server_stats(self.h, ctypes.byref(s)))
+        return s
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,124 @@
+"""Serving (hpg_server_*): continuous batching of independent solves.
+
+Each request's result must be the same alone (hpg_solve on its own problem)
+and in the mix (submitted with others while they run): every reduction in the
+library has a fixed order, so the comparison is exact.  Also checked: several
+requests ran at once, admission keeps the reserved HBM within the budget, the
+footprint estimate bounds what a solve allocates, and served results match the
+oracle on small cases."""
+import numpy as np
+import pytest
+
+from oracle import lvpp
+import workloads as W
+
+from gpu_common import build_pair, log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _request(i):
+    """A small mixed request list: 1-D / 2-D, degrees 2..6, both precisions."""
+    rng = np.random.default_rng(500 + i)
+    dim = 1 if i % 4 == 0 else 2
+    n = int(rng.integers(6, 17)) if dim == 1 else int(rng.integers(4, 11))
+    p = int(rng.integers(2, 7))
+    prec = i % 2
+    return dim, n, p, prec
+
+
+def _mesh_data(hpg, dim, n, p, seed):
+    mesh = hpg.Mesh(dim, [n] * dim, p)
+    x = mesh.quadrature_points()
+    f, phi = W.w1d() if dim == 1 else W.w2d(seed)
+    return mesh, f(x), phi(x)
+
+
+def _opts(hpg, prec):
+    if prec == hpg.FP64:
+        return hpg.default_opts(fixed_prox_steps=6)
+    return hpg.default_opts(fixed_prox_steps=6, precision=hpg.MIXED, newton_tol=1e-10,
+                            krylov_rtol=1e-6)
+
+
+def test_serving_results_equal_alone_and_in_mix():
+    from paper_2412_13733_amd import hpg
+    reqs = [_request(i) for i in range(12)]
+    alone = []
+    for i, (dim, n, p, prec) in enumerate(reqs):
+        log("alone", i, dim, n, p, prec)
+        mesh, f, phi = _mesh_data(hpg, dim, n, p, i)
+        prob = hpg.Problem(mesh)
+        prob.set_forcing(f)
+        prob.set_obstacle(phi)
+        u, psi, _, st = prob.solve(_opts(hpg, prec))
+        alone.append((u, psi, st.krylov_iters))
+        del prob
+    srv = hpg.Server(device=0, max_slots=4)
+    tickets = []
+    for i, (dim, n, p, prec) in enumerate(reqs):
+        mesh, f, phi = _mesh_data(hpg, dim, n, p, i)
+        tickets.append((srv.submit(mesh, f, phi, _opts(hpg, prec)), mesh.footprint(prec)))
+    log("submitted", len(tickets))
+    for i, (t, fp) in enumerate(tickets):
+        u, psi, st, info = srv.wait(t)
+        ua, psia, ka = alone[i]
+        log("mix", i, reqs[i], "krylov", st.krylov_iters, ka, info.as_dict())
+        assert st.status == 0
+        assert np.array_equal(u, ua)
+        assert np.array_equal(psi, psia)
+        assert st.krylov_iters == ka
+        assert info.footprint == fp
+        assert 0 < info.device_bytes <= info.footprint
+        assert info.latency_s >= info.run_s > 0
+    s = srv.stats()
+    log("stats", s.as_dict())
+    assert s.completed == len(reqs) and s.failed == 0
+    assert s.max_running > 1            # requests overlapped on the device
+    assert s.p99_latency_s >= s.p50_latency_s > 0
+    assert s.solves_per_s > 0 and s.dof_krylov_per_s > 0
+    with pytest.raises(hpg.HpgError):   # a retrieved ticket is released
+        srv.poll(tickets[0][0])
+    srv.close()
+
+
+def test_serving_admission_respects_budget():
+    from paper_2412_13733_amd import hpg
+    sizes = [(2, 8, 4), (2, 10, 5), (2, 6, 6), (2, 9, 3), (2, 7, 4), (2, 10, 2)]
+    meshes = [_mesh_data(hpg, d, n, p, k) for k, (d, n, p) in enumerate(sizes)]
+    fps = [m.footprint(hpg.FP64) for m, _, _ in meshes]
+    budget = int(max(fps) * 1.5)        # room for one large request at a time
+    srv = hpg.Server(device=0, hbm_budget=budget, max_slots=4)
+    ts = [srv.submit(m, f, phi, _opts(hpg, hpg.FP64)) for m, f, phi in meshes]
+    for t in ts:
+        u, psi, st, info = srv.wait(t)
+        assert st.status == 0
+    s = srv.stats()
+    log("budget", budget, "peak reserved", s.hbm_peak_reserved, "max running", s.max_running)
+    assert s.hbm_peak_reserved <= budget
+    assert s.hbm_budget == budget
+    # a request larger than the whole budget is refused at submission
+    big, fb, pb = _mesh_data(hpg, 2, 40, 8, 0)
+    assert big.footprint(hpg.FP64) > budget
+    with pytest.raises(hpg.HpgError) as e:
+        srv.submit(big, fb, pb, _opts(hpg, hpg.FP64))
+    assert e.value.status == hpg.ERR_BUDGET
+    srv.close()
+
+
+@pytest.mark.parametrize("dim,m,p", [(1, 16, 4), (2, 6, 4)])
+def test_served_result_matches_oracle(dim, m, p):
+    from paper_2412_13733_amd import hpg
+    data = W.w1d() if dim == 1 else W.w2d(0)
+    mesh, prob, sysm = build_pair(dim, m, p, data)
+    ro = lvpp.solve(sysm, lvpp.Options())
+    x = mesh.quadrature_points()
+    srv = hpg.Server(device=0, max_slots=2)
+    t = srv.submit(mesh, data[0](x), data[1](x), hpg.default_opts(fixed_prox_steps=ro.prox_steps))
+    u, psi, st, info = srv.wait(t)
+    eu = sysm.l2_norm_u(u - ro.u) / sysm.l2_norm_u(ro.u)
+    log("served vs oracle", dim, m, p, "rel L2", eu)
+    assert st.status == 0 and eu < 1e-10
+    srv.close()

@@ -65,3 +65,18 @@ def test_invalid_arguments_are_rejected():
         hpg.Mesh(1, [2], 3, breaks=[np.array([0.0, 0.5, 2.0])])   # must end at 1
     m = hpg.Mesh(1, [3], 2, constraint=hpg.GRADIENT)
     assert m.P == 2 and m.n_psi == 3 * 2
+
+
+def test_footprint_estimate_is_host_only_and_monotone():
+    from paper_2412_13733_amd import hpg
+    small = hpg.Mesh(2, [8, 8], 4)
+    big = hpg.Mesh(2, [32, 32], 4)
+    hi_p = hpg.Mesh(2, [8, 8], 8)
+    f64, f32 = small.footprint(hpg.FP64), small.footprint(hpg.MIXED)
+    assert 0 < f32 < f64
+    assert big.footprint(hpg.FP64) > f64
+    assert hi_p.footprint(hpg.FP64) > f64
+    # at least the FP64 Newton state and Krylov vectors
+    assert f64 > 8 * 15 * (small.n_u + small.n_psi)
+    with pytest.raises(hpg.HpgError):
+        small.footprint(7)
