@@ -1,0 +1,240 @@
+// Device helpers shared by the kernels of the hpG library: block reductions,
+// register copies of the sparse 1-D rows, and the sum-factorised per-cell
+// contractions staged in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace hpg {
+namespace dev {
+
+// ---------------------------------------------------------------------------
+// block reduction of a double (fixed order: wave shuffle tree, then waves in order)
+__device__ inline double block_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += red[i];
+    }
+    return s;   // valid in thread 0
+}
+
+// register copies of one sparse 1-D row (stiffness/mass, and psi coupling)
+template <typename T, int W>
+struct Row {
+    int n;
+    int c[W];
+    T a[W], m[W];
+    __device__ inline void load(const URows<T>& r, int g) {
+        n = r.lenM[g];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const bool ok = e < n;
+            c[e] = ok ? r.colM[g * W + e] : 0;
+            a[e] = ok ? r.aM[g * W + e] : (T)0;
+            m[e] = ok ? r.mM[g * W + e] : (T)0;
+        }
+    }
+};
+template <typename T, int W>
+struct BRow {
+    int n;
+    int cell[W], mode[W];
+    T v[W];
+    __device__ inline void load(const URows<T>& r, int g) {
+        n = r.lenB[g];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const bool ok = e < n;
+            cell[e] = ok ? r.cellB[g * W + e] : 0;
+            mode[e] = ok ? r.modeB[g * W + e] : 0;
+            v[e] = ok ? r.vB[g * W + e] : (T)0;
+        }
+    }
+    // the (v', zeta) coupling rows of the gradient constraint
+    __device__ inline void loadG(const URows<T>& r, int g) {
+        n = r.lenG[g];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const bool ok = e < n;
+            cell[e] = ok ? r.cellG[g * W + e] : 0;
+            mode[e] = ok ? r.modeG[g * W + e] : 0;
+            v[e] = ok ? r.vG[g * W + e] : (T)0;
+        }
+    }
+};
+
+// (A_0 M_1 M_2 + M_0 A_1 M_2 + M_0 M_1 A_2) x_u at the global unknown with
+// 1-D indices gi: tensor products of the sparse 1-D rows held in registers
+template <typename T, int D>
+__device__ inline T stiff_mass_sum(const Geo& g, const URows<T>& r0, const URows<T>& r1,
+                                   const URows<T>& r2, const int gi[3], const T* __restrict__ xu) {
+    constexpr int W = URows<T>::WM;
+    Row<T, W> R0;
+    R0.load(r0, gi[0]);
+    T acc = 0;
+    if (D == 1) {
+#pragma unroll
+        for (int e0 = 0; e0 < W; ++e0)
+            if (e0 < R0.n) acc += R0.a[e0] * xu[R0.c[e0]];
+    } else if (D == 2) {
+        Row<T, W> R1;
+        R1.load(r1, gi[1]);
+#pragma unroll
+        for (int e1 = 0; e1 < W; ++e1) {
+            if (e1 < R1.n) {
+                const T* row = xu + (int64_t)R1.c[e1] * g.n1[0];
+                const T m1 = R1.m[e1], a1 = R1.a[e1];
+#pragma unroll
+                for (int e0 = 0; e0 < W; ++e0)
+                    if (e0 < R0.n) acc += (R0.a[e0] * m1 + R0.m[e0] * a1) * row[R0.c[e0]];
+            }
+        }
+    } else {
+        Row<T, W> R1, R2;
+        R1.load(r1, gi[1]);
+        R2.load(r2, gi[2]);
+#pragma unroll
+        for (int e2 = 0; e2 < W; ++e2) {
+            if (e2 >= R2.n) continue;
+#pragma unroll
+            for (int e1 = 0; e1 < W; ++e1) {
+                if (e1 >= R1.n) continue;
+                const T* row = xu + ((int64_t)R2.c[e2] * g.n1[1] + R1.c[e1]) * g.n1[0];
+                const T am = R1.a[e1] * R2.m[e2] + R1.m[e1] * R2.a[e2];
+                const T mm = R1.m[e1] * R2.m[e2];
+#pragma unroll
+                for (int e0 = 0; e0 < W; ++e0)
+                    if (e0 < R0.n) acc += (R0.a[e0] * mm + R0.m[e0] * am) * row[R0.c[e0]];
+            }
+        }
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// sum-factorised contraction along one axis of a batch of cell tensors in LDS:
+// out[.., i, ..] = sum_j mat(i, j) in[.., j, ..], mat(i, j) = mat[i*ld + j] or
+// mat[j*ld + i] (trans).  din: input dims (direction 0 fastest).
+template <typename T>
+__device__ inline void contract_axis(const T* in, T* out, int stride, int ncell, int ax,
+                                     const int din[3], int nout, const T* mat, int ld,
+                                     bool trans) {
+    int dout[3] = {din[0], din[1], din[2]};
+    dout[ax] = nout;
+    const int tot = dout[0] * dout[1] * dout[2];
+    const int nin = din[ax];
+    const int sax = (ax == 0) ? 1 : (ax == 1 ? din[0] : din[0] * din[1]);
+    for (int e = threadIdx.x; e < ncell * tot; e += blockDim.x) {
+        const int c = e / tot, o = e - c * tot;
+        int idx[3];
+        idx[0] = o % dout[0];
+        const int r = o / dout[0];
+        idx[1] = r % dout[1];
+        idx[2] = r / dout[1];
+        const int iout = idx[ax];
+        idx[ax] = 0;
+        const T* src = in + c * stride + idx[0] + din[0] * (idx[1] + din[1] * idx[2]);
+        T acc = 0;
+        if (trans)
+            for (int j = 0; j < nin; ++j) acc += mat[j * ld + iout] * src[j * sax];
+        else
+            for (int j = 0; j < nin; ++j) acc += mat[iout * ld + j] * src[j * sax];
+        out[c * stride + o] = acc;
+    }
+}
+
+// apply the same matrix along every axis 0..D-1: buffers ping-pong between
+// a and b; returns the buffer holding the result
+template <typename T, int D>
+__device__ inline T* contract_all(T* a, T* b, int stride, int ncell, int nin, int nout,
+                                  const T* mat, int ld, bool trans) {
+    int dims[3] = {1, 1, 1};
+    for (int k = 0; k < D; ++k) dims[k] = nin;
+    T* src = a;
+    T* dst = b;
+    for (int k = 0; k < D; ++k) {
+        contract_axis<T>(src, dst, stride, ncell, k, dims, nout, mat, ld, trans);
+        __syncthreads();
+        dims[k] = nout;
+        T* t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
+// a different matrix along each axis k (mats[k], all nin -> nout, leading
+// dimension ld); returns the buffer holding the result
+template <typename T, int D>
+__device__ inline T* contract_axes(T* a, T* b, int stride, int ncell, int nin, int nout,
+                                   const T* const* mats, int ld, bool trans) {
+    int dims[3] = {1, 1, 1};
+    for (int k = 0; k < D; ++k) dims[k] = nin;
+    T* src = a;
+    T* dst = b;
+    for (int k = 0; k < D; ++k) {
+        contract_axis<T>(src, dst, stride, ncell, k, dims, nout, mats[k], ld, trans);
+        __syncthreads();
+        dims[k] = nout;
+        T* t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
+// gather the (p+1)^D local u coefficients of the block's cells into LDS
+template <typename T, int D>
+__device__ inline void gather_u(const Geo& g, const T* __restrict__ xu, T* buf, int stride,
+                                int64_t cell0, int ncell) {
+    const int L = g.p + 1;
+    const int Ld = g.Ld;
+    for (int e = threadIdx.x; e < ncell * Ld; e += blockDim.x) {
+        const int ci = e / Ld, l = e - ci * Ld;
+        int64_t cell = cell0 + ci;
+        int cc[3] = {0, 0, 0};
+        cc[0] = (int)(cell % g.m[0]);
+        cell /= g.m[0];
+        if (D >= 2) {
+            cc[1] = (int)(cell % g.m[1]);
+            cell /= g.m[1];
+        }
+        if (D >= 3) cc[2] = (int)cell;
+        int ll[3] = {l % L, (l / L) % L, l / (L * L)};
+        int64_t flat = 0, stridek = 1;
+        bool ok = true;
+        for (int k = 0; k < D; ++k) {
+            const int gk = cc[k] * g.p + ll[k] - 1;
+            ok = ok && gk >= 0 && gk < g.n1[k];
+            flat += (int64_t)gk * stridek;
+            stridek *= g.n1[k];
+        }
+        buf[ci * stride + l] = ok ? xu[flat] : (T)0;
+    }
+}
+
+template <typename T, int D>
+__device__ inline T cell_jac(const Geo& g, const T* const* hw, int64_t cell, T* hk) {
+    T J = 1;
+    int64_t c = cell;
+    for (int k = 0; k < D; ++k) {
+        const int ck = (int)(c % g.m[k]);
+        c /= g.m[k];
+        hk[k] = hw[k][ck];
+        J *= (T)0.5 * hk[k];
+    }
+    return J;
+}
+
+}  // namespace dev
+}  // namespace hpg

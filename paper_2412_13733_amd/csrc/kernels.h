@@ -18,7 +18,8 @@ struct Geo {
     int n1[3];
     int64_t n_u, n_psi, n_cells;
     int Pd, Qd, Ld;
-    int S;   // per-cell LDS stride: max(p+1, q)^d
+    int S;    // per-cell LDS stride: max(p+1, q)^d
+    int nc;   // psi components per cell: 1 (obstacle) or d (gradient)
 };
 
 // sparse global 1-D rows of one direction (see Rows1D on the host)
@@ -37,6 +38,11 @@ struct URows {
     // the tail are zero): stiffness and mass at columns g - p .. g + p, then the
     // psi coupling of cells g / p and g / p + 1 (P modes each)
     const T* win;
+    // gradient constraint: rows of (v', zeta) in this direction (<= WB entries)
+    const int32_t* lenG;
+    const int32_t* cellG;
+    const int32_t* modeG;
+    const T* vG;
 };
 
 // 1-D reference tables and cell widths
@@ -48,6 +54,9 @@ struct PsiTabs {
     const T* w;      // q
     const T* Mdiag;  // P: 2/(2a+1)
     const T* h[3];   // cell widths per direction
+    const T* G1;     // (p+1) x P: (phi_l', P_a) on [-1, 1] (gradient)
+    const T* AY;     // P x P: (Y_a', Y_b') on [-1, 1] (gradient E_beta)
+    const T* MY;     // P x P: (Y_a, Y_b) on [-1, 1]
 };
 
 // MINRES scalar state (device)
@@ -128,6 +137,32 @@ void launch_lambda(int64_t n, const double* psi_prev, const double* psi, double 
                    double* lam, hipStream_t s);
 void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u, const double* v,
                double* partial, hipStream_t s);
+
+// ---- gradient constraint |grad u| <= phi (gradient.hip) ---------------------
+// omega layout: [cell][pair (c <= l, row-major upper triangle)][q^d] of the
+// symmetric d x d weights w_q |J| phi_q F(psi_h(x_q)).
+template <typename T>
+void launch_u_side_grad(const Geo& g, const URows<T>* r, T alpha, const T* xu, const T* xb,
+                        const T* xb_prev, const double* F, T* yu, double* partial,
+                        const int* done, int mode, hipStream_t s, const double* prm);
+template <typename T>
+int psi_side_grad_cpb(const Geo& g);
+template <typename T>
+void launch_psi_side_grad(const Geo& g, const PsiTabs<T>& tb, int cpb, T beta, const T* xu,
+                          const T* xpsi, const T* omega, const double* phi_q, T* ypsi,
+                          double* partial, const int* done, int mode, hipStream_t s,
+                          const double* prm);
+// Newton-step setup: omega and the inverses of -S_hat_K = D_K + beta E_K
+// (n = d P^d); blocks that do not fit in LDS are inverted in place in sinv64
+bool setup_grad_in_hbm(const Geo& g);
+void launch_setup_grad(const Geo& g, const PsiTabs<double>& tb, const double* psi,
+                       const double* phi_q, double beta, double* om64, float* om32, double* s64,
+                       float* s32, hipStream_t s);
+// psi-block preconditioner for blocks too large to stage in LDS: one block of
+// threads per cell streams the symmetric inverse row by row
+template <typename T>
+void launch_prec_psi_big(int64_t n_cells, int n, const T* sinv, const T* r, T* z,
+                         double* partial, int nblocks, const int* done, hipStream_t s);
 
 }  // namespace dev
 }  // namespace hpg

@@ -39,13 +39,13 @@ struct DBuf {
 
 template <typename T>
 struct DevRows {
-    DBuf lenM, colM, aM, mM, lenB, cellB, modeB, vB, win;
+    DBuf lenM, colM, aM, mM, lenB, cellB, modeB, vB, win, lenG, cellG, modeG, vG;
     dev::URows<T> view() const;
 };
 
 template <typename T>
 struct DevTabs {
-    DBuf B1, Vpsi, Vu, w, Mdiag, h[3];
+    DBuf B1, Vpsi, Vu, w, Mdiag, h[3], G1, AY, MY;
     dev::PsiTabs<T> view() const;
 };
 
@@ -101,6 +101,9 @@ struct Problem {
     std::vector<double> f_qp, phi_qp;
     bool have_f = false, have_phi = false;
     DBuf F, Phi;
+    DBuf PhiQ;                             // gradient: phi at the Gauss points (FP64)
+    bool gradient = false;                 // constraint |grad u| <= phi
+    bool prec_big = false;                 // psi blocks streamed from HBM (too large for LDS)
     double normF = 1.0, normPhi = 1.0;
     // linearisation (hpg_op_setup / Newton setup)
     double alpha = 1.0, beta = 0.0;

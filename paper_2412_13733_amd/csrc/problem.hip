@@ -122,14 +122,18 @@ size_t footprint_bytes(const Mesh& M, int precision) {
     b += 16.0 * n;                        // F, Phi
     b += 40.0 * n;                        // Newton state: u, psi, psi_prev, ut, pt, u_old, R, delta
     b += 8.0 * 2 * 4096 * 2;              // partial sums, parameters, Krylov scalars
+    const double npair = M.ncomp * (M.ncomp + 1) / 2.0;
+    const double blk = (double)M.psi_per_cell * (double)M.psi_per_cell;
+    if (M.kind == HPG_GRADIENT) b += 8.0 * nc * (double)M.Qd;        // phi at the Gauss points
     if (precision == HPG_FP64) {
         b += 8.0 * n;                                                  // Krylov solution
         b += 8.0 * (7 * n + 2 * nu);                                   // Krylov work vectors
-        b += 8.0 * nc * (double)M.Qd + 8.0 * nc * (double)M.Pd * M.Pd; // weights, psi blocks
+        b += 8.0 * nc * (double)M.Qd * npair + 8.0 * nc * blk;         // weights, psi blocks
     } else {
         b += 8.0 * n;                                                  // FP32 rhs and correction
         b += 4.0 * (7 * n + 2 * nu);
-        b += 4.0 * nc * (double)M.Qd + 4.0 * nc * (double)M.Pd * M.Pd;
+        b += 4.0 * nc * (double)M.Qd * npair + 4.0 * nc * blk;
+        if (M.kind == HPG_GRADIENT) b += 8.0 * nc * blk;               // FP64 blocks formed in HBM
     }
     return (size_t)(1.15 * b) + ((size_t)8 << 20);
 }
@@ -184,6 +188,10 @@ dev::URows<T> DevRows<T>::view() const {
     r.modeB = modeB.as<int32_t>();
     r.vB = vB.as<T>();
     r.win = win.as<T>();
+    r.lenG = lenG.as<int32_t>();
+    r.cellG = cellG.as<int32_t>();
+    r.modeG = modeG.as<int32_t>();
+    r.vG = vG.as<T>();
     return r;
 }
 template <typename T>
@@ -195,6 +203,9 @@ dev::PsiTabs<T> DevTabs<T>::view() const {
     t.w = w.as<T>();
     t.Mdiag = Mdiag.as<T>();
     for (int k = 0; k < 3; ++k) t.h[k] = h[k].as<T>();
+    t.G1 = G1.as<T>();
+    t.AY = AY.as<T>();
+    t.MY = MY.as<T>();
     return t;
 }
 
@@ -380,8 +391,7 @@ void Problem::build(const Mesh& mesh, int dev_) {
         HPG_HIP(hipGetDeviceProperties(&prop, device));
         lds_max = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
     }
-    if (M.kind != HPG_OBSTACLE)
-        fail(HPG_ERR_INVALID_ARG, "the GPU path implements the obstacle constraint");
+    gradient = M.kind == HPG_GRADIENT;
     // geometry
     geo.d = M.d;
     geo.p = M.p;
@@ -400,20 +410,31 @@ void Problem::build(const Mesh& mesh, int dev_) {
     int sb = std::max(M.p + 1, M.q), S = 1;
     for (int k = 0; k < M.d; ++k) S *= sb;
     geo.S = S;
+    geo.nc = M.ncomp;
     // per-kernel cells per block
     if ((size_t)5 * S * 8 > lds_max || (size_t)4 * S * 8 > lds_max)
         fail(HPG_ERR_INVALID_ARG, "(p+1)^d too large for the LDS-staged cell kernels");
-    cpb_psi = pick_cpb(5 * S, 8, geo.Qd, std::min<size_t>(48 * 1024, lds_max));
     cpb_l2 = pick_cpb(4 * S, 8, geo.Qd, std::min<size_t>(48 * 1024, lds_max));
-    const size_t setup_cell = dev::setup_smem_per_cell(geo);
-    if (setup_cell > lds_max)
-        fail(HPG_ERR_INVALID_ARG, "P^d too large for the in-LDS Schur block inverse");
-    cpb_setup = std::max(1, std::min(256 / std::max(1, geo.Pd), (int)(lds_max / setup_cell)));
-    while (cpb_setup > 1 && setup_cell * cpb_setup > std::min<size_t>(64 * 1024, lds_max)) --cpb_setup;
-    // psi-block preconditioner: ~16 KB of inverse blocks per block of 256 threads
-    cpb_prec = std::max(1, (int)(2048 / std::max<int64_t>(1, M.Pd * M.Pd)));
-    while (cpb_prec > 1 && (size_t)cpb_prec * (M.Pd * M.Pd + M.Pd) * 8 > 48 * 1024) --cpb_prec;
-    if ((size_t)(M.Pd * M.Pd + M.Pd) * 8 > lds_max)
+    const int64_t nblk = M.psi_per_cell;   // psi block per cell: ncomp P^d
+    if (gradient) {
+        cpb_psi = dev::psi_side_grad_cpb<double>(geo);
+        if ((size_t)(1 + 3 * M.d + 3) * S * 8 > std::min<size_t>(48 * 1024, lds_max))
+            fail(HPG_ERR_INVALID_ARG, "(p+1)^d too large for the gradient psi-side kernel");
+    } else {
+        cpb_psi = pick_cpb(5 * S, 8, geo.Qd, std::min<size_t>(48 * 1024, lds_max));
+        const size_t setup_cell = dev::setup_smem_per_cell(geo);
+        if (setup_cell > lds_max)
+            fail(HPG_ERR_INVALID_ARG, "P^d too large for the in-LDS Schur block inverse");
+        cpb_setup = std::max(1, std::min(256 / std::max(1, geo.Pd), (int)(lds_max / setup_cell)));
+        while (cpb_setup > 1 && setup_cell * cpb_setup > std::min<size_t>(64 * 1024, lds_max))
+            --cpb_setup;
+    }
+    // psi-block preconditioner: ~16 KB of inverse blocks per block of 256
+    // threads; blocks beyond 48 KB are streamed from HBM one cell per block
+    prec_big = (size_t)(nblk * nblk + nblk) * 8 > 48 * 1024;
+    cpb_prec = std::max(1, (int)(2048 / std::max<int64_t>(1, nblk * nblk)));
+    while (cpb_prec > 1 && (size_t)cpb_prec * (nblk * nblk + nblk) * 8 > 48 * 1024) --cpb_prec;
+    if (prec_big && !gradient)
         fail(HPG_ERR_INVALID_ARG, "P^d too large for the LDS-staged preconditioner blocks");
     // 1-D rows per direction
     for (int k = 0; k < 3; ++k) {
@@ -451,6 +472,24 @@ void Problem::build(const Mesh& mesh, int dev_) {
         upload(rows32[k].cellB, cellB);
         upload(rows32[k].modeB, modeB);
         upload(rows32[k].vB, cast<float>(R.vB));
+        if (R.lenG.empty()) {
+            R.lenG.assign(R.n, 0);
+            R.colG.assign((size_t)R.n * Rows1D::WB, 0);
+            R.vG.assign((size_t)R.n * Rows1D::WB, 0.0);
+        }
+        std::vector<int32_t> cellG(R.colG.size()), modeG(R.colG.size());
+        for (size_t i = 0; i < R.colG.size(); ++i) {
+            cellG[i] = R.colG[i] / std::max(1, M.P);
+            modeG[i] = R.colG[i] % std::max(1, M.P);
+        }
+        upload(rows64[k].lenG, R.lenG);
+        upload(rows64[k].cellG, cellG);
+        upload(rows64[k].modeG, modeG);
+        upload(rows64[k].vG, R.vG);
+        upload(rows32[k].lenG, R.lenG);
+        upload(rows32[k].cellG, cellG);
+        upload(rows32[k].modeG, modeG);
+        upload(rows32[k].vG, cast<float>(R.vG));
         const std::vector<double> win = dense_windows(M, R);
         upload(rows64[k].win, win);
         upload(rows32[k].win, cast<float>(win));
@@ -467,6 +506,12 @@ void Problem::build(const Mesh& mesh, int dev_) {
     upload(tab32.Vu, cast<float>(T.Vu));
     upload(tab32.w, cast<float>(T.w));
     upload(tab32.Mdiag, cast<float>(T.MpsiDiag));
+    upload(tab64.G1, T.G1);
+    upload(tab64.AY, T.AY);
+    upload(tab64.MY, T.MY);
+    upload(tab32.G1, cast<float>(T.G1));
+    upload(tab32.AY, cast<float>(T.AY));
+    upload(tab32.MY, cast<float>(T.MY));
     for (int k = 0; k < 3; ++k) {
         std::vector<double> hv;
         if (k < M.d)
@@ -503,7 +548,7 @@ void Problem::build(const Mesh& mesh, int dev_) {
     }
     const int nw0 = (int)wval[0].size(), nw1 = (int)wval[1].size(), nw2 = (int)wval[2].size();
     std::vector<double> Call;
-    for (int i2 = 0; i2 < nw2; ++i2)
+    for (int i2 = 0; i2 < (gradient ? 0 : nw2); ++i2)
         for (int i1 = 0; i1 < nw1; ++i1)
             for (int i0 = 0; i0 < nw0; ++i0) {
                 const double hk[3] = {wval[0][i0], wval[1][i1], wval[2][i2]};
@@ -520,6 +565,7 @@ void Problem::build(const Mesh& mesh, int dev_) {
         }
         cc[c] = ci[0] + nw0 * (ci[1] + nw1 * ci[2]);
     }
+    if (Call.empty()) Call.assign(1, 0.0);   // the gradient preconditioner has no C_K term
     upload(C, Call);
     upload(cclass, cc);
     // reduction scratch
@@ -666,8 +712,11 @@ void Problem::set_data(const double* f, const double* phi) {
             for (int k = 0; k < d; ++k) din[k] = q;
             std::vector<double> cur = vals;
             for (int k = 0; k < d; ++k) cur = hcontract(cur, d, din, k, P, T.Vpsi, P, true);
-            for (int64_t a = 0; a < M.Pd; ++a) Ph[c * M.Pd + a] = cur[a];
+            // gradient: Phi (the scale of the psi residual) repeats per component
+            for (int comp = 0; comp < M.ncomp; ++comp)
+                for (int64_t a = 0; a < M.Pd; ++a) Ph[(c * M.ncomp + comp) * M.Pd + a] = cur[a];
         }
+        if (gradient) upload(PhiQ, std::vector<double>(phi, phi + M.n_cells * M.Qd));
         double s = 0.0;
         for (double v : Ph) s += v * v;
         normPhi = std::max(std::sqrt(s), 1e-300);
@@ -677,14 +726,17 @@ void Problem::set_data(const double* f, const double* phi) {
 }
 
 void Problem::ensure_linearisation_buffers() {
-    const size_t nq = (size_t)M.n_cells * M.Qd;
-    const size_t ns = (size_t)M.n_cells * M.Pd * M.Pd;
+    const size_t npair = (size_t)M.ncomp * (M.ncomp + 1) / 2;
+    const size_t nq = (size_t)M.n_cells * M.Qd * npair;
+    const size_t ns = (size_t)M.n_cells * M.psi_per_cell * M.psi_per_cell;
     if (precision == HPG_FP64) {
         om64.alloc(nq * sizeof(double));
         sinv64.alloc(ns * sizeof(double));
     } else {
         om32.alloc(nq * sizeof(float));
         sinv32.alloc(ns * sizeof(float));
+        // gradient blocks too large for LDS are formed and inverted in FP64 in place
+        if (gradient && dev::setup_grad_in_hbm(geo)) sinv64.alloc(ns * sizeof(double));
     }
 }
 
@@ -735,11 +787,20 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
     hparams[2] = 1.0 / alpha;
     HPG_HIP(hipMemcpyAsync(params.p, hparams, sizeof(hparams), hipMemcpyHostToDevice, s));
     tstart("setup", s);
-    dev::launch_setup(geo, tab64.view(), cpb_setup, d_psi, alpha, beta, C.as<double>(),
-                      cclass.as<int>(), prec == HPG_FP64 ? om64.as<double>() : nullptr,
-                      prec == HPG_FP64 ? nullptr : om32.as<float>(),
-                      prec == HPG_FP64 ? sinv64.as<double>() : nullptr,
-                      prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
+    if (gradient) {
+        const bool hbm = dev::setup_grad_in_hbm(geo);
+        dev::launch_setup_grad(geo, tab64.view(), d_psi, PhiQ.as<double>(), beta,
+                               prec == HPG_FP64 ? om64.as<double>() : nullptr,
+                               prec == HPG_FP64 ? nullptr : om32.as<float>(),
+                               (prec == HPG_FP64 || hbm) ? sinv64.as<double>() : nullptr,
+                               prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
+    } else {
+        dev::launch_setup(geo, tab64.view(), cpb_setup, d_psi, alpha, beta, C.as<double>(),
+                          cclass.as<int>(), prec == HPG_FP64 ? om64.as<double>() : nullptr,
+                          prec == HPG_FP64 ? nullptr : om32.as<float>(),
+                          prec == HPG_FP64 ? sinv64.as<double>() : nullptr,
+                          prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
+    }
     tstop("setup", s);
     HPG_HIP(hipGetLastError());
     linearised = true;
@@ -799,13 +860,22 @@ void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t
     hipStream_t s_psi = par ? side : s;
     if (par) fork(s);
     tstart("apply_G_psi", s_psi);
-    dev::launch_psi_side<T>(geo, Sel<T>::tabs(*this).view(), cpb_psi, (T)beta, x, x + M.n_u,
-                            Sel<T>::om(*this), nullptr, y + M.n_u, part ? part + np_u : nullptr,
-                            dn, dev::MODE_APPLY, s_psi, prm);
+    if (gradient)
+        dev::launch_psi_side_grad<T>(geo, Sel<T>::tabs(*this).view(), cpb_psi, (T)beta, x,
+                                     x + M.n_u, Sel<T>::om(*this), nullptr, y + M.n_u,
+                                     part ? part + np_u : nullptr, dn, dev::MODE_APPLY, s_psi, prm);
+    else
+        dev::launch_psi_side<T>(geo, Sel<T>::tabs(*this).view(), cpb_psi, (T)beta, x, x + M.n_u,
+                                Sel<T>::om(*this), nullptr, y + M.n_u,
+                                part ? part + np_u : nullptr, dn, dev::MODE_APPLY, s_psi, prm);
     tstop("apply_G_psi", s_psi);
     tstart("apply_G_u", s);
-    dev::launch_u_side<T>(geo, r, (T)alpha, x, x + M.n_u, nullptr, nullptr, y, part, dn,
-                          dev::MODE_APPLY, s, prm);
+    if (gradient)
+        dev::launch_u_side_grad<T>(geo, r, (T)alpha, x, x + M.n_u, nullptr, nullptr, y, part, dn,
+                                   dev::MODE_APPLY, s, prm);
+    else
+        dev::launch_u_side<T>(geo, r, (T)alpha, x, x + M.n_u, nullptr, nullptr, y, part, dn,
+                              dev::MODE_APPLY, s, prm);
     tstop("apply_G_u", s);
     if (par) join(s);
 }
@@ -826,8 +896,13 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
     if (par) fork(s);
     // psi-block: z_psi = (-S_hat_K)^{-1} r_psi, concurrently with the A-block
     tstart("prec_psi", s_psi);
-    dev::launch_prec_psi<T>(M.n_cells, (int)M.Pd, cpb_prec, Sel<T>::sinv(*this), r + M.n_u,
-                            z + M.n_u, part ? part + np_dot : nullptr, dn, s_psi);
+    if (prec_big)
+        dev::launch_prec_psi_big<T>(M.n_cells, (int)M.psi_per_cell, Sel<T>::sinv(*this),
+                                    r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr, np_prec,
+                                    dn, s_psi);
+    else
+        dev::launch_prec_psi<T>(M.n_cells, (int)M.psi_per_cell, cpb_prec, Sel<T>::sinv(*this),
+                                r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr, dn, s_psi);
     tstop("prec_psi", s_psi);
     // A-block: z_u = (alpha A)^{-1} r_u by fast diagonalisation: d forward
     // passes with V^T (the last one divides by alpha (lam_0 + ... )), then d
@@ -1019,11 +1094,19 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
             b += h[2 * i + 1];
         }
     } else {
-        dev::launch_u_side<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR, part, nullptr,
-                                   dev::MODE_RES, s);
-        dev::launch_psi_side<double>(geo, tab64.view(), cpb_psi, 0.0, uu, pp, nullptr,
-                                     Phi.as<double>(), RR + M.n_u, part + np_u, nullptr,
-                                     dev::MODE_RES, s);
+        if (gradient) {
+            dev::launch_u_side_grad<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR,
+                                            part, nullptr, dev::MODE_RES, s, nullptr);
+            dev::launch_psi_side_grad<double>(geo, tab64.view(), cpb_psi, 0.0, uu, pp, nullptr,
+                                              PhiQ.as<double>(), RR + M.n_u, part + np_u,
+                                              nullptr, dev::MODE_RES, s, nullptr);
+        } else {
+            dev::launch_u_side<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR, part,
+                                       nullptr, dev::MODE_RES, s);
+            dev::launch_psi_side<double>(geo, tab64.view(), cpb_psi, 0.0, uu, pp, nullptr,
+                                         Phi.as<double>(), RR + M.n_u, part + np_u, nullptr,
+                                         dev::MODE_RES, s);
+        }
         tstop("residual", s);
         HPG_HIP(hipGetLastError());
         std::vector<double> h(np_u + np_psi);

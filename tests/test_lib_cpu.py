@@ -80,3 +80,12 @@ def test_footprint_estimate_is_host_only_and_monotone():
     assert f64 > 8 * 15 * (small.n_u + small.n_psi)
     with pytest.raises(hpg.HpgError):
         small.footprint(7)
+
+
+def test_gradient_footprint_counts_component_blocks():
+    from paper_2412_13733_amd import hpg
+    ob = hpg.Mesh(2, [8, 8], 4)
+    gr = hpg.Mesh(2, [8, 8], 4, constraint=hpg.GRADIENT)
+    assert gr.n_psi == 8 * 8 * 2 * 16      # d components of P^d = p^d modes per cell
+    # psi blocks (d P^d)^2 per cell dominate the difference
+    assert gr.footprint(hpg.FP64) - ob.footprint(hpg.FP64) > 8 * 64 * (32 * 32 - 9 * 9)
