@@ -690,6 +690,10 @@ __global__ __launch_bounds__(256) void k_kr_update(int64_t n, const KState* st_i
             s.iters += 1;
             if (fabs(s.eta) <= s.rtol * s.gamma1 || s.iters >= s.max_iters || gnew == 0.0)
                 s.done = 1;
+            // a negative preconditioned norm of the next Lanczos vector means the
+            // preconditioner lost definiteness in the working precision: stop and
+            // report it rather than take it for convergence
+            if (g2 < 0.0) s.breakdown = 1;
         }
         if (blockIdx.x == 0) *st_out = s;
     }

@@ -153,6 +153,9 @@ struct Problem {
     double l2_diff(const double* a, const double* b, double* norm_a, hipStream_t s);
     hpg_status solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stats* st, double* d_u_out,
                      double* d_psi_out, double* d_lam_out);
+    int newton_direction64(const double* dR, double* dd, double eta, const hpg_solve_opts& o,
+                           hipStream_t s);
+    bool last_minres_breakdown = false;    // the last MINRES stopped on a breakdown
 
     void tstart(const char* grp, hipStream_t s);
     void tstop(const char* grp, hipStream_t s);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -133,7 +134,9 @@ size_t footprint_bytes(const Mesh& M, int precision) {
         b += 8.0 * n;                                                  // FP32 rhs and correction
         b += 4.0 * (7 * n + 2 * nu);
         b += 4.0 * nc * (double)M.Qd * npair + 4.0 * nc * blk;
-        if (M.kind == HPG_GRADIENT) b += 8.0 * nc * blk;               // FP64 blocks formed in HBM
+        // FP64 operator, Krylov vectors and solution of the steps that fall back to FP64
+        b += 8.0 * n + 8.0 * (7 * n + 2 * nu);
+        b += 8.0 * nc * (double)M.Qd * npair + 8.0 * nc * blk;
     }
     return (size_t)(1.15 * b) + ((size_t)8 << 20);
 }
@@ -1068,7 +1071,9 @@ int Problem::minres_on(const T* b, T* x, double rtol, int maxit, int chunk, hipS
     }
     HPG_HIP(hipGetLastError());
     if (!(hs.gamma1 == hs.gamma1)) fail(HPG_ERR_NUMERIC, "MINRES: non-finite right-hand side");
-    if (hs.breakdown && hs.iters == 0 && hs.gamma1 != 0.0) fail(HPG_ERR_NUMERIC, "MINRES breakdown");
+    if (hs.breakdown && hs.iters == 0 && hs.gamma1 != 0.0 && Sel<T>::prec == HPG_FP64)
+        fail(HPG_ERR_NUMERIC, "MINRES breakdown");
+    last_minres_breakdown = hs.breakdown != 0;
     return hs.iters;
 }
 
@@ -1136,6 +1141,22 @@ double Problem::l2_diff(const double* a, const double* b, double* norm_a, hipStr
     return std::sqrt(std::max(d2, 0.0));
 }
 
+// MINRES tolerance of a mixed-precision Newton step recomputed in FP64 (the
+// FP64 path's default): a direction accurate only to the FP32 tolerance does
+// not reduce the merit function near the Newton tolerance
+constexpr double kFallbackKrylovRtol = 1e-10;
+
+// Newton direction with the FP64 operator: b = -R, MINRES into xk64, delta = xk64
+int Problem::newton_direction64(const double* dR, double* dd, double eta, const hpg_solve_opts& o,
+                                hipStream_t s) {
+    const int64_t n = M.n_u + M.n_psi;
+    xk64.alloc(n * sizeof(double));
+    dev::launch_convert<double, double>(n, dR, dd, -1.0, s);
+    const int its = minres<double>(dd, xk64.as<double>(), eta, o.max_krylov, o.krylov_chunk, s);
+    HPG_HIP(hipMemcpyAsync(dd, xk64.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return its;
+}
+
 // ---------------------------------------------------------------------------
 // The proximal-point loop with Newton (paper Sec. 2.1 / Sec. 4; readings on
 // the alpha schedule, the Newton stop, the backtracking line search and the
@@ -1171,6 +1192,9 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
     bool ok = true;
     double last_err = 0.0;
     double alpha_used = alpha_k;
+    // HPG_TRACE=1: one line per Newton step on stderr (proximal step, Newton
+    // step, error, Krylov iterations, accepted step length)
+    const bool trace = std::getenv("HPG_TRACE") != nullptr;
     while (k < kmax) {
         ++k;
         HPG_HIP(hipMemcpyAsync(u_old.p, du, M.n_u * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1196,37 +1220,50 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                                    ? std::min(1e-6, std::max(o.krylov_rtol, 1e-6 * err))
                                    : o.krylov_rtol;
             int its;
+            bool need64 = false;   // FP32 Krylov solve broke down or hit its cap
             if (mixed) {
                 float* b32 = rhs32.as<float>();
                 float* x32 = delta32.as<float>();
                 dev::launch_convert<double, float>(n, dR, b32, -1.0, s);
                 its = minres<float>(b32, x32, eta, o.max_krylov, o.krylov_chunk, s);
                 dev::launch_convert<float, double>(n, x32, dd, 1.0, s);
+                need64 = last_minres_breakdown || its >= o.max_krylov;
             } else {
-                // b = -R in dd, MINRES into xk64, then delta = xk64
-                dev::launch_convert<double, double>(n, dR, dd, -1.0, s);
-                its = minres<double>(dd, xk64.as<double>(), eta, o.max_krylov, o.krylov_chunk, s);
-                HPG_HIP(hipMemcpyAsync(dd, xk64.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                its = newton_direction64(dR, dd, eta, o, s);
             }
             S.krylov_iters += its;
             S.newton_iters += 1;
-            // backtracking on ||(R_u / alpha, R_psi)||
+            // backtracking on ||(R_u / alpha, R_psi)||; a step from the FP32
+            // Krylov solve that the line search rejects is recomputed once in FP64
             const double m0 = std::sqrt(nu2 / (alpha_k * alpha_k) + np2);
             double t = 1.0;
             bool acc = false;
-            for (int hv = 0; hv <= 30; ++hv) {
-                dev::launch_axpy_to<double>(M.n_u, du, t, dd, dut, s);
-                dev::launch_axpy_to<double>(M.n_psi, dp, t, dd + M.n_u, dpt, s);
-                double a2, b2;
-                residual(dut, dpt, dpp, alpha_k, dR, s, &a2, &b2);
-                const double m1 = std::sqrt(a2 / (alpha_k * alpha_k) + b2);
-                if (m1 <= (1.0 - 1e-4 * t) * m0) {
-                    acc = true;
-                    break;
+            for (int attempt = need64 ? 1 : 0; attempt < (mixed ? 2 : 1) && !acc; ++attempt) {
+                if (attempt == 1) {
+                    residual(du, dp, dpp, alpha_k, dR, s, &nu2, &np2);
+                    setup(dp, alpha_k, o.beta, HPG_FP64, s);
+                    its = newton_direction64(dR, dd, std::min(eta, kFallbackKrylovRtol), o, s);
+                    S.krylov_iters += its;
+                    S.fp64_fallbacks += 1;   // the next Newton step sets up FP32 again
                 }
-                t *= 0.5;
-                S.line_search_halvings += 1;
+                t = 1.0;
+                for (int hv = 0; hv <= 30; ++hv) {
+                    dev::launch_axpy_to<double>(M.n_u, du, t, dd, dut, s);
+                    dev::launch_axpy_to<double>(M.n_psi, dp, t, dd + M.n_u, dpt, s);
+                    double a2, b2;
+                    residual(dut, dpt, dpp, alpha_k, dR, s, &a2, &b2);
+                    const double m1 = std::sqrt(a2 / (alpha_k * alpha_k) + b2);
+                    if (m1 <= (1.0 - 1e-4 * t) * m0) {
+                        acc = true;
+                        break;
+                    }
+                    t *= 0.5;
+                    S.line_search_halvings += 1;
+                }
             }
+            if (trace)
+                std::fprintf(stderr, "hpg: prox %d newton %d err %.3e krylov %d step %s\n", k, it,
+                             err, its, acc ? std::to_string(t).c_str() : "rejected");
             if (!acc) {
                 conv = err <= o.stall_tol;
                 break;
@@ -1235,6 +1272,9 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
             std::swap(dp, dpt);
         }
         alpha_used = alpha_k;
+        if (trace)
+            std::fprintf(stderr, "hpg: prox %d alpha %g %s err %.3e\n", k, alpha_k,
+                         conv ? "converged" : "NOT converged", last_err);
         if (!conv) {
             ok = false;
             break;

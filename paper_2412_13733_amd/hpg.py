@@ -46,7 +46,8 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("prox_steps", ctypes.c_int32),
                 ("newton_iters", ctypes.c_int32), ("line_search_halvings", ctypes.c_int32),
                 ("krylov_iters", ctypes.c_int64), ("newton_error", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("alpha_last", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("alpha_last", ctypes.c_double),
+                ("fp64_fallbacks", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
