@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--probe-m", type=int, default=4096)
     ap.add_argument("--probe-p", type=int, default=2)
     ap.add_argument("--probe-launches", type=int, default=20)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="prefix of the 512-request serving stream to run")
+    ap.add_argument("--serve-slots", type=int, default=8)
     return ap.parse_args()
 
 
@@ -179,6 +183,104 @@ def apply_probe(args, torch, hpg):
     del prob, mesh, x, y, psi
     torch.cuda.empty_cache()
     return out
+
+
+# ---- serving: the Poisson request stream (2-D n x n cells, n in 8..64,
+# p in 2..10, 25% gradient constraint) through the continuous-batching server
+def serving_requests(hpg, W, n_req):
+    arrivals, reqs = W.serving_stream(512, 40.0, 12345)
+    built = []
+    for r in reqs[:n_req]:
+        kind = hpg.GRADIENT if r["kind"] == "gradient" else hpg.OBSTACLE
+        mesh = hpg.Mesh(2, [r["n"], r["n"]], r["p"], constraint=kind)
+        x = mesh.quadrature_points()
+        f, phi = W.request_data(r)
+        built.append((mesh, f(x), phi(x), r))
+    return arrivals[:n_req], built
+
+
+def request_opts(hpg, r, precision):
+    """Obstacle requests: alpha_k = 2^k to the 1e-10 proximal tolerance.
+    Gradient requests: the paper's schedule for that problem class,
+    alpha_1 = 2^-7, alpha_{k+1} = min(sqrt(2) alpha_k, 4), 20 steps.  A Newton
+    stall is accepted at error 1e-8 (the serving accuracy target)."""
+    kw = dict(stall_tol=1e-8)
+    if r["kind"] == "gradient":
+        kw.update(alpha0=2.0 ** -7, alpha_factor=2.0 ** 0.5, alpha_max=4.0, fixed_prox_steps=20)
+    if precision == hpg.MIXED:
+        kw.update(precision=hpg.MIXED, newton_tol=1e-10, krylov_rtol=1e-6)
+    return hpg.default_opts(**kw)
+
+
+def serve(hpg, built, arrivals, slots, precision, label):
+    srv = hpg.Server(device=0, max_slots=slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for i, (mesh, f, phi, r) in enumerate(built):
+        if arrivals is not None:
+            dt = t0 + float(arrivals[i]) - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        tickets.append(srv.submit(mesh, f, phi, request_opts(hpg, r, precision)))
+    out = [None] * len(tickets)
+    pending = dict(enumerate(tickets))
+    while pending:
+        for i, t in list(pending.items()):
+            res = srv.poll(t)
+            if res is None:
+                continue
+            u, psi, st, info = res
+            out[i] = (u, st, info)
+            del pending[i]
+            print("[bench] serving %s: request %d done (status %d, %.2f s), %d/%d, %.1f s"
+                  % (label, i, st.status, info.run_s, len(tickets) - len(pending), len(tickets),
+                     time.perf_counter() - t0), file=sys.stderr, flush=True)
+        time.sleep(0.01)
+    stats = srv.stats().as_dict()
+    srv.close()
+    return out, stats
+
+
+def serving_bench(args, hpg, W):
+    arrivals, built = serving_requests(hpg, W, args.serve_requests)
+
+    def summary(res, stats):
+        ok = [st.status == 0 for _, st, _ in res]
+        return {"requests": len(res), "converged": int(sum(ok)),
+                "solves_per_s": stats["solves_per_s"],
+                "dof_krylov_per_s": stats["dof_krylov_per_s"],
+                "p50_latency_s": stats["p50_latency_s"], "p99_latency_s": stats["p99_latency_s"],
+                "max_running": stats["max_running"], "span_s": stats["span_s"],
+                "hbm_peak_reserved_GB": stats["hbm_peak_reserved"] / 1e9,
+                "fp64_fallbacks": int(sum(st.fp64_fallbacks for _, st, _ in res))}
+
+    seq, s_seq = serve(hpg, built, None, 1, hpg.FP64, "fp64 x1")
+    bat, s_bat = serve(hpg, built, None, args.serve_slots, hpg.MIXED,
+                       "mixed x%d" % args.serve_slots)
+    live, s_live = serve(hpg, built, arrivals, args.serve_slots, hpg.MIXED, "mixed poisson")
+    # accuracy of the mixed path against the FP64 path over the requests both converged on
+    errs = [float(np.linalg.norm(ub - us) / max(np.linalg.norm(us), 1e-300))
+            for (ub, sb, _), (us, ss, _) in zip(bat, seq) if sb.status == 0 and ss.status == 0]
+    differ = [i for i, (a, b) in enumerate(zip(bat, live)) if not np.array_equal(a[0], b[0])]
+    kinds = [r["kind"] for _, _, _, r in built]
+    return {
+        "workload": "serving stream: first %d of 512 requests, Poisson arrivals 40/s (seed "
+                    "12345); 2-D n x n cells, n in 8..64, p in 2..10, f sine family and "
+                    "paraboloid / dip obstacle, 25%% gradient constraint with phi ~ U[0.2, 0.5]"
+                    % len(built),
+        "gradient_requests": kinds.count("gradient"),
+        "slots": args.serve_slots,
+        "fp64_sequential": summary(seq, s_seq),
+        "mixed_batched": summary(bat, s_bat),
+        "mixed_poisson": summary(live, s_live),
+        "speedup_batched_mixed_vs_fp64": s_bat["solves_per_s"] / max(s_seq["solves_per_s"], 1e-300),
+        "accuracy_note": "relative l2 distance of the mixed-path u to the FP64-path u, over the "
+                         "requests both paths converged on",
+        "max_rel_l2_mixed_vs_fp64": max(errs) if errs else None,
+        "median_rel_l2_mixed_vs_fp64": float(np.median(errs)) if errs else None,
+        "poisson_equals_batched": not differ,
+        "poisson_differs_at": differ,
+    }
 
 
 def main():
@@ -313,6 +415,15 @@ def main():
         out["apply_G_probe"] = apply_probe(args, torch, hpg)
         print("[bench] apply_G probe: %.1f us, %.0f GB/s" % (out["apply_G_probe"]["apply_us"],
                                                             out["apply_G_probe"]["achieved_GBs"]),
+              file=sys.stderr, flush=True)
+    if not args.no_serving:
+        out["serving"] = serving_bench(args, hpg, W)
+        sv = out["serving"]
+        print("[bench] serving: fp64 x1 %.2f solves/s, mixed x%d %.2f solves/s, poisson p50 "
+              "%.2f s p99 %.2f s" % (sv["fp64_sequential"]["solves_per_s"], sv["slots"],
+                                    sv["mixed_batched"]["solves_per_s"],
+                                    sv["mixed_poisson"]["p50_latency_s"],
+                                    sv["mixed_poisson"]["p99_latency_s"]),
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, int(round(results[precs[0]]["newton"] / args.steps)))
