@@ -55,7 +55,42 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="prefix of the 512-request serving stream to run")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--counters", action="store_true",
+                    help="only a few operator launches for rocprofv3 --pmc passes: the "
+                         "workload's G apply and preconditioner (FP32 and FP64), the 4096^2 "
+                         "p=2 G apply, and a 1 GiB device copy to calibrate the counters")
     return ap.parse_args()
+
+
+def counters_run(args, torch, hpg, W):
+    """Short, fixed sequence of launches to read HBM counters against."""
+    f, phi = W.w2d(args.seed)
+    mesh = hpg.Mesh(2, [args.m, args.m], args.p)
+    x = mesh.quadrature_points()
+    prob = hpg.Problem(mesh, device=0)
+    prob.set_forcing(f(x))
+    prob.set_obstacle(phi(x))
+    n = mesh.n_u + mesh.n_psi
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    psi = 0.5 * torch.randn(mesh.n_psi, dtype=torch.float64, device="cuda", generator=g)
+    for prec, dt in ((hpg.MIXED, torch.float32), (hpg.FP64, torch.float64)):
+        prob.op_setup(psi, 4.0, 0.0, precision=prec)
+        v = torch.randn(n, dtype=dt, device="cuda", generator=g)
+        w = torch.empty_like(v)
+        for _ in range(5):
+            prob.op_apply_prec(v, w)
+            prob.op_apply_G(v, w)
+    torch.cuda.synchronize()
+    del prob
+    args.probe_launches = 5
+    apply_probe(args, torch, hpg)
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": "done", "copy_bytes": a.numel() * 8}), flush=True)
 
 
 GROUPS = ["apply_G", "apply_G_u", "apply_G_psi", "fdm", "prec_psi", "minres_vec", "setup",
@@ -76,11 +111,27 @@ def group_work(mesh, b):
         "apply_G_u": ("hbm", b * (2 * n_u + n_psi)),
         # psi-side: x_u, x_psi, omega in, y_psi out
         "apply_G_psi": ("hbm", b * (n_u + 2 * n_psi + N * Qd)),
-        # 2d tensor-axis passes, each 2 n1^(d+1) flops
-        "fdm": ("mfma", 2 * d * 2.0 * n1 ** (d + 1)),
+        # one fast-diagonalisation pass (one GEMM launch; 2d per preconditioner apply)
+        "fdm": ("mfma", 2.0 * n1 ** (d + 1)),
         # inverse blocks, r_psi in, z_psi out
         "prec_psi": ("hbm", b * (N * Pd * Pd + 2 * n_psi)),
     }
+
+
+TRAFFIC_LABEL = {"fdm": "fdm pass", "apply_G": "G apply", "prec_psi": "psi-block preconditioner"}
+
+
+def measured_traffic(group, m, p, path):
+    """HBM bytes per launch of a kernel group as read by rocprofv3 --pmc
+    (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy) and recorded in
+    profiles/pmc_traffic.json; None if that kernel/workload was not measured."""
+    fn = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pmc_traffic.json")
+    if group not in TRAFFIC_LABEL or not os.path.exists(fn):
+        return None
+    key = "%s, 2-D %dx%d p=%d, %s" % (TRAFFIC_LABEL[group], m, m, p,
+                                      "FP64" if path == "fp64" else "FP32")
+    ent = json.load(open(fn))["kernels"].get(key)
+    return ent["traffic_bytes"] if ent else None
 
 
 def run_solves(prob, d_u, d_psi, opts, steps, torch, group=None):
@@ -175,7 +226,12 @@ def apply_probe(args, torch, hpg):
         t_apply = (msu / nu + msp / npx) * 1e-3
         launches = nu
     ach = alg / t_apply / 1e9
+    fn = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pmc_traffic.json")
+    ent = None
+    if os.path.exists(fn):
+        ent = json.load(open(fn))["kernels"].get("G apply, 2-D %dx%d p=%d, FP64" % (m, m, p))
     out = {"workload": "apply_G, 2-D %dx%d cells, p=%d, FP64" % (m, m, p),
+           "traffic": ent["traffic_bytes"] if ent else None,
            "kernel": "fused tiled apply" if nf else "u-side + psi-side kernels",
            "algorithmic_bytes": alg, "apply_us": t_apply * 1e6,
            "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
@@ -294,6 +350,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.counters:
+        counters_run(args, torch, hpg, W)
+        return
     f, phi = W.w2d(args.seed)
     mesh = hpg.Mesh(2, [args.m, args.m], args.p)
     x = mesh.quadrature_points()
@@ -366,6 +425,7 @@ def main():
                 "frac": ach / pk, "traffic": None, "flops_per_launch": amount}
     roof["avg_launch_us"] = groups[dom]["avg_us"]
     roof["launches"] = groups[dom]["launches"]
+    roof["traffic"] = measured_traffic(dom, args.m, args.p, best)
 
     def summary(r):
         return dict(dof_krylov_per_s=n_dof * r["krylov"] / r["seconds"],

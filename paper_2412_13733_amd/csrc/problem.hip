@@ -910,7 +910,6 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
     // A-block: z_u = (alpha A)^{-1} r_u by fast diagonalisation: d forward
     // passes with V^T (the last one divides by alpha (lam_0 + ... )), then d
     // backward passes with V (the last one forms the partial sums of <z_u, r_u>)
-    tstart("fdm", s);
     const int d = M.d;
     const T* src = r;
     int pass = 0;
@@ -934,6 +933,7 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                 ep.partial = part;
             }
             const int N = M.n1[k];
+            tstart("fdm", s);   // timed per pass: one GEMM launch each
             if (k == 0) {
                 // Y (R x N) = X (R x N) Mat^T with Mat = V^T (forward) / V (backward)
                 const T* Bm = ph == 0 ? F.V[k].template as<T>() : F.Vt[k].template as<T>();
@@ -948,11 +948,11 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                 dev::launch_gemm<T>(N, (int)inner, N, Am, N, 0, src, inner, (int64_t)N * inner, dst,
                                     inner, (int64_t)N * inner, (int)outer, dn, ep, s);
             }
+            tstop("fdm", s);
             src = dst;
         }
     }
     if (part && !fuse_dot) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
-    tstop("fdm", s);
     if (par) join(s);
 }
 

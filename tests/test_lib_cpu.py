@@ -73,7 +73,8 @@ def test_footprint_estimate_is_host_only_and_monotone():
     big = hpg.Mesh(2, [32, 32], 4)
     hi_p = hpg.Mesh(2, [8, 8], 8)
     f64, f32 = small.footprint(hpg.FP64), small.footprint(hpg.MIXED)
-    assert 0 < f32 < f64
+    # a mixed solve also reserves the FP64 buffers of the steps it recomputes in FP64
+    assert 0 < f64 < f32
     assert big.footprint(hpg.FP64) > f64
     assert hi_p.footprint(hpg.FP64) > f64
     # at least the FP64 Newton state and Krylov vectors
