@@ -859,7 +859,7 @@ void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t
         tstop("apply_G", s);
         return;
     }
-    const bool par = !timing;   // timed runs keep every launch on one stream
+    const bool par = !timing && !single_stream;   // timed runs keep every launch on one stream
     hipStream_t s_psi = par ? side : s;
     if (par) fork(s);
     tstart("apply_G_psi", s_psi);
@@ -894,7 +894,7 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
     T* t1 = kw.t1.template as<T>();
     T* t2 = kw.t2.template as<T>();
     const double* prm = params.as<double>();
-    const bool par = !timing;
+    const bool par = !timing && !single_stream;
     hipStream_t s_psi = par ? side : s;
     if (par) fork(s);
     // psi-block: z_psi = (-S_hat_K)^{-1} r_psi, concurrently with the A-block

@@ -82,6 +82,7 @@ void Server::run(Request& r) {
     size_t& counter = device_bytes_counter();
     const size_t before = counter;
     Problem P;
+    P.single_stream = true;
     P.build(r.mesh, device);
     P.set_data(r.f.data(), r.phi.data());
     r.status = P.solve(r.opts, P.own_stream, &r.stats, nullptr, nullptr, nullptr);
