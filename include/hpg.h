@@ -186,7 +186,9 @@ hpg_status hpg_l2_diff(hpg_problem* prob, const double* d_a, const double* d_b, 
  * named group ("apply_G" (fused tiled apply), "apply_G_u", "apply_G_psi" (the
  * two-kernel apply used where no tiled variant exists), "fdm", "prec_psi",
  * "minres_vec", "setup", "residual") is timed.  While enabled, every launch of a timed
- * group is bracketed by HIP events on the stream it is launched on;
+ * group gets a pair of HIP events: recorded by the kernel's dispatch itself for
+ * "apply_G" and "fdm" (one GEMM pass per launch), recorded on the launch stream
+ * around the group's launches for the others;
  * hpg_kernel_time returns the number of bracketed launches and their summed
  * duration in milliseconds.  Enabling resets the counters. */
 hpg_status hpg_set_kernel_timing(hpg_problem* prob, const char* group);

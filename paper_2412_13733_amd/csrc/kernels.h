@@ -59,6 +59,13 @@ struct PsiTabs {
     const T* MY;     // P x P: (Y_a, Y_b) on [-1, 1]
 };
 
+// start/stop events recorded by the dispatch of one kernel launch itself
+// (hipExtLaunchKernelGGL), used when kernel timing is enabled
+struct KernelEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 // MINRES scalar state (device)
 struct KState {
     double gamma1, gamma, delta;
@@ -87,7 +94,7 @@ template <typename T>
 bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                  const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
                  const double* F, const double* Phi, T* yu, T* ypsi, double* partial,
-                 const int* done, int mode, hipStream_t s);
+                 const int* done, int mode, hipStream_t s, const KernelEvents* ev = nullptr);
 size_t setup_smem_per_cell(const Geo& g);
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
@@ -111,7 +118,8 @@ struct GemmEpi {
 template <typename T>
 void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,
                  int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, int batch,
-                 const int* done, const GemmEpi<T>& ep, hipStream_t s);
+                 const int* done, const GemmEpi<T>& ep, hipStream_t s,
+                 const KernelEvents* ev = nullptr);
 template <typename T>
 void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
                       const int* done, hipStream_t s);

@@ -14,6 +14,7 @@
 // is cell-local: a block stages several cells' coefficients in LDS and
 // applies D_psi sum-factorised through the Gauss-Legendre points
 // (paper Sec. 4.3: D_psi = V^T diag(omega) V per cell).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -874,10 +875,14 @@ void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r,
 template <typename T>
 void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,
                  int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, int batch,
-                 const int* done, const GemmEpi<T>& ep, hipStream_t s) {
+                 const int* done, const GemmEpi<T>& ep, hipStream_t s, const KernelEvents* ev) {
     dim3 grid((N + 15) / 16, (M + 15) / 16, batch);
-    hipLaunchKernelGGL((k_gemm_mfma<T>), grid, dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB,
-                       C, ldc, sC, done, ep);
+    if (ev && ev->start)
+        hipExtLaunchKernelGGL((k_gemm_mfma<T>), grid, dim3(256), 0, s, ev->start, ev->stop, 0, M,
+                              N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, done, ep);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma<T>), grid, dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb,
+                           sB, C, ldc, sC, done, ep);
 }
 
 template <typename T>
@@ -959,7 +964,7 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
                                      const int*, hipStream_t);                                   \
     template void launch_gemm<T>(int, int, int, const T*, int64_t, int64_t, const T*, int64_t,    \
                                  int64_t, T*, int64_t, int64_t, int, const int*,                 \
-                                 const GemmEpi<T>&, hipStream_t);                                \
+                                 const GemmEpi<T>&, hipStream_t, const KernelEvents*);           \
     template void launch_fdm_scale<T>(const Geo&, const T*, const T*, const T*, T, T*,          \
                                       const int*, hipStream_t);                                  \
     template void launch_kr_start<T>(int64_t, KState*, const double*, int, double, int, const T*, \

@@ -161,6 +161,9 @@ struct Problem {
                            hipStream_t s);
     bool last_minres_breakdown = false;    // the last MINRES stopped on a breakdown
 
+    // events for one timed launch of group grp (recorded by the dispatch), or
+    // none when the group is not being timed
+    dev::KernelEvents kernel_events(const char* grp);
     void tstart(const char* grp, hipStream_t s);
     void tstop(const char* grp, hipStream_t s);
     ~Problem();

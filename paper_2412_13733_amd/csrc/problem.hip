@@ -773,6 +773,23 @@ void Problem::tstart(const char* grp, hipStream_t s) {
     }
     HPG_HIP(hipEventRecord(g.start[g.used], s));
 }
+dev::KernelEvents Problem::kernel_events(const char* grp) {
+    dev::KernelEvents ev;
+    if (!timed(*this, grp)) return ev;
+    TimingGroup& g = groups[grp];
+    if (g.used == g.start.size()) {
+        hipEvent_t a, b;
+        HPG_HIP(hipEventCreate(&a));
+        HPG_HIP(hipEventCreate(&b));
+        g.start.push_back(a);
+        g.stop.push_back(b);
+    }
+    ev.start = g.start[g.used];
+    ev.stop = g.stop[g.used];
+    g.used++;
+    return ev;
+}
+
 void Problem::tstop(const char* grp, hipStream_t s) {
     if (!timed(*this, grp)) return;
     TimingGroup& g = groups[grp];
@@ -852,11 +869,10 @@ void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t
     const double* prm = params.as<double>();
     if (use_tile) {
         // one fused LDS-tiled launch for both sides of G
-        tstart("apply_G", s);
+        const dev::KernelEvents ke = kernel_events("apply_G");
         dev::launch_tile<T>(geo, r, Sel<T>::tabs(*this).view(), (T)alpha, (T)beta, prm, x,
                             x + M.n_u, nullptr, Sel<T>::om(*this), nullptr, nullptr, y, y + M.n_u,
-                            part, dn, dev::MODE_APPLY, s);
-        tstop("apply_G", s);
+                            part, dn, dev::MODE_APPLY, s, &ke);
         return;
     }
     const bool par = !timing && !single_stream;   // timed runs keep every launch on one stream
@@ -933,12 +949,12 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                 ep.partial = part;
             }
             const int N = M.n1[k];
-            tstart("fdm", s);   // timed per pass: one GEMM launch each
+            const dev::KernelEvents ke = kernel_events("fdm");   // timed per pass (one GEMM)
             if (k == 0) {
                 // Y (R x N) = X (R x N) Mat^T with Mat = V^T (forward) / V (backward)
                 const T* Bm = ph == 0 ? F.V[k].template as<T>() : F.Vt[k].template as<T>();
                 const int R = (int)(M.n_u / N);
-                dev::launch_gemm<T>(R, N, N, src, N, 0, Bm, N, 0, dst, N, 0, 1, dn, ep, s);
+                dev::launch_gemm<T>(R, N, N, src, N, 0, Bm, N, 0, dst, N, 0, 1, dn, ep, s, &ke);
             } else {
                 // Y_o (N x inner) = Mat (N x N) X_o (N x inner)
                 const T* Am = ph == 0 ? F.Vt[k].template as<T>() : F.V[k].template as<T>();
@@ -946,9 +962,8 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                 for (int j = 0; j < k; ++j) inner *= M.n1[j];
                 const int64_t outer = M.n_u / (inner * N);
                 dev::launch_gemm<T>(N, (int)inner, N, Am, N, 0, src, inner, (int64_t)N * inner, dst,
-                                    inner, (int64_t)N * inner, (int)outer, dn, ep, s);
+                                    inner, (int64_t)N * inner, (int)outer, dn, ep, s, &ke);
             }
-            tstop("fdm", s);
             src = dst;
         }
     }

@@ -42,17 +42,17 @@ template <typename T, int D, int MODE>
 bool launch_tile_d(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                    const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev,
                    const T* omega, const double* F, const double* Phi, T* yu, T* ypsi,
-                   double* partial, const int* done, hipStream_t s);
+                   double* partial, const int* done, hipStream_t s, const KernelEvents* ev);
 
 template <typename T>
 bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                  const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
                  const double* F, const double* Phi, T* yu, T* ypsi, double* partial,
-                 const int* done, int mode, hipStream_t s) {
+                 const int* done, int mode, hipStream_t s, const KernelEvents* ev) {
     if (!tile_supported(g)) return false;
 #define HPG_TD(DD, MM)                                                                        \
     return launch_tile_d<T, DD, MM>(g, r, tb, alpha, beta, prm, xu, xpsi, xpsi_prev, omega, F, \
-                                    Phi, yu, ypsi, partial, done, s)
+                                    Phi, yu, ypsi, partial, done, s, ev)
     if (mode == MODE_APPLY) {
         if (g.d == 1) HPG_TD(1, MODE_APPLY);
         if (g.d == 2) HPG_TD(2, MODE_APPLY);
@@ -67,11 +67,12 @@ bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha,
 template bool launch_tile<double>(const Geo&, const URows<double>*, const PsiTabs<double>&, double,
                                   double, const double*, const double*, const double*,
                                   const double*, const double*, const double*, const double*,
-                                  double*, double*, double*, const int*, int, hipStream_t);
+                                  double*, double*, double*, const int*, int, hipStream_t,
+                                  const KernelEvents*);
 template bool launch_tile<float>(const Geo&, const URows<float>*, const PsiTabs<float>&, float,
                                  float, const double*, const float*, const float*, const float*,
                                  const float*, const double*, const double*, float*, float*,
-                                 double*, const int*, int, hipStream_t);
+                                 double*, const int*, int, hipStream_t, const KernelEvents*);
 
 }  // namespace dev
 }  // namespace hpg

@@ -23,6 +23,7 @@
 // output written once.  Residual mode evaluates eq. (pG) instead: the Gram
 // term acts on psi - psi_prev, R_u subtracts alpha F, and R_psi uses
 // (exp(-psi_h), zeta) - Phi with the exponent guard exp(min(-psi, 700)).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -765,27 +766,32 @@ void launch_tile_impl(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T a
                              T beta, const double* prm, const T* xu, const T* xpsi,
                              const T* xpsi_prev, const T* omega, const double* F,
                              const double* Phi, T* yu, T* ypsi, double* partial, const int* done,
-                             hipStream_t s) {
+                             hipStream_t s, const KernelEvents* ev) {
     constexpr int TC = tile_cells(D, PP);
     // the prefetching path runs persistent blocks over contiguous runs of tiles;
     // otherwise one block per tile, unless per-block partial sums are written
     // (their count must fit the reduction buffer)
     const unsigned grid = (TileCfg<D, PP, TC>::DENSE || partial) ? (unsigned)tile_grid(g)
                                                                  : (unsigned)tile_count(g);
-    hipLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), dim3(grid), dim3(256), 0, s, g,
-                       r[0], r[1], r[2], tb, alpha, beta, prm, xu, xpsi, xpsi_prev, omega, F, Phi,
-                       yu, ypsi, partial, done);
+    if (ev && ev->start)
+        hipExtLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), dim3(grid), dim3(256), 0, s,
+                              ev->start, ev->stop, 0, g, r[0], r[1], r[2], tb, alpha, beta, prm, xu,
+                              xpsi, xpsi_prev, omega, F, Phi, yu, ypsi, partial, done);
+    else
+        hipLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), dim3(grid), dim3(256), 0, s, g,
+                           r[0], r[1], r[2], tb, alpha, beta, prm, xu, xpsi, xpsi_prev, omega, F,
+                           Phi, yu, ypsi, partial, done);
 }
 
 template <typename T, int D, int MODE>
 bool launch_tile_d(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                    const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev,
                    const T* omega, const double* F, const double* Phi, T* yu, T* ypsi,
-                   double* partial, const int* done, hipStream_t s) {
+                   double* partial, const int* done, hipStream_t s, const KernelEvents* ev) {
 #define HPG_TC(PV)                                                                            \
     case PV:                                                                                  \
         launch_tile_impl<T, D, PV, MODE>(g, r, tb, alpha, beta, prm, xu, xpsi, xpsi_prev,    \
-                                         omega, F, Phi, yu, ypsi, partial, done, s);          \
+                                         omega, F, Phi, yu, ypsi, partial, done, s, ev);      \
         return true;
     if constexpr (D == 3) {
         switch (g.p) {
@@ -806,7 +812,7 @@ bool launch_tile_d(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alph
     template bool launch_tile_d<T, DD, MM>(const Geo&, const URows<T>*, const PsiTabs<T>&, T, T, \
                                            const double*, const T*, const T*, const T*,          \
                                            const T*, const double*, const double*, T*, T*,       \
-                                           double*, const int*, hipStream_t);
+                                           double*, const int*, hipStream_t, const KernelEvents*);
 
 }  // namespace dev
 }  // namespace hpg
