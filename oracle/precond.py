@@ -52,6 +52,28 @@ def schur_hat(system, psi, alpha, beta):
     return sp.csr_matrix(-D.toarray() - Bhat.T.toarray() @ X)
 
 
+def schur_hat_cells(system, psi, alpha, beta, cells):
+    """Dense cell blocks of S_hat for the listed cells (S_hat is block-diagonal
+    by cells); the same matrices as schur_hat, restricted to each cell."""
+    D = (system.Dpsi(psi) + beta * system.Ebeta_unit).tocsr()
+    mesh = system.mesh
+    if mesh.kind == OBSTACLE:
+        Ahat, Bhat = phi_blocks(system, alpha)
+        Ahat, Bhat = Ahat.tocsr(), Bhat.tocsr()
+    nY = mesh.P ** mesh.d
+    out = []
+    for c in cells:
+        pg = mesh.psi_dofs(int(c))
+        blk = -D[pg][:, pg].toarray()
+        if mesh.kind == OBSTACLE:
+            eta = np.arange(int(c) * nY, (int(c) + 1) * nY)
+            Bk = Bhat[eta][:, pg].toarray()
+            Ak = Ahat[eta][:, eta].toarray()
+            blk = blk - Bk.T @ np.linalg.solve(Ak, Bk)
+        out.append(blk)
+    return out
+
+
 def apply_prec(system, psi, alpha, beta, r_u, r_psi):
     """z = diag(alpha A, -S_hat)^{-1} r (direct solves)."""
     zu = spla.spsolve((alpha * system.A).tocsc(), r_u)

@@ -1,0 +1,191 @@
+"""GPU parity at the full sizes of the workloads, in the launch configurations
+the solves use.
+
+* 2-D 32 x 32 cells, p = 6 (the benchmark workload): G and the Newton residual
+  element by element against the oracle's assembled matrices; the
+  preconditioner's psi-block on sampled cells against the oracle's cell
+  blocks, and its A-block through alpha A z_u = r_u.
+* 3-D 16^3 cells (obstacle p = 5; gradient p = 4): the oracle cannot assemble
+  these meshes in seconds, so the comparison is windowed and still exact: G of
+  the full mesh applied to a vector supported on cells 0..2 in every direction
+  equals, on every unknown, G of the oracle's 4^3-cell mesh with the same cell
+  widths (every cell touching the support lies in that box); psi-block outputs
+  are compared on the cells of a 2^3 box against the oracle's, and the A-block
+  through alpha A z_u = r_u.
+Tolerances as for the small parity cases (FP64 1e-12 / 1e-10, FP32 2e-5)."""
+import numpy as np
+import pytest
+
+from oracle import assemble, precond, mesh as OM
+import workloads as W
+
+from gpu_common import log, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def _gpu(d, m, p, kind, data):
+    from paper_2412_13733_amd import hpg
+    mesh = hpg.Mesh(d, [m] * d, p, constraint=hpg.GRADIENT if kind == OM.GRADIENT else hpg.OBSTACLE)
+    x = mesh.quadrature_points()
+    prob = hpg.Problem(mesh)
+    prob.set_forcing(data[0](x))
+    prob.set_obstacle(data[1](x))
+    return mesh, prob
+
+
+def _oracle(d, m_full, m_sub, p, kind, data):
+    br = W.uniform_breaks(m_full)[: m_sub + 1]
+    om = OM.TensorMesh([br] * d, p, kind)
+    xo = om.quadrature_points()
+    return om, assemble.System(om, data[0](xo), data[1](xo))
+
+
+def _u_map(d, p, m_full, m_sub):
+    """Full-mesh flat index of every sub-mesh u unknown (sub-mesh order)."""
+    n1f, n1s = m_full * p - 1, m_sub * p - 1
+    g = np.arange(n1s)
+    idx = g.copy()
+    stride = n1f
+    for _ in range(d - 1):
+        idx = (idx[None, :] + stride * g[:, None]).reshape(-1)
+        stride *= n1f
+    return idx
+
+
+def _cell_map(d, m_full, m_sub):
+    c = np.arange(m_sub)
+    idx = c.copy()
+    stride = m_full
+    for _ in range(d - 1):
+        idx = (idx[None, :] + stride * c[:, None]).reshape(-1)
+        stride *= m_full
+    return idx
+
+
+def _window_u(d, p, m_full, ncell):
+    """Full-mesh flat indices of the u unknowns supported on cells < ncell."""
+    n1f = m_full * p - 1
+    g = np.arange(n1f)
+    c = g // p
+    hat = (g + 1) % p == 0
+    ok = np.where(hat, c + 1 < ncell, c < ncell)
+    g1 = g[ok]
+    idx = g1.copy()
+    stride = n1f
+    for _ in range(d - 1):
+        idx = (idx[None, :] + stride * g1[:, None]).reshape(-1)
+        stride *= n1f
+    return idx
+
+
+# ---------------------------------------------------------------------------
+def test_fullsize_2d_32x32_p6_operators():
+    f, phi = W.w2d(0)
+    mesh, prob = _gpu(2, 32, 6, OM.OBSTACLE, (f, phi))
+    om, sysm = _oracle(2, 32, 32, 6, OM.OBSTACLE, (f, phi))
+    log("2-D 32x32 p=6: n_u", mesh.n_u, "n_psi", mesh.n_psi)
+    rng = np.random.default_rng(101)
+    psi = 0.5 * rng.standard_normal(mesh.n_psi)
+    x = rng.standard_normal(mesh.n_u + mesh.n_psi)
+    alpha, beta = 16.0, 1e-4
+    yu, yp = precond.apply_G(sysm, psi, alpha, beta, x[:mesh.n_u], x[mesh.n_u:])
+    for prec, dt, tol in ((0, torch.float64, 1e-12), (1, torch.float32, 2e-5)):
+        prob.op_setup(_dev(psi), alpha, beta, precision=prec)
+        y = torch.zeros(mesh.n_u + mesh.n_psi, dtype=dt, device="cuda")
+        prob.op_apply_G(_dev(x, dt), y)
+        yg = y.double().cpu().numpy()
+        log("  G prec", prec, rel(yg[:mesh.n_u], yu), rel(yg[mesh.n_u:], yp))
+        assert rel(yg[:mesh.n_u], yu) < tol and rel(yg[mesh.n_u:], yp) < tol
+    # residual
+    u = 0.1 * rng.standard_normal(mesh.n_u)
+    psi_prev = 0.5 * rng.standard_normal(mesh.n_psi)
+    R = torch.zeros(mesh.n_u + mesh.n_psi, dtype=torch.float64, device="cuda")
+    prob.op_residual(_dev(u), _dev(psi), _dev(psi_prev), alpha, R)
+    Ru, Rp = sysm.residual(u, psi, psi_prev, alpha)
+    Rg = R.cpu().numpy()
+    assert rel(Rg[:mesh.n_u], Ru) < 1e-12 and rel(Rg[mesh.n_u:], Rp) < 1e-12
+    # preconditioner: A-block by alpha A z_u = r_u, psi-block on sampled cells
+    prob.op_setup(_dev(psi), alpha, beta, precision=0)
+    r = rng.standard_normal(mesh.n_u + mesh.n_psi)
+    z = torch.zeros_like(_dev(r))
+    prob.op_apply_prec(_dev(r), z)
+    zz = z.clone()
+    zz[mesh.n_u:] = 0
+    y = torch.zeros_like(z)
+    prob.op_apply_G(zz, y)
+    assert rel(y[:mesh.n_u].cpu().numpy(), r[:mesh.n_u]) < 1e-10
+    _check_psi_block_cells(sysm, psi, alpha, beta, r, z.cpu().numpy(), mesh.n_u,
+                           cells=rng.choice(mesh.n_cells, 12, replace=False), npc=mesh.P ** 2)
+
+
+def _check_psi_block_cells(sysm, psi, alpha, beta, r, zg, n_u, cells, npc, cell_map=None):
+    """z_psi on the given cells against the oracle's cell blocks of -S_hat."""
+    S = precond.schur_hat_cells(sysm, psi, alpha, beta, cells)
+    for k, c in enumerate(cells):
+        cg = c if cell_map is None else cell_map[c]
+        rb = r[n_u + cg * npc: n_u + (cg + 1) * npc]
+        zo = np.linalg.solve(-S[k], rb)
+        zb = zg[n_u + cg * npc: n_u + (cg + 1) * npc]
+        assert rel(zb, zo) < 1e-10, (c, rel(zb, zo))
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,p,data", [(OM.OBSTACLE, 5, W.w3d()), (OM.GRADIENT, 4, W.w3d_gradient())],
+                         ids=["obstacle-p5", "gradient-p4"])
+def test_fullsize_3d_16cubed_windowed(kind, p, data):
+    d, m, msub = 3, 16, 4
+    mesh, prob = _gpu(d, m, p, kind, data)
+    ncomp = 1 if kind == OM.OBSTACLE else d
+    npc = ncomp * mesh.P ** d
+    log("3-D 16^3", kind, "p", p, "n_u", mesh.n_u, "n_psi", mesh.n_psi)
+    rng = np.random.default_rng(202)
+    psi = 0.6 * rng.standard_normal(mesh.n_psi)
+    alpha, beta = 8.0, 1e-3
+    # x supported on cells 0..2 in every direction
+    x = np.zeros(mesh.n_u + mesh.n_psi)
+    wu = _window_u(d, p, m, 3)
+    x[wu] = rng.standard_normal(wu.size)
+    wc = _cell_map(d, m, 3)
+    for c in wc:
+        x[mesh.n_u + c * npc: mesh.n_u + (c + 1) * npc] = rng.standard_normal(npc)
+    om, sysm = _oracle(d, m, msub, p, kind, data)
+    umap = _u_map(d, p, m, msub)
+    cmap = _cell_map(d, m, msub)
+    pidx = (cmap[:, None] * npc + np.arange(npc)[None, :]).reshape(-1)
+    psi_s = psi[pidx]
+    yu_o, yp_o = precond.apply_G(sysm, psi_s, alpha, beta, x[umap], x[mesh.n_u + pidx])
+    for prec, dt, tol in ((0, torch.float64, 1e-12), (1, torch.float32, 2e-5)):
+        prob.op_setup(_dev(psi), alpha, beta, precision=prec)
+        y = torch.zeros(mesh.n_u + mesh.n_psi, dtype=dt, device="cuda")
+        prob.op_apply_G(_dev(x, dt), y)
+        yg = y.double().cpu().numpy()
+        e_u, e_p = rel(yg[umap], yu_o), rel(yg[mesh.n_u + pidx], yp_o)
+        # nothing outside the box
+        mask = np.ones(mesh.n_u + mesh.n_psi, bool)
+        mask[umap] = False
+        mask[mesh.n_u + pidx] = False
+        log("  G prec", prec, "window rel", e_u, e_p, "outside max", np.abs(yg[mask]).max())
+        assert e_u < tol and e_p < tol
+        assert np.abs(yg[mask]).max() <= tol * np.abs(yg).max()
+    # preconditioner (FP64)
+    prob.op_setup(_dev(psi), alpha, beta, precision=0)
+    r = rng.standard_normal(mesh.n_u + mesh.n_psi)
+    z = torch.zeros_like(_dev(r))
+    prob.op_apply_prec(_dev(r), z)
+    zz = z.clone()
+    zz[mesh.n_u:] = 0
+    y = torch.zeros_like(z)
+    prob.op_apply_G(zz, y)
+    assert rel(y[:mesh.n_u].cpu().numpy(), r[:mesh.n_u]) < 1e-10
+    om2, sys2 = _oracle(d, m, 2, p, kind, data)
+    cm2 = _cell_map(d, m, 2)
+    p2 = (cm2[:, None] * npc + np.arange(npc)[None, :]).reshape(-1)
+    _check_psi_block_cells(sys2, psi[p2], alpha, beta, r, z.cpu().numpy(), mesh.n_u,
+                           cells=np.arange(om2.n_cells), npc=npc, cell_map=cm2)

@@ -189,3 +189,25 @@ def test_residual_jacobian_consistency(d, p, kind):
     assert np.linalg.norm(fd - Gv) <= 1e-8 * np.linalg.norm(Gv)
     # G is symmetric (GL quadrature keeps D_psi symmetric)
     assert abs(G - G.T).max() < 1e-12 * abs(G).max()
+
+
+@pytest.mark.parametrize("kind", [M.OBSTACLE, M.GRADIENT])
+def test_schur_hat_cells_are_the_blocks_of_schur_hat(kind):
+    # the per-cell accessor used by the full-size GPU checks must reproduce the
+    # diagonal blocks of the (pinned) global S_hat, and S_hat must vanish
+    # outside them
+    om = M.TensorMesh([np.array([0, .3, .55, 1.0]), np.array([0, .4, 1.0])], 4, kind)
+    f, phi = W.w2d(0)
+    xo = om.quadrature_points()
+    sysm = assemble.System(om, f(xo), np.abs(phi(xo)) + 0.1)
+    rng = np.random.default_rng(3)
+    psi = 0.7 * rng.standard_normal(om.n_psi)
+    S = precond.schur_hat(sysm, psi, 2.5, 1e-3).toarray()
+    cells = np.arange(om.n_cells)
+    blocks = precond.schur_hat_cells(sysm, psi, 2.5, 1e-3, cells)
+    mask = np.zeros_like(S, dtype=bool)
+    for c, B in zip(cells, blocks):
+        pg = om.psi_dofs(int(c))
+        assert np.allclose(S[np.ix_(pg, pg)], B, rtol=1e-12, atol=1e-12 * np.abs(S).max())
+        mask[np.ix_(pg, pg)] = True
+    assert np.abs(S[~mask]).max() <= 1e-12 * np.abs(S).max()
