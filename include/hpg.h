@@ -73,8 +73,9 @@ const char* hpg_last_error(void);
  * dim: 1..3.  ncells[k]: cells in direction k (>= 1).  breaks: NULL for
  * uniform cells on (0,1), else breaks[k] points to ncells[k]+1 strictly
  * increasing values with breaks[k][0] = 0 and breaks[k][ncells[k]] = 1.
- * p: partial degree; constraint: HPG_OBSTACLE or HPG_GRADIENT.
- * Inputs are copied; the handle is freed with hpg_destroy_mesh.
+ * p: partial degree (obstacle 2..24, gradient 1..24); ncells[k] * p >= 2,
+ * so that every direction has an interior u unknown; constraint:
+ * HPG_OBSTACLE or HPG_GRADIENT.  Inputs are copied; the handle is freed with hpg_destroy_mesh.
  * Errors: HPG_ERR_INVALID_ARG for any out-of-range argument. */
 hpg_status hpg_create_mesh(int dim, const int32_t* ncells, const double* const* breaks,
                            int32_t p, int32_t constraint, hpg_mesh** out);

@@ -96,6 +96,11 @@ hpg_status hpg_create_mesh(int dim, const int32_t* ncells, const double* const* 
                     }
             }
             M.n1[k] = ncells[k] * p - 1;
+            if (M.n1[k] < 1) {
+                // only p = 1 on one cell: the H^1_0 space in that direction is empty
+                delete m;
+                fail(HPG_ERR_INVALID_ARG, "ncells * p must be at least 2 in every direction");
+            }
         }
         M.n_cells = 1;
         M.n_u = 1;

@@ -223,6 +223,114 @@ __device__ inline void gather_u(const Geo& g, const T* __restrict__ xu, T* buf, 
     }
 }
 
+// D block of one weight field on one cell: out[a * ldo + b] (+)= sum_q w(q)
+// V_a(q) V_b(q), a, b in [0, P^d), sum-factorised direction by direction
+// (T1: q^(d-1) P^2, T2: q P^4 (d = 3) of work space)
+template <int D>
+__device__ inline void d_block(const double* w, const double* V, int P, int q, double* T1,
+                               double* T2, double* out, int ldo) {
+    const int PP = P * P;
+    if (D == 1) {
+        for (int e = threadIdx.x; e < PP; e += blockDim.x) {
+            const int a = e / P, b = e % P;
+            double s = 0.0;
+            for (int j = 0; j < q; ++j) s += w[j] * V[j * P + a] * V[j * P + b];
+            out[a * ldo + b] = s;
+        }
+        __syncthreads();
+    } else if (D == 2) {
+        for (int e = threadIdx.x; e < q * PP; e += blockDim.x) {
+            const int q2 = e / PP, ab = e % PP, a1 = ab / P, b1 = ab % P;
+            double s = 0.0;
+            for (int j = 0; j < q; ++j) s += w[q2 * q + j] * V[j * P + a1] * V[j * P + b1];
+            T1[e] = s;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+            const int ab2 = e / PP, ab1 = e % PP;
+            const int a2 = ab2 / P, b2 = ab2 % P, a1 = ab1 / P, b1 = ab1 % P;
+            double s = 0.0;
+            for (int j = 0; j < q; ++j) s += V[j * P + a2] * V[j * P + b2] * T1[j * PP + ab1];
+            out[(a1 + P * a2) * ldo + (b1 + P * b2)] = s;
+        }
+        __syncthreads();
+    } else {
+        for (int e = threadIdx.x; e < q * q * PP; e += blockDim.x) {
+            const int q32 = e / PP, ab = e % PP, a1 = ab / P, b1 = ab % P;
+            double s = 0.0;
+            for (int j = 0; j < q; ++j) s += w[q32 * q + j] * V[j * P + a1] * V[j * P + b1];
+            T1[e] = s;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < q * PP * PP; e += blockDim.x) {
+            const int q3 = e / (PP * PP), rr = e % (PP * PP), ab2 = rr / PP, ab1 = rr % PP;
+            const int a2 = ab2 / P, b2 = ab2 % P;
+            double s = 0.0;
+            for (int j = 0; j < q; ++j)
+                s += V[j * P + a2] * V[j * P + b2] * T1[(q3 * q + j) * PP + ab1];
+            T2[e] = s;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < PP * PP * PP; e += blockDim.x) {
+            const int ab3 = e / (PP * PP), rr = e % (PP * PP), ab2 = rr / PP, ab1 = rr % PP;
+            const int a3 = ab3 / P, b3 = ab3 % P, a2 = ab2 / P, b2 = ab2 % P, a1 = ab1 / P,
+                      b1 = ab1 % P;
+            double s = 0.0;
+            for (int j = 0; j < q; ++j) s += V[j * P + a3] * V[j * P + b3] * T2[(j * PP + ab2) * PP + ab1];
+            out[(a1 + P * (a2 + P * a3)) * ldo + (b1 + P * (b2 + P * b3))] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// d = 3 form of d_block without the q P^4 work space: the last two
+// directions are summed together (q^2 terms per entry instead of q)
+__device__ inline void d_block3_direct(const double* w, const double* V, int P, int q,
+                                       double* T1, double* out, int ldo) {
+    const int PP = P * P;
+    for (int e = threadIdx.x; e < q * q * PP; e += blockDim.x) {
+        const int q32 = e / PP, ab = e % PP, a1 = ab / P, b1 = ab % P;
+        double s = 0.0;
+        for (int j = 0; j < q; ++j) s += w[q32 * q + j] * V[j * P + a1] * V[j * P + b1];
+        T1[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < PP * PP * PP; e += blockDim.x) {
+        const int ab3 = e / (PP * PP), rr = e % (PP * PP), ab2 = rr / PP, ab1 = rr % PP;
+        const int a3 = ab3 / P, b3 = ab3 % P, a2 = ab2 / P, b2 = ab2 % P, a1 = ab1 / P,
+                  b1 = ab1 % P;
+        double s = 0.0;
+        for (int j3 = 0; j3 < q; ++j3) {
+            double t = 0.0;
+            for (int j2 = 0; j2 < q; ++j2)
+                t += V[j2 * P + a2] * V[j2 * P + b2] * T1[(j3 * q + j2) * PP + ab1];
+            s += V[j3 * P + a3] * V[j3 * P + b3] * t;
+        }
+        out[(a1 + P * (a2 + P * a3)) * ldo + (b1 + P * (b2 + P * b3))] = s;
+    }
+    __syncthreads();
+}
+
+// In-place inverse of one SPD n x n block (row-major, any memory space) by
+// Gauss-Jordan elimination without pivoting; cr: 2n doubles of LDS for the
+// pivot column and row.  Every thread of the block takes part.
+__device__ inline void gauss_jordan_spd(double* Dm, int n, double* cr) {
+    for (int k = 0; k < n; ++k) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            cr[i] = Dm[(int64_t)i * n + k];
+            cr[n + i] = Dm[(int64_t)k * n + i];
+        }
+        __syncthreads();
+        const double ip = 1.0 / cr[k];
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            const double rk = (j == k ? 1.0 : cr[n + j]) * ip;
+            Dm[e] = (i == k) ? rk : ((j == k ? 0.0 : Dm[e]) - cr[i] * rk);
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, int D>
 __device__ inline T cell_jac(const Geo& g, const T* const* hw, int64_t cell, T* hk) {
     T J = 1;

@@ -95,8 +95,13 @@ bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha,
                  const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
                  const double* F, const double* Phi, T* yu, T* ypsi, double* partial,
                  const int* done, int mode, hipStream_t s, const KernelEvents* ev = nullptr);
+// Obstacle setup: LDS bytes per cell with the block in LDS; and of the
+// variants that form and invert the block in s64 (global memory), with or
+// without (d = 3) the q P^4 contraction intermediate in LDS.
+enum { SETUP_LDS = 0, SETUP_HBM_T2 = 1, SETUP_HBM = 2 };
 size_t setup_smem_per_cell(const Geo& g);
-void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* psi,
+size_t setup_big_smem(const Geo& g, bool t2);
+void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
                   float* om32, double* s64, float* s32, hipStream_t s);
 template <typename T>

@@ -394,6 +394,82 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
 }
 
 // ---------------------------------------------------------------------------
+// The same setup for blocks too large for LDS (high P^d): one cell per block,
+// -S_hat_K formed and inverted in place in its slot of s64 (global memory);
+// LDS holds the weights, the contraction work space and the pivot row.
+// T2: the d = 3 contraction keeps its q P^4 intermediate (else d_block3_direct).
+template <int D, bool T2S>
+__global__ __launch_bounds__(256) void k_setup_big(Geo g, PsiTabs<double> tb,
+                                                   const double* __restrict__ psi, double alpha,
+                                                   double beta, const double* __restrict__ Cmat,
+                                                   const int* __restrict__ cclass,
+                                                   double* __restrict__ omega64,
+                                                   float* __restrict__ omega32,
+                                                   double* __restrict__ s64,
+                                                   float* __restrict__ s32) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    const int n = g.Pd, q = g.q, P = g.P, Qd = g.Qd, S = g.S;
+    const int sT1 = (D == 1) ? 1 : ((D == 2) ? q * P * P : q * q * P * P);
+    const int sT2 = (D == 3 && T2S) ? q * P * P * P * P : 1;
+    const int64_t cell = blockIdx.x;
+    double* bA = sm;
+    double* bB = sm + S;
+    double* T1 = sm + 2 * S;
+    double* T2 = T1 + sT1;
+    double* cr = T2 + sT2;
+    double* Dm = s64 + cell * (int64_t)n * n;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) bA[a] = psi[cell * n + a];
+    __syncthreads();
+    double* vq = contract_all<double, D>(bA, bB, S, 1, P, q, tb.Vpsi, P, false);
+    double hk[3];
+    const double J = cell_jac<double, D>(g, tb.h, cell, hk);
+    for (int j = threadIdx.x; j < Qd; j += blockDim.x) {
+        int jj[3] = {j % q, (j / q) % q, j / (q * q)};
+        double wq = J;
+        for (int k = 0; k < D; ++k) wq *= tb.w[jj[k]];
+        const double arg = -vq[j];
+        const double om = wq * exp(arg < 700.0 ? arg : 700.0);
+        vq[j] = om;
+        if (omega64) omega64[cell * Qd + j] = om;
+        if (omega32) omega32[cell * Qd + j] = (float)om;
+    }
+    __syncthreads();
+    if (D == 3 && !T2S)
+        d_block3_direct(vq, tb.Vpsi, P, q, T1, Dm, n);
+    else
+        d_block<D>(vq, tb.Vpsi, P, q, T1, T2, Dm, n);
+    // + beta M_K + C_K / alpha
+    const double ia = 1.0 / alpha;
+    const double* C = Cmat + (int64_t)cclass[cell] * n * n;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        double v = Dm[e] + ia * C[e];
+        if (i == j) {
+            int aa[3] = {i % P, (i / P) % P, i / (P * P)};
+            double md = J;
+            for (int k = 0; k < D; ++k) md *= tb.Mdiag[aa[k]];
+            v += beta * md;
+        }
+        Dm[e] = v;
+    }
+    __syncthreads();
+    gauss_jordan_spd(Dm, n, cr);
+    // symmetrise: the thread of (i, j), j >= i, owns both mirror entries
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        if (j < i) continue;
+        const double v = 0.5 * (Dm[(int64_t)i * n + j] + Dm[(int64_t)j * n + i]);
+        Dm[(int64_t)i * n + j] = v;
+        Dm[(int64_t)j * n + i] = v;
+        if (s32) {
+            s32[cell * (int64_t)n * n + (int64_t)i * n + j] = (float)v;
+            s32[cell * (int64_t)n * n + (int64_t)j * n + i] = (float)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // psi-block of the preconditioner: z_psi = (-S_hat_K)^{-1} r_psi per cell.
 // A block copies the contiguous inverse blocks of cpb cells into LDS with
 // coalesced loads, then one thread per (cell, row) forms the row product
@@ -849,9 +925,29 @@ size_t setup_smem_per_cell(const Geo& g) {
     return (size_t)(2 * g.S + sT1 + sT2 + n * n + 2 * n) * sizeof(double);
 }
 
-void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* psi,
+size_t setup_big_smem(const Geo& g, bool t2) {
+    const int n = g.Pd, q = g.q, P = g.P;
+    const int sT1 = (g.d == 1) ? 1 : ((g.d == 2) ? q * P * P : q * q * P * P);
+    const int sT2 = (g.d == 3 && t2) ? q * P * P * P * P : 1;
+    return (size_t)(2 * g.S + sT1 + sT2 + 2 * n) * sizeof(double);
+}
+
+void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
                   float* om32, double* s64, float* s32, hipStream_t s) {
+    if (big) {
+        const bool t2 = big == SETUP_HBM_T2;
+        const size_t shm = setup_big_smem(g, t2);
+#define HPG_SB(DD, TT)                                                                      \
+    hipLaunchKernelGGL((k_setup_big<DD, TT>), dim3((unsigned)g.n_cells), dim3(256), shm, s, \
+                       g, tb, psi, alpha, beta, C, cclass, om64, om32, s64, s32)
+        if (g.d == 1) HPG_SB(1, true);
+        else if (g.d == 2) HPG_SB(2, true);
+        else if (t2) HPG_SB(3, true);
+        else HPG_SB(3, false);
+#undef HPG_SB
+        return;
+    }
     dim3 grid(nblk(g.n_cells, cpb)), blk(256);
     size_t shm = setup_smem_per_cell(g) * cpb;
 #define HPG_S(DD)                                                                        \

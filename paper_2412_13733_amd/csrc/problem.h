@@ -108,6 +108,7 @@ struct Problem {
     DBuf PhiQ;                             // gradient: phi at the Gauss points (FP64)
     bool gradient = false;                 // constraint |grad u| <= phi
     bool prec_big = false;                 // psi blocks streamed from HBM (too large for LDS)
+    int setup_mode = 0;                    // obstacle Schur blocks: dev::SETUP_LDS / _HBM_T2 / _HBM
     double normF = 1.0, normPhi = 1.0;
     // linearisation (hpg_op_setup / Newton setup)
     double alpha = 1.0, beta = 0.0;

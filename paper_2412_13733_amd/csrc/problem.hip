@@ -425,20 +425,28 @@ void Problem::build(const Mesh& mesh, int dev_) {
             fail(HPG_ERR_INVALID_ARG, "(p+1)^d too large for the gradient psi-side kernel");
     } else {
         cpb_psi = pick_cpb(5 * S, 8, geo.Qd, std::min<size_t>(48 * 1024, lds_max));
+        // Schur blocks: formed and inverted in LDS when one fits, else in place
+        // in global memory (one cell per workgroup)
         const size_t setup_cell = dev::setup_smem_per_cell(geo);
-        if (setup_cell > lds_max)
-            fail(HPG_ERR_INVALID_ARG, "P^d too large for the in-LDS Schur block inverse");
-        cpb_setup = std::max(1, std::min(256 / std::max(1, geo.Pd), (int)(lds_max / setup_cell)));
-        while (cpb_setup > 1 && setup_cell * cpb_setup > std::min<size_t>(64 * 1024, lds_max))
-            --cpb_setup;
+        setup_mode = dev::SETUP_LDS;
+        if (setup_cell > lds_max) {
+            setup_mode = dev::setup_big_smem(geo, true) <= lds_max ? dev::SETUP_HBM_T2
+                                                                   : dev::SETUP_HBM;
+            if (dev::setup_big_smem(geo, false) > lds_max)
+                fail(HPG_ERR_INVALID_ARG, "P^d too large for the Schur block setup");
+        }
+        cpb_setup = 1;
+        if (!setup_mode) {
+            cpb_setup = std::max(1, std::min(256 / std::max(1, geo.Pd), (int)(lds_max / setup_cell)));
+            while (cpb_setup > 1 && setup_cell * cpb_setup > std::min<size_t>(64 * 1024, lds_max))
+                --cpb_setup;
+        }
     }
     // psi-block preconditioner: ~16 KB of inverse blocks per block of 256
     // threads; blocks beyond 48 KB are streamed from HBM one cell per block
     prec_big = (size_t)(nblk * nblk + nblk) * 8 > 48 * 1024;
     cpb_prec = std::max(1, (int)(2048 / std::max<int64_t>(1, nblk * nblk)));
     while (cpb_prec > 1 && (size_t)cpb_prec * (nblk * nblk + nblk) * 8 > 48 * 1024) --cpb_prec;
-    if (prec_big && !gradient)
-        fail(HPG_ERR_INVALID_ARG, "P^d too large for the LDS-staged preconditioner blocks");
     // 1-D rows per direction
     for (int k = 0; k < 3; ++k) {
         Rows1D R;
@@ -738,8 +746,9 @@ void Problem::ensure_linearisation_buffers() {
     } else {
         om32.alloc(nq * sizeof(float));
         sinv32.alloc(ns * sizeof(float));
-        // gradient blocks too large for LDS are formed and inverted in FP64 in place
-        if (gradient && dev::setup_grad_in_hbm(geo)) sinv64.alloc(ns * sizeof(double));
+        // blocks too large for LDS are formed and inverted in FP64 in place
+        if ((gradient && dev::setup_grad_in_hbm(geo)) || (!gradient && setup_mode))
+            sinv64.alloc(ns * sizeof(double));
     }
 }
 
@@ -815,10 +824,11 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
                                (prec == HPG_FP64 || hbm) ? sinv64.as<double>() : nullptr,
                                prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
     } else {
-        dev::launch_setup(geo, tab64.view(), cpb_setup, d_psi, alpha, beta, C.as<double>(),
-                          cclass.as<int>(), prec == HPG_FP64 ? om64.as<double>() : nullptr,
+        dev::launch_setup(geo, tab64.view(), cpb_setup, setup_mode, d_psi, alpha, beta,
+                          C.as<double>(), cclass.as<int>(),
+                          prec == HPG_FP64 ? om64.as<double>() : nullptr,
                           prec == HPG_FP64 ? nullptr : om32.as<float>(),
-                          prec == HPG_FP64 ? sinv64.as<double>() : nullptr,
+                          (prec == HPG_FP64 || setup_mode) ? sinv64.as<double>() : nullptr,
                           prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
     }
     tstop("setup", s);

@@ -63,6 +63,9 @@ def test_invalid_arguments_are_rejected():
         hpg.Mesh(1, [2], 3, breaks=[np.array([0.0, 0.7, 0.6])])   # not increasing
     with pytest.raises(hpg.HpgError):
         hpg.Mesh(1, [2], 3, breaks=[np.array([0.0, 0.5, 2.0])])   # must end at 1
+    with pytest.raises(hpg.HpgError):
+        hpg.Mesh(2, [1, 3], 1, constraint=hpg.GRADIENT)   # p = 1 on one cell: no u unknown
+    assert hpg.Mesh(1, [2], 1, constraint=hpg.GRADIENT).n_u == 1
     m = hpg.Mesh(1, [3], 2, constraint=hpg.GRADIENT)
     assert m.P == 2 and m.n_psi == 3 * 2
 
