@@ -13,9 +13,13 @@ What it computes (Papadopoulos, "Hierarchical proximal Galerkin", arXiv
                  spectral-Galerkin Y_n and a Gauss-Legendre rule (Sec. 3).
 * ``mesh``     - tensor-product meshes, the continuous space U_{h,p} and the
                  discontinuous space Psi_{h,p} with their DOF numbering (Sec. 3).
+* ``hpmesh``   - the same with one degree per cell (obstacle), conforming by
+                 the minimum rule on shared entities.
 * ``assemble`` - the sparse matrices A, B, M_psi, the load vectors and the
                  nonlinear terms of eq. (pG) / eq. (pG:gradient) and their
                  Jacobian blocks D_psi, E_beta (Sec. 4.1-4.3).
+* ``precond``  - the block preconditioner diag(alpha A, -S_hat) (Sec. 4.4-4.6)
+                 and its block-Jacobi A-block on hp meshes.
 * ``lvpp``     - the latent-variable proximal point loop with Newton and a
                  direct sparse LU of the full saddle matrix G of eq.
                  (pG-matrix) (Sec. 2, Sec. 4, remark on sparse LU in Sec. 4.4).

@@ -30,10 +30,12 @@ EXP_CAP = 700.0
 
 
 class RefTables:
-    """1-D reference tables at the q Gauss-Legendre nodes."""
+    """1-D reference tables at the q Gauss-Legendre nodes (degree p, P psi
+    modes per direction); from a uniform mesh or given explicitly."""
 
-    def __init__(self, mesh):
-        p, P, q = mesh.p, mesh.P, mesh.q
+    def __init__(self, mesh=None, p=None, P=None, q=None):
+        if mesh is not None:
+            p, P, q = mesh.p, mesh.P, mesh.q
         self.y, self.w = basis.gauss_legendre(q)
         V, D = basis.u_local(p, self.y)
         self.Vu = V.T                        # (q, p+1)
@@ -84,7 +86,8 @@ class System:
 
     def __init__(self, mesh, f_qp, phi_qp):
         self.mesh = mesh
-        self.ref = RefTables(mesh)
+        self._refs = {}
+        self.ref = None if getattr(mesh, "hp", False) else RefTables(mesh)
         f_qp = np.asarray(f_qp, dtype=np.float64).reshape(-1)
         phi_qp = np.asarray(phi_qp, dtype=np.float64).reshape(-1)
         if f_qp.size != mesh.n_qp or phi_qp.size != mesh.n_qp:
@@ -92,20 +95,28 @@ class System:
         self.f_qp, self.phi_qp = f_qp, phi_qp
         self._assemble()
 
+    def ref_for(self, cno):
+        """Reference tables of a cell (cached per degree)."""
+        key = self.mesh.cell_p(cno)
+        if key not in self._refs:
+            self._refs[key] = RefTables(p=key[0], P=key[1], q=key[2])
+        return self._refs[key]
+
     def _assemble(self):
-        mesh, ref = self.mesh, self.ref
+        mesh = self.mesh
         d, nc = mesh.d, mesh.ncomp
-        Q = mesh.q ** d
         cA, cB, cMu, cMpsi, cEg = _Coo(), _Coo(), _Coo(), _Coo(), _Coo()
         F = np.zeros(mesh.n_u)
         Phi = np.zeros(mesh.n_psi)
         self.cells = []
+        self.cell_refs = []
         for cno, cidx in mesh.cells():
+            ref = self.ref_for(cno)
             W, Vu, Gu, Vpsi, hs = _cell_tables(mesh, ref, cidx)
             ug = mesh.u_dofs(cidx)
             pg = mesh.psi_dofs(cno)
-            fq = self.f_qp[cno * Q:(cno + 1) * Q]
-            phq = self.phi_qp[cno * Q:(cno + 1) * Q]
+            fq = self.f_qp[mesh.qp_slice(cno)]
+            phq = self.phi_qp[mesh.qp_slice(cno)]
             A_K = sum(G.T @ (W[:, None] * G) for G in Gu)
             cA.add(ug, ug, A_K)
             cMu.add(ug, ug, Vu.T @ (W[:, None] * Vu))
@@ -134,6 +145,7 @@ class System:
                 Phi[pg] = np.tile(Vpsi.T @ (W * phq), nc)
                 assert nP == mesh.P ** d
             self.cells.append((cno, cidx, W, Vpsi, pg, phq))
+            self.cell_refs.append(ref)
         self.A = cA.csr((mesh.n_u, mesh.n_u))
         self.B = cB.csr((mesh.n_u, mesh.n_psi))
         self.Mu = cMu.csr((mesh.n_u, mesh.n_u))
@@ -147,21 +159,21 @@ class System:
 
     # ---- nonlinear terms ---------------------------------------------------
     def psi_at_points(self, psi):
-        """psi_h at every quadrature point, shape (n_cells, ncomp, Q)."""
+        """psi_h at every quadrature point, shape (n_cells, ncomp, Q) (a list
+        of (ncomp, Q_K) arrays when the degree varies by cell)."""
         mesh = self.mesh
-        nP = mesh.P ** mesh.d
         out = []
         for cno, cidx, W, Vpsi, pg, phq in self.cells:
-            c = psi[pg].reshape(mesh.ncomp, nP)
+            c = psi[pg].reshape(mesh.ncomp, Vpsi.shape[1])
             out.append(c @ Vpsi.T)
-        return np.array(out)
+        return out if getattr(mesh, "hp", False) else np.array(out)
 
     def nonlinear(self, psi):
         """Obstacle: E(psi) of eq. (pG).  Gradient: N(psi) of eq. (pG:gradient)."""
         mesh = self.mesh
         out = np.zeros(mesh.n_psi)
-        nP = mesh.P ** mesh.d
         for cno, cidx, W, Vpsi, pg, phq in self.cells:
+            nP = Vpsi.shape[1]
             c = psi[pg].reshape(mesh.ncomp, nP)
             pq = c @ Vpsi.T                      # (ncomp, Q)
             if mesh.kind == OBSTACLE:
@@ -177,9 +189,9 @@ class System:
         """Jacobian block D_psi (sparse, cell-block diagonal)."""
         mesh = self.mesh
         coo = _Coo()
-        nP = mesh.P ** mesh.d
         nc = mesh.ncomp
         for cno, cidx, W, Vpsi, pg, phq in self.cells:
+            nP = Vpsi.shape[1]
             c = psi[pg].reshape(nc, nP)
             pq = c @ Vpsi.T
             if mesh.kind == OBSTACLE:
@@ -216,12 +228,11 @@ class System:
         return float(np.sqrt(max(u @ (self.Mu @ u), 0.0)))
 
     def u_at_points(self, u):
-        mesh, ref = self.mesh, self.ref
-        Q = mesh.q ** mesh.d
+        mesh = self.mesh
         out = np.zeros(mesh.n_qp)
         for cno, cidx in mesh.cells():
-            Vu = kron_dirs([ref.Vu] * mesh.d)
+            Vu = kron_dirs([self.ref_for(cno).Vu] * mesh.d)
             ug = mesh.u_dofs(cidx)
             loc = np.where(ug >= 0, u[np.maximum(ug, 0)], 0.0)
-            out[cno * Q:(cno + 1) * Q] = Vu @ loc
+            out[mesh.qp_slice(cno)] = Vu @ loc
         return out

@@ -98,6 +98,14 @@ class TensorMesh:
         s = self.psi_per_cell
         return np.arange(cell_no * s, (cell_no + 1) * s, dtype=np.int64)
 
+    def cell_p(self, cell_no):
+        """(p, P, q) of a cell: the same on every cell of this mesh."""
+        return self.p, self.P, self.q
+
+    def qp_slice(self, cell_no):
+        Q = self.q ** self.d
+        return slice(cell_no * Q, (cell_no + 1) * Q)
+
     # ---- quadrature --------------------------------------------------------
     def reference_rule(self):
         return basis.gauss_legendre(self.q)

@@ -13,6 +13,12 @@ complement S = -(D_psi + E_beta + B^T A_alpha^{-1} B) is replaced by
 
 A symmetric Krylov method needs a positive definite preconditioner, so the
 operator returned is the SPD form diag(alpha A, -S_hat) (reading Q12).
+
+With one degree per cell (``HpMesh``) the u space is no longer a tensor
+product and the A-block is replaced (reading) by the block-Jacobi operator
+sum_g R_g^T (alpha A_gg)^{-1} R_g over the groups of ``mesh.u_groups()``: all
+vertex unknowns together (the Q1 space of the mesh) and each edge, face and
+cell-interior entity on its own.  It is SPD and exact on each group.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -24,10 +30,10 @@ from .mesh import OBSTACLE
 
 def phi_blocks(system, alpha):
     """(A_hat_alpha, B_hat) of eq. (schur-preconditioner), sparse, on Phi_h."""
-    mesh, ref = system.mesh, system.ref
+    mesh = system.mesh
     cA, cB = _Coo(), _Coo()
-    nY = mesh.P ** mesh.d
     for cno, cidx, W, Vpsi, pg, phq in system.cells:
+        ref = system.cell_refs[cno]
         hs = mesh.cell_widths(cidx)
         VY = kron_dirs([ref.Y] * mesh.d)
         GY = []
@@ -35,10 +41,10 @@ def phi_blocks(system, alpha):
             tabs = [ref.Y] * mesh.d
             tabs[k] = ref.dY * (2.0 / hs[k])
             GY.append(kron_dirs(tabs))
-        eta = np.arange(cno * nY, (cno + 1) * nY)
+        eta = pg   # Phi_h carries as many functions per cell as Psi_h (P_K^d)
         cA.add(eta, eta, alpha * sum(G.T @ (W[:, None] * G) for G in GY))
         cB.add(eta, pg, VY.T @ (W[:, None] * Vpsi))
-    n_eta = mesh.n_cells * nY
+    n_eta = mesh.n_psi
     return cA.csr((n_eta, n_eta)).tocsc(), cB.csr((n_eta, mesh.n_psi)).tocsc()
 
 
@@ -60,13 +66,12 @@ def schur_hat_cells(system, psi, alpha, beta, cells):
     if mesh.kind == OBSTACLE:
         Ahat, Bhat = phi_blocks(system, alpha)
         Ahat, Bhat = Ahat.tocsr(), Bhat.tocsr()
-    nY = mesh.P ** mesh.d
     out = []
     for c in cells:
         pg = mesh.psi_dofs(int(c))
         blk = -D[pg][:, pg].toarray()
         if mesh.kind == OBSTACLE:
-            eta = np.arange(int(c) * nY, (int(c) + 1) * nY)
+            eta = pg
             Bk = Bhat[eta][:, pg].toarray()
             Ak = Ahat[eta][:, eta].toarray()
             blk = blk - Bk.T @ np.linalg.solve(Ak, Bk)
@@ -74,9 +79,21 @@ def schur_hat_cells(system, psi, alpha, beta, cells):
     return out
 
 
+def a_block(system, alpha, r_u):
+    """z_u: (alpha A)^{-1} r_u, or the block-Jacobi operator on hp meshes."""
+    if not getattr(system.mesh, "hp", False):
+        return spla.spsolve((alpha * system.A).tocsc(), r_u)
+    A = system.A.tocsr()
+    z = np.zeros_like(r_u)
+    for g in system.mesh.u_groups():
+        if g.size:
+            z[g] = np.linalg.solve(alpha * A[g][:, g].toarray(), r_u[g])
+    return z
+
+
 def apply_prec(system, psi, alpha, beta, r_u, r_psi):
-    """z = diag(alpha A, -S_hat)^{-1} r (direct solves)."""
-    zu = spla.spsolve((alpha * system.A).tocsc(), r_u)
+    """z = diag(alpha A, -S_hat)^{-1} r (direct solves; A-block as a_block)."""
+    zu = a_block(system, alpha, r_u)
     S = schur_hat(system, psi, alpha, beta)
     zpsi = np.linalg.solve(-S.toarray(), r_psi)
     return zu, zpsi
