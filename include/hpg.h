@@ -73,12 +73,25 @@ const char* hpg_last_error(void);
  * dim: 1..3.  ncells[k]: cells in direction k (>= 1).  breaks: NULL for
  * uniform cells on (0,1), else breaks[k] points to ncells[k]+1 strictly
  * increasing values with breaks[k][0] = 0 and breaks[k][ncells[k]] = 1.
- * p: partial degree (obstacle 2..24, gradient 1..24); ncells[k] * p >= 2,
- * so that every direction has an interior u unknown; constraint:
- * HPG_OBSTACLE or HPG_GRADIENT.  Inputs are copied; the handle is freed with hpg_destroy_mesh.
+ * degree: NULL for one partial degree p on every cell (obstacle 2..24,
+ * gradient 1..24; ncells[k] * p >= 2, so that every direction has an
+ * interior u unknown).  Otherwise one degree per cell (2..24, cells numbered
+ * with direction 0 fastest; obstacle constraint only; p is then ignored and
+ * hpg_get_mesh_info reports the largest degree).  With per-cell degrees the u
+ * space is the conforming one in which every vertex, edge, face and cell
+ * interior carries the smallest degree of the cells containing it (the
+ * hierarchical hats and bubbles of Sec. 3 are shared across cells); its
+ * unknowns are numbered entity by entity: entities are the points of the
+ * doubled grid (2 ncells[k] + 1 per direction, even = vertex coordinate, odd
+ * = cell interval), direction 0 fastest, and inside an entity by the bubble
+ * modes of its odd directions (first odd direction fastest, 0..p_E - 2).
+ * psi holds (p_K - 1)^dim Legendre values per cell (cell-major) and each
+ * cell has (p_K + 1)^dim Gauss points (cell-major, as hpg_quadrature_points
+ * returns them).  constraint: HPG_OBSTACLE or HPG_GRADIENT.
+ * Inputs are copied; the handle is freed with hpg_destroy_mesh.
  * Errors: HPG_ERR_INVALID_ARG for any out-of-range argument. */
 hpg_status hpg_create_mesh(int dim, const int32_t* ncells, const double* const* breaks,
-                           int32_t p, int32_t constraint, hpg_mesh** out);
+                           const int32_t* degree, int32_t p, int32_t constraint, hpg_mesh** out);
 void hpg_destroy_mesh(hpg_mesh* mesh);
 
 typedef struct hpg_mesh_info {

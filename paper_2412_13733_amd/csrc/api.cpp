@@ -48,7 +48,7 @@ extern "C" {
 const char* hpg_last_error(void) { return hpg::g_last_error.c_str(); }
 
 hpg_status hpg_create_mesh(int dim, const int32_t* ncells, const double* const* breaks,
-                           int32_t p, int32_t constraint, hpg_mesh** out) {
+                           const int32_t* degree, int32_t p, int32_t constraint, hpg_mesh** out) {
     return guarded([&]() -> hpg_status {
         if (!out) fail(HPG_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
@@ -56,6 +56,27 @@ hpg_status hpg_create_mesh(int dim, const int32_t* ncells, const double* const* 
         if (!ncells) fail(HPG_ERR_INVALID_ARG, "ncells is NULL");
         if (constraint != HPG_OBSTACLE && constraint != HPG_GRADIENT)
             fail(HPG_ERR_INVALID_ARG, "constraint must be HPG_OBSTACLE or HPG_GRADIENT");
+        int64_t ncell_total = 1;
+        for (int k = 0; k < dim; ++k) {
+            if (ncells[k] < 1 || ncells[k] > (1 << 20)) fail(HPG_ERR_INVALID_ARG, "ncells out of range");
+            ncell_total *= ncells[k];
+        }
+        std::vector<int32_t> deg;
+        int pmin = 0;
+        if (degree) {
+            // one degree per cell: p is the largest one
+            if (constraint != HPG_OBSTACLE)
+                fail(HPG_ERR_INVALID_ARG, "per-cell degrees: obstacle constraint only");
+            if (ncell_total > (int64_t)1 << 26) fail(HPG_ERR_INVALID_ARG, "too many cells");
+            deg.assign(degree, degree + ncell_total);
+            p = 0;
+            pmin = 1 << 30;
+            for (int32_t v : deg) {
+                if (v < 2 || v > 24) fail(HPG_ERR_INVALID_ARG, "per-cell degree outside 2..24");
+                p = std::max(p, v);
+                pmin = std::min(pmin, v);
+            }
+        }
         if (constraint == HPG_OBSTACLE && p < 2)
             fail(HPG_ERR_INVALID_ARG, "obstacle constraint needs p >= 2");
         if (constraint == HPG_GRADIENT && p < 1)
@@ -116,6 +137,16 @@ hpg_status hpg_create_mesh(int dim, const int32_t* ncells, const double* const* 
         M.n_psi = M.n_cells * M.psi_per_cell;
         M.n_qp = M.n_cells * M.Qd;
         M.ref.build(p, M.P, M.q);
+        if (degree) {
+            M.hp = true;
+            M.pmin = pmin;
+            M.deg = std::move(deg);
+            hp_number(M);
+            if (M.n_u >= ((int64_t)1 << 31) || M.n_psi >= ((int64_t)1 << 40)) {
+                delete m;
+                fail(HPG_ERR_INVALID_ARG, "mesh too large");
+            }
+        }
         *out = m;
         return HPG_OK;
     });
@@ -145,7 +176,33 @@ hpg_status hpg_quadrature_points(const hpg_mesh* mesh, double* xyz) {
     return guarded([&]() -> hpg_status {
         if (!mesh || !xyz) fail(HPG_ERR_INVALID_ARG, "NULL argument");
         const Mesh& M = mesh->M;
-        const int q = M.q, d = M.d;
+        const int d = M.d;
+        if (M.hp) {
+            // cell-major, each cell with its own q_K = p_K + 1 points per direction
+            std::vector<std::vector<double>> nodes(M.p + 2);
+            for (int64_t c = 0; c < M.n_cells; ++c) {
+                const int q = M.deg[c] + 1;
+                if (nodes[q].empty()) {
+                    std::vector<double> w;
+                    gauss_legendre(q, nodes[q], w);
+                }
+                int64_t t = c;
+                int cc[3] = {0, 0, 0};
+                for (int k = 0; k < d; ++k) {
+                    cc[k] = (int)(t % M.m[k]);
+                    t /= M.m[k];
+                }
+                const int64_t Qd = M.qp_off[c + 1] - M.qp_off[c];
+                for (int64_t j = 0; j < Qd; ++j) {
+                    int jj[3] = {(int)(j % q), (int)((j / q) % q), (int)(j / ((int64_t)q * q))};
+                    double* o = xyz + (M.qp_off[c] + j) * d;
+                    for (int k = 0; k < d; ++k)
+                        o[k] = M.breaks[k][cc[k]] + 0.5 * (nodes[q][jj[k]] + 1.0) * M.h(k, cc[k]);
+                }
+            }
+            return HPG_OK;
+        }
+        const int q = M.q;
         for (int64_t c = 0; c < M.n_cells; ++c) {
             int64_t t = c;
             int cc[3] = {0, 0, 0};

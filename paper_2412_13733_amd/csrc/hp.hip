@@ -1,0 +1,569 @@
+// Kernels for meshes with one degree per cell (obstacle constraint).
+//
+// The u space is the conforming space of the minimum rule (every vertex, edge,
+// face and cell interior carries the smallest degree of the cells containing
+// it), so it is no longer a tensor product and the operator is applied cell by
+// cell: a work item (a run of cells of equal degree p) gathers its local u
+// coefficients through a local -> global map (absent functions read as zero),
+// contracts them with the 1-D reference matrices of degree p along each
+// direction (stiffness A_K = sum_k J (2/h_k)^2 A1 (x) M1 ..., coupling
+// B_K = J (x) B1, paper Sec. 3-4), and writes one value per local function;
+// a second pass sums those values into each global unknown in a fixed order
+// (deterministic, no atomics).  The psi side (Bᵀ u, D_psi, E(psi), the Schur
+// blocks) is cell-local as in the uniform kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "dev_util.h"
+#include "kernels.h"
+
+namespace hpg {
+namespace dev {
+
+template <typename T>
+struct HpCellTabs {
+    const T *A1, *M1, *B1, *Vu, *Vpsi, *w, *Mdiag;
+};
+
+template <typename T>
+__device__ inline HpCellTabs<T> hp_tabs(const HpTabs<T>& tb, int p) {
+    const HpTabOff o = tb.off[p];
+    return {tb.base + o.A1, tb.base + o.M1,   tb.base + o.B1,   tb.base + o.Vu,
+            tb.base + o.Vpsi, tb.base + o.w, tb.base + o.Mdiag};
+}
+
+template <typename T, int D>
+__device__ inline T hp_jac(const HpGeo& g, const HpTabs<T>& tb, int64_t cell, T* hk) {
+    T J = 1;
+    int64_t c = cell;
+    for (int k = 0; k < D; ++k) {
+        const int ck = (int)(c % g.m[k]);
+        c /= g.m[k];
+        hk[k] = tb.h[k][ck];
+        J *= (T)0.5 * hk[k];
+    }
+    return J;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int D, int MODE>
+__global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha, T beta,
+                                                 const double* __restrict__ prm,
+                                                 const T* __restrict__ xu,
+                                                 const T* __restrict__ xpsi,
+                                                 const T* __restrict__ xpsi_prev,
+                                                 const T* __restrict__ omega,
+                                                 const double* __restrict__ Phi,
+                                                 T* __restrict__ yloc, T* __restrict__ ypsi,
+                                                 double* __restrict__ partial,
+                                                 const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[4];
+    if (done && *done) return;
+    if (prm) {
+        alpha = (T)prm[0];
+        beta = (T)prm[1];
+    }
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int SB = g.lds_elems;
+    T* bU = sm;            // local u coefficients
+    T* bX = sm + SB;       // psi coefficients (RES: psi - psi_prev)
+    T* bY = sm + 2 * SB;   // A_K x_K
+    T* bT = sm + 3 * SB;   // J B1^T x_K
+    T* bA = sm + 4 * SB;
+    T* bB = sm + 5 * SB;
+    double part = 0.0;
+    for (int it = blockIdx.x; it < g.n_items; it += gridDim.x) {
+        const int p = g.item_p[it], L = p + 1, P = p - 1, q = p + 1;
+        const int start = g.item_start[it], ncell = g.item_count[it];
+        int S = 1, Pd = 1;
+        for (int k = 0; k < D; ++k) {
+            S *= L;
+            Pd *= P;
+        }
+        const HpCellTabs<T> t = hp_tabs(tb, p);
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = e / S, l = e - ci * S;
+            const int64_t cell = g.order[start + ci];
+            const int gi = g.loc2glob[g.loc_off[cell] + l];
+            bU[ci * S + l] = gi >= 0 ? xu[gi] : (T)0;
+            bY[ci * S + l] = 0;
+        }
+        for (int e = threadIdx.x; e < ncell * Pd; e += blockDim.x) {
+            const int ci = e / Pd, a = e - ci * Pd;
+            const int64_t o = g.psi_off[g.order[start + ci]] + a;
+            bX[ci * S + a] = MODE == MODE_RES ? xpsi[o] - xpsi_prev[o] : xpsi[o];
+        }
+        __syncthreads();
+        // A_K x_K = sum_k J (2/h_k)^2 (A1 in direction k, M1 elsewhere) x_K
+        for (int k = 0; k < D; ++k) {
+            for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) bA[e] = bU[e];
+            __syncthreads();
+            const T* mats[3] = {t.M1, t.M1, t.M1};
+            mats[k] = t.A1;
+            const T* r = contract_axes<T, D>(bA, bB, S, ncell, L, L, mats, L, false);
+            for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+                const int ci = e / S;
+                T hk[3];
+                const T J = hp_jac<T, D>(g, tb, g.order[start + ci], hk);
+                const T c = J * ((T)2 / hk[k]) * ((T)2 / hk[k]);
+                bY[e] += c * r[e];
+            }
+            __syncthreads();
+        }
+        // + B_K x_psi, written per local function
+        for (int e = threadIdx.x; e < ncell * Pd; e += blockDim.x) {
+            const int ci = e / Pd, a = e - ci * Pd;
+            bA[ci * S + a] = bX[ci * S + a];
+        }
+        __syncthreads();
+        {
+            const T* r = contract_all<T, D>(bA, bB, S, ncell, P, L, t.B1, P, false);
+            for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+                const int ci = e / S, l = e - ci * S;
+                const int64_t cell = g.order[start + ci];
+                T hk[3];
+                const T J = hp_jac<T, D>(g, tb, cell, hk);
+                yloc[g.loc_off[cell] + l] = alpha * bY[e] + J * r[e];
+            }
+        }
+        __syncthreads();
+        // psi side: J B1^T x_K
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) bA[e] = bU[e];
+        __syncthreads();
+        {
+            const T* r = contract_all<T, D>(bA, bB, S, ncell, L, P, t.B1, P, true);
+            for (int e = threadIdx.x; e < ncell * Pd; e += blockDim.x) {
+                const int ci = e / Pd, a = e - ci * Pd;
+                T hk[3];
+                const T J = hp_jac<T, D>(g, tb, g.order[start + ci], hk);
+                bT[ci * S + a] = J * r[ci * S + a];
+            }
+        }
+        __syncthreads();
+        // the psi coefficients (APPLY: x_psi; RES: psi) to the Gauss points
+        for (int e = threadIdx.x; e < ncell * Pd; e += blockDim.x) {
+            const int ci = e / Pd, a = e - ci * Pd;
+            bA[ci * S + a] =
+                MODE == MODE_RES ? xpsi[g.psi_off[g.order[start + ci]] + a] : bX[ci * S + a];
+        }
+        __syncthreads();
+        T* vq = contract_all<T, D>(bA, bB, S, ncell, P, q, t.Vpsi, P, false);
+        T* other = (vq == bA) ? bB : bA;
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = e / S, j = e - ci * S;
+            const int64_t cell = g.order[start + ci];
+            if (MODE == MODE_RES) {
+                T hk[3];
+                const T J = hp_jac<T, D>(g, tb, cell, hk);
+                int jj[3] = {j % q, (j / q) % q, j / (q * q)};
+                T wq = J;
+                for (int k = 0; k < D; ++k) wq *= t.w[jj[k]];
+                const double arg = -(double)vq[e];
+                vq[e] = (T)((double)wq * exp(arg < 700.0 ? arg : 700.0));
+            } else {
+                vq[e] *= omega[g.qp_off[cell] + j];
+            }
+        }
+        __syncthreads();
+        const T* dx = contract_all<T, D>(vq, other, S, ncell, q, P, t.Vpsi, P, true);
+        for (int e = threadIdx.x; e < ncell * Pd; e += blockDim.x) {
+            const int ci = e / Pd, a = e - ci * Pd;
+            const int64_t cell = g.order[start + ci];
+            const int64_t o = g.psi_off[cell] + a;
+            if (MODE == MODE_RES) {
+                const double r = (double)bT[ci * S + a] + (double)dx[ci * S + a] - Phi[o];
+                ypsi[o] = (T)r;
+                part += r * r;
+            } else {
+                T hk[3];
+                const T J = hp_jac<T, D>(g, tb, cell, hk);
+                int aa[3] = {a % P, (a / P) % P, a / (P * P)};
+                T md = J;
+                for (int k = 0; k < D; ++k) md *= t.Mdiag[aa[k]];
+                const T y = bT[ci * S + a] - dx[ci * S + a] - beta * md * bX[ci * S + a];
+                ypsi[o] = y;
+                part += (double)y * (double)bX[ci * S + a];
+            }
+        }
+        __syncthreads();   // the LDS buffers are reused by the next item
+    }
+    if (partial) {
+        const double s = block_sum(part, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_hp_gather(int64_t n_u, const int32_t* __restrict__ ip,
+                                                   const int32_t* __restrict__ ix,
+                                                   const T* __restrict__ yloc,
+                                                   const double* __restrict__ F, double alpha,
+                                                   const T* __restrict__ xu, T* __restrict__ yu,
+                                                   double* __restrict__ partial,
+                                                   const int* __restrict__ done) {
+    __shared__ double red[4];
+    if (done && *done) return;
+    double part = 0.0;
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < n_u;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        T s = 0;
+        for (int i = ip[gi]; i < ip[gi + 1]; ++i) s += yloc[ix[i]];
+        if (MODE == MODE_RES) {
+            const double r = (double)s - alpha * F[gi];
+            yu[gi] = (T)r;
+            part += r * r;
+        } else {
+            yu[gi] = s;
+            part += (double)s * (double)xu[gi];
+        }
+    }
+    if (partial) {
+        const double s = block_sum(part, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_hp_l2(HpGeo g, HpTabs<double> tb,
+                                               const double* __restrict__ a,
+                                               const double* __restrict__ b,
+                                               double* __restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[4];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    const int SB = g.lds_elems;
+    double* bD = sm;
+    double* bN = sm + SB;
+    double* bA = sm + 2 * SB;
+    double* bB = sm + 3 * SB;
+    double pd = 0.0, pn = 0.0;
+    for (int it = blockIdx.x; it < g.n_items; it += gridDim.x) {
+        const int p = g.item_p[it], L = p + 1, q = p + 1;
+        const int start = g.item_start[it], ncell = g.item_count[it];
+        int S = 1;
+        for (int k = 0; k < D; ++k) S *= L;
+        const HpCellTabs<double> t = hp_tabs(tb, p);
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = e / S, l = e - ci * S;
+            const int gi = g.loc2glob[g.loc_off[g.order[start + ci]] + l];
+            bD[e] = gi >= 0 ? a[gi] - b[gi] : 0.0;
+            bN[e] = gi >= 0 ? a[gi] : 0.0;
+        }
+        __syncthreads();
+        const double* vd = contract_all<double, D>(bD, bA, S, ncell, L, q, t.Vu, L, false);
+        const double* vn = contract_all<double, D>(bN, bB, S, ncell, L, q, t.Vu, L, false);
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = e / S, j = e - ci * S;
+            double hk[3];
+            const double J = hp_jac<double, D>(g, tb, g.order[start + ci], hk);
+            int jj[3] = {j % q, (j / q) % q, j / (q * q)};
+            double wq = J;
+            for (int k = 0; k < D; ++k) wq *= t.w[jj[k]];
+            pd += wq * vd[e] * vd[e];
+            pn += wq * vn[e] * vn[e];
+        }
+        __syncthreads();
+    }
+    const double s1 = block_sum(pd, red);
+    const double s2 = block_sum(pn, red);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = s1;
+        partial[2 * blockIdx.x + 1] = s2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Newton-step setup, one cell per block (sizes vary by cell): the block of
+// -S_hat_K is formed and inverted in place in s64 (global memory).
+template <int D>
+__global__ __launch_bounds__(256) void k_hp_setup(HpGeo g, HpTabs<double> tb,
+                                                  const double* __restrict__ psi, double alpha,
+                                                  double beta, const double* __restrict__ Cmat,
+                                                  const int64_t* __restrict__ c_off,
+                                                  const int32_t* __restrict__ cclass,
+                                                  double* __restrict__ om64,
+                                                  float* __restrict__ om32,
+                                                  double* __restrict__ s64,
+                                                  float* __restrict__ s32) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    const int64_t cell = blockIdx.x;
+    const int p = g.cell_p[cell], P = p - 1, q = p + 1;
+    int n = 1, S = 1;
+    for (int k = 0; k < D; ++k) {
+        n *= P;
+        S *= q;
+    }
+    const int sT1 = D == 1 ? 1 : (D == 2 ? q * P * P : q * q * P * P);
+    double* bA = sm;
+    double* bB = sm + S;
+    double* T1 = sm + 2 * S;
+    double* cr = T1 + sT1;
+    const HpCellTabs<double> t = hp_tabs(tb, p);
+    const int64_t po = g.psi_off[cell], qo = g.qp_off[cell];
+    double* Dm = s64 + g.sinv_off[cell];
+    for (int a = threadIdx.x; a < n; a += blockDim.x) bA[a] = psi[po + a];
+    __syncthreads();
+    double* vq = contract_all<double, D>(bA, bB, S, 1, P, q, t.Vpsi, P, false);
+    double hk[3];
+    const double J = hp_jac<double, D>(g, tb, cell, hk);
+    for (int j = threadIdx.x; j < S; j += blockDim.x) {
+        int jj[3] = {j % q, (j / q) % q, j / (q * q)};
+        double wq = J;
+        for (int k = 0; k < D; ++k) wq *= t.w[jj[k]];
+        const double arg = -vq[j];
+        const double om = wq * exp(arg < 700.0 ? arg : 700.0);
+        vq[j] = om;
+        if (om64) om64[qo + j] = om;
+        if (om32) om32[qo + j] = (float)om;
+    }
+    __syncthreads();
+    if (D == 3)
+        d_block3_direct(vq, t.Vpsi, P, q, T1, Dm, n);
+    else
+        d_block<D>(vq, t.Vpsi, P, q, T1, T1, Dm, n);
+    const double ia = 1.0 / alpha;
+    const double* C = Cmat + c_off[cclass[cell]];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        double v = Dm[e] + ia * C[e];
+        if (i == j) {
+            int aa[3] = {i % P, (i / P) % P, i / (P * P)};
+            double md = J;
+            for (int k = 0; k < D; ++k) md *= t.Mdiag[aa[k]];
+            v += beta * md;
+        }
+        Dm[e] = v;
+    }
+    __syncthreads();
+    gauss_jordan_spd(Dm, n, cr);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        if (j < i) continue;
+        const double v = 0.5 * (Dm[(int64_t)i * n + j] + Dm[(int64_t)j * n + i]);
+        Dm[(int64_t)i * n + j] = v;
+        Dm[(int64_t)j * n + i] = v;
+        if (s32) {
+            s32[g.sinv_off[cell] + (int64_t)i * n + j] = (float)v;
+            s32[g.sinv_off[cell] + (int64_t)j * n + i] = (float)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(128) void k_hp_prec_psi(HpGeo g, const T* __restrict__ sinv,
+                                                     const T* __restrict__ r,
+                                                     T* __restrict__ z,
+                                                     double* __restrict__ partial,
+                                                     const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[2];
+    if (done && *done) return;
+    T* rb = reinterpret_cast<T*>(smem_raw);
+    double part = 0.0;
+    for (int64_t cell = blockIdx.x; cell < g.n_cells; cell += gridDim.x) {
+        const int P = g.cell_p[cell] - 1;
+        int n = 1;
+        for (int k = 0; k < g.d; ++k) n *= P;
+        const int64_t po = g.psi_off[cell];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) rb[i] = r[po + i];
+        __syncthreads();
+        const T* Sb = sinv + g.sinv_off[cell];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            T acc = 0;
+            for (int j = 0; j < n; ++j) acc += Sb[(int64_t)j * n + i] * rb[j];
+            z[po + i] = acc;
+            part += (double)acc * (double)rb[i];
+        }
+        __syncthreads();
+    }
+    if (partial) {
+        const double s = block_sum(part, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_hp_vgather(int64_t n, const int32_t* __restrict__ idx,
+                                                    const T* __restrict__ r, T* __restrict__ out,
+                                                    const int* __restrict__ done) {
+    if (done && *done) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = r[idx[i]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hp_vscatter(int64_t n, const int32_t* __restrict__ idx,
+                                                     const T* __restrict__ in,
+                                                     T* __restrict__ z,
+                                                     const int* __restrict__ done) {
+    if (done && *done) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        z[idx[i]] = in[i];
+}
+
+// z_E = (1/alpha) Ainv_E r_E (Ainv_E symmetric: read by columns, coalesced)
+template <typename T>
+__global__ __launch_bounds__(64) void k_hp_entity(int64_t n_ent, const int32_t* __restrict__ first,
+                                                  const int32_t* __restrict__ cnt,
+                                                  const int64_t* __restrict__ off,
+                                                  const T* __restrict__ inv,
+                                                  const double* __restrict__ prm,
+                                                  const T* __restrict__ r, T* __restrict__ z,
+                                                  const int* __restrict__ done) {
+    if (done && *done) return;
+    const T ia = (T)prm[2];
+    for (int64_t e = blockIdx.x; e < n_ent; e += gridDim.x) {
+        const int n = cnt[e];
+        const int64_t f = first[e];
+        const T* A = inv + off[e];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            T acc = 0;
+            for (int j = 0; j < n; ++j) acc += A[(int64_t)j * n + i] * r[f + j];
+            z[f + i] = ia * acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned grid_of(int64_t n, int b, int cap) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + b - 1) / b, cap));
+}
+
+template <typename T>
+void launch_hp_cell(const HpGeo& g, const HpTabs<T>& tb, T alpha, T beta, const double* prm,
+                    const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
+                    const double* Phi, T* yloc, T* ypsi, double* partial, int nblocks,
+                    const int* done, int mode, hipStream_t s) {
+    const unsigned grid = (unsigned)std::max(1, std::min(g.n_items, nblocks));
+    const size_t shm = (size_t)6 * g.lds_elems * sizeof(T);
+#define HPG_HC(DD, MM)                                                                          \
+    hipLaunchKernelGGL((k_hp_cell<T, DD, MM>), dim3(grid), dim3(256), shm, s, g, tb, alpha, beta, \
+                       prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi, partial, done)
+    if (mode == MODE_RES) {
+        if (g.d == 1) HPG_HC(1, MODE_RES);
+        else if (g.d == 2) HPG_HC(2, MODE_RES);
+        else HPG_HC(3, MODE_RES);
+    } else {
+        if (g.d == 1) HPG_HC(1, MODE_APPLY);
+        else if (g.d == 2) HPG_HC(2, MODE_APPLY);
+        else HPG_HC(3, MODE_APPLY);
+    }
+#undef HPG_HC
+}
+
+template <typename T>
+void launch_hp_gather(int64_t n_u, const int32_t* inc_ptr, const int32_t* inc_idx, const T* yloc,
+                      const double* F, double alpha, const T* xu, T* yu, double* partial,
+                      int nblocks, const int* done, int mode, hipStream_t s) {
+    const unsigned grid = grid_of(n_u, 256, nblocks);
+    if (mode == MODE_RES)
+        hipLaunchKernelGGL((k_hp_gather<T, MODE_RES>), dim3(grid), dim3(256), 0, s, n_u, inc_ptr,
+                           inc_idx, yloc, F, alpha, xu, yu, partial, done);
+    else
+        hipLaunchKernelGGL((k_hp_gather<T, MODE_APPLY>), dim3(grid), dim3(256), 0, s, n_u, inc_ptr,
+                           inc_idx, yloc, F, alpha, xu, yu, partial, done);
+}
+
+void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, const double* b,
+                  double* partial, int nblocks, hipStream_t s) {
+    const unsigned grid = (unsigned)std::max(1, std::min(g.n_items, nblocks));
+    const size_t shm = (size_t)4 * g.lds_elems * sizeof(double);
+    if (g.d == 1)
+        hipLaunchKernelGGL((k_hp_l2<1>), dim3(grid), dim3(256), shm, s, g, tb, a, b, partial);
+    else if (g.d == 2)
+        hipLaunchKernelGGL((k_hp_l2<2>), dim3(grid), dim3(256), shm, s, g, tb, a, b, partial);
+    else
+        hipLaunchKernelGGL((k_hp_l2<3>), dim3(grid), dim3(256), shm, s, g, tb, a, b, partial);
+}
+
+size_t hp_setup_lds(int d, int pmax) {
+    size_t best = 0;
+    for (int p = 2; p <= pmax; ++p) {
+        const size_t P = p - 1, q = p + 1;
+        size_t n = 1, S = 1;
+        for (int k = 0; k < d; ++k) {
+            n *= P;
+            S *= q;
+        }
+        const size_t sT1 = d == 1 ? 1 : (d == 2 ? q * P * P : q * q * P * P);
+        best = std::max(best, (2 * S + sT1 + 2 * n) * sizeof(double));
+    }
+    return best;
+}
+
+void launch_hp_setup(const HpGeo& g, const HpTabs<double>& tb, const double* psi, double alpha,
+                     double beta, const double* C, const int64_t* c_off, const int32_t* cclass,
+                     double* om64, float* om32, double* s64, float* s32, size_t lds_bytes,
+                     hipStream_t s) {
+    const unsigned grid = (unsigned)g.n_cells;
+#define HPG_HS(DD)                                                                             \
+    hipLaunchKernelGGL((k_hp_setup<DD>), dim3(grid), dim3(256), lds_bytes, s, g, tb, psi, alpha, \
+                       beta, C, c_off, cclass, om64, om32, s64, s32)
+    if (g.d == 1) HPG_HS(1);
+    else if (g.d == 2) HPG_HS(2);
+    else HPG_HS(3);
+#undef HPG_HS
+}
+
+template <typename T>
+void launch_hp_prec_psi(const HpGeo& g, const T* sinv, const T* r, T* z, double* partial,
+                        int nblocks, int nmax, const int* done, hipStream_t s) {
+    const unsigned grid = grid_of(g.n_cells, 1, nblocks);
+    hipLaunchKernelGGL((k_hp_prec_psi<T>), dim3(grid), dim3(128), (size_t)nmax * sizeof(T), s, g,
+                       sinv, r, z, partial, done);
+}
+
+template <typename T>
+void launch_hp_vgather(int64_t n, const int32_t* idx, const T* r, T* out, const int* done,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((k_hp_vgather<T>), dim3(grid_of(n, 256, 1024)), dim3(256), 0, s, n, idx, r,
+                       out, done);
+}
+
+template <typename T>
+void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const int* done,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_hp_vscatter<T>), dim3(grid_of(n, 256, 1024)), dim3(256), 0, s, n, idx,
+                       in, z, done);
+}
+
+template <typename T>
+void launch_hp_entity(int64_t n_ent, const int32_t* first, const int32_t* cnt, const int64_t* off,
+                      const T* inv, const double* prm, const T* r, T* z, const int* done,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((k_hp_entity<T>), dim3(grid_of(n_ent, 1, 8192)), dim3(64), 0, s, n_ent,
+                       first, cnt, off, inv, prm, r, z, done);
+}
+
+#define HPG_INST(T)                                                                               \
+    template void launch_hp_cell<T>(const HpGeo&, const HpTabs<T>&, T, T, const double*, const T*, \
+                                    const T*, const T*, const T*, const double*, T*, T*, double*,  \
+                                    int, const int*, int, hipStream_t);                            \
+    template void launch_hp_gather<T>(int64_t, const int32_t*, const int32_t*, const T*,          \
+                                      const double*, double, const T*, T*, double*, int,          \
+                                      const int*, int, hipStream_t);                               \
+    template void launch_hp_prec_psi<T>(const HpGeo&, const T*, const T*, T*, double*, int, int,  \
+                                        const int*, hipStream_t);                                  \
+    template void launch_hp_vgather<T>(int64_t, const int32_t*, const T*, T*, const int*,         \
+                                       hipStream_t);                                               \
+    template void launch_hp_vscatter<T>(int64_t, const int32_t*, const T*, T*, const int*,        \
+                                        hipStream_t);                                              \
+    template void launch_hp_entity<T>(int64_t, const int32_t*, const int32_t*, const int64_t*,    \
+                                      const T*, const double*, const T*, T*, const int*,          \
+                                      hipStream_t);
+HPG_INST(double)
+HPG_INST(float)
+#undef HPG_INST
+
+}  // namespace dev
+}  // namespace hpg

@@ -79,7 +79,38 @@ struct Mesh {
     int64_t Pd = 0, Qd = 0, Ld = 0;   // P^d, q^d, (p+1)^d
     RefTables ref;
     double h(int k, int c) const { return breaks[k][c + 1] - breaks[k][c]; }
+    // One degree per cell (obstacle only; p, P, q, Pd, Qd, Ld above then
+    // describe the largest degree).  Entities (vertices, edges, faces, cell
+    // interiors) are the points of the doubled grid, 2 m_k + 1 per direction
+    // (even: vertex, odd: cell interval), direction 0 fastest; each interior
+    // entity carries the smallest degree of the cells containing it and
+    // (p_E - 1)^(number of odd directions) consecutive unknowns starting at
+    // ent_base (boundary entities: -1).
+    bool hp = false;
+    int pmin = 0;
+    std::vector<int32_t> deg;              // n_cells
+    std::vector<int64_t> psi_off, qp_off;  // n_cells + 1: P_K^d and q_K^d prefix sums
+    std::vector<int64_t> ent_base;
+    std::vector<int32_t> ent_deg;
+    int64_t ent_index(const int e[3]) const {
+        return e[0] + (int64_t)(2 * m[0] + 1) * (d > 1 ? e[1] + (int64_t)(2 * m[1] + 1) * (d > 2 ? e[2] : 0) : 0);
+    }
 };
+
+// dense Cholesky solve A X = B (A n x n SPD, B n x m, row-major)
+void chol_solve(int n, std::vector<double> A, std::vector<double>& B, int m);
+// C_K = Bhat^T Ahat^{-1} Bhat of one cell shape (widths hk) at the mesh's P
+std::vector<double> schur_block(const Mesh& M, const double* hk);
+// contract axis ax of a d-D tensor (dims din, updated) with mat (nout x din[ax])
+std::vector<double> hcontract(const std::vector<double>& in, int d, int din[3], int ax,
+                              int nout, const std::vector<double>& mat, int ld, bool trans);
+
+// number the unknowns of a per-cell-degree mesh (fills n_u, n_psi, n_qp,
+// offsets and the entity tables from d, m, breaks and deg)
+void hp_number(Mesh& M);
+// global unknown of every local function of cell c ((p_K+1)^d, direction 0
+// fastest; -1 where the function is absent), appended to out
+void hp_cell_dofs(const Mesh& M, int64_t c, std::vector<int32_t>& out);
 
 // Sparse 1-D global rows in direction k (assembled from the cell matrices):
 // for every 1-D u unknown g: up to 7 (column, stiffness, mass) entries and up

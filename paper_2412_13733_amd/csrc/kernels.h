@@ -177,5 +177,81 @@ template <typename T>
 void launch_prec_psi_big(int64_t n_cells, int n, const T* sinv, const T* r, T* z,
                          double* partial, int nblocks, const int* done, hipStream_t s);
 
+// ---- one degree per cell (hp.hip) -----------------------------------------
+// Offsets of the reference tables of degree p (L = p+1 local u functions,
+// P = p-1 psi modes, q = p+1 Gauss points per direction) in a packed array:
+// A1, M1 (L x L), B1 (L x P), Vu (q x L), Vpsi (q x P), w (q), Mdiag (P).
+struct HpTabOff {
+    int64_t A1, M1, B1, Vu, Vpsi, w, Mdiag;
+};
+template <typename T>
+struct HpTabs {
+    const T* base;
+    const HpTabOff* off;   // indexed by degree
+    const T* h[3];         // cell widths per direction
+};
+// Cells are processed in work items: runs of up to item_count cells of equal
+// degree item_p (cell numbers order[item_start .. item_start + count)).
+struct HpGeo {
+    int d;
+    int m[3];
+    int64_t n_cells, n_u, n_psi;
+    int n_items, lds_elems;   // lds_elems: per-buffer LDS elements of the cell kernels
+    const int32_t* cell_p;
+    const int64_t* loc_off;   // prefix sums of (p_K+1)^d
+    const int64_t* psi_off;   // prefix sums of P_K^d
+    const int64_t* qp_off;    // prefix sums of q_K^d
+    const int64_t* sinv_off;  // prefix sums of (P_K^d)^2
+    const int32_t* loc2glob;  // local -> global u unknown (-1: absent)
+    const int32_t* order;
+    const int32_t* item_start;
+    const int32_t* item_count;
+    const int32_t* item_p;
+};
+constexpr int MODE_L2 = 2;
+// Cell pass of G (MODE_APPLY: y_loc = alpha A_K x_K + B_K x_psi, y_psi =
+// B_K^T x_K - (D_K + beta M_K) x_psi, partial <y_psi, x_psi>) or of the FP64
+// residual (MODE_RES: x_psi = psi, xpsi_prev = psi_{k-1}; y_loc = alpha A_K u_K
+// + B_K (psi - psi_prev), y_psi = B_K^T u_K + E_K(psi) - Phi_K, partial
+// |y_psi|^2).  y_loc is per local function, summed into y_u by launch_hp_gather.
+template <typename T>
+void launch_hp_cell(const HpGeo& g, const HpTabs<T>& tb, T alpha, T beta, const double* prm,
+                    const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
+                    const double* Phi, T* yloc, T* ypsi, double* partial, int nblocks,
+                    const int* done, int mode, hipStream_t s);
+// y_u[g] = sum of y_loc over the local functions of unknown g (fixed order),
+// minus alpha F[g] in MODE_RES; partial <y_u, x_u> (APPLY) or |y_u|^2 (RES)
+template <typename T>
+void launch_hp_gather(int64_t n_u, const int32_t* inc_ptr, const int32_t* inc_idx, const T* yloc,
+                      const double* F, double alpha, const T* xu, T* yu, double* partial,
+                      int nblocks, const int* done, int mode, hipStream_t s);
+// ||a - b||_{L2}^2 and ||a||_{L2}^2 per block (partial[2 i], partial[2 i + 1])
+void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, const double* b,
+                  double* partial, int nblocks, hipStream_t s);
+// Newton-step setup: omega_q = w_q |J| exp(-psi_h) at qp_off, and the inverse of
+// -S_hat_K = D_K + beta M_K + C_K / alpha formed in place at s64 + sinv_off
+// (C of cell K at C + c_off[cclass[K]]), one cell per block
+void launch_hp_setup(const HpGeo& g, const HpTabs<double>& tb, const double* psi, double alpha,
+                     double beta, const double* C, const int64_t* c_off, const int32_t* cclass,
+                     double* om64, float* om32, double* s64, float* s32, size_t lds_bytes,
+                     hipStream_t s);
+size_t hp_setup_lds(int d, int pmax);
+// z_psi = (-S_hat_K)^{-1} r_psi per cell, partial <z_psi, r_psi>
+template <typename T>
+void launch_hp_prec_psi(const HpGeo& g, const T* sinv, const T* r, T* z, double* partial,
+                        int nblocks, int nmax, const int* done, hipStream_t s);
+// block-Jacobi A-block: out[t] = r[idx[t]] / z[idx[t]] = in[t] (vertex unknowns),
+// and per edge/face/interior entity z_E = (1/alpha) Ainv_E r_E
+template <typename T>
+void launch_hp_vgather(int64_t n, const int32_t* idx, const T* r, T* out, const int* done,
+                       hipStream_t s);
+template <typename T>
+void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const int* done,
+                        hipStream_t s);
+template <typename T>
+void launch_hp_entity(int64_t n_ent, const int32_t* first, const int32_t* cnt, const int64_t* off,
+                      const T* inv, const double* prm, const T* r, T* z, const int* done,
+                      hipStream_t s);
+
 }  // namespace dev
 }  // namespace hpg

@@ -8,6 +8,7 @@
 #include <utility>
 #include <vector>
 
+#include "hp_host.h"
 #include "hpg_internal.h"
 #include "kernels.h"
 
@@ -101,6 +102,28 @@ struct Problem {
     DevFdm<double> fdm64;
     DevFdm<float> fdm32;
     DBuf C, cclass;
+    // one degree per cell (M.hp): host tables, their device copies, the cell
+    // kernels' geometry, and the coarse (vertex) fast diagonalisation
+    HpHost hph;
+    struct HpDev {
+        DBuf cell_p, loc_off, psi_off, qp_off, sinv_off, loc2glob, inc_ptr, inc_idx, order;
+        DBuf item_start, item_count, item_p, cclass, c_off, C, vert, ent_first, ent_n, ent_off;
+        DBuf inv64, inv32, tab64, tab32, toff, h64[3], h32[3], yloc64, yloc32, cv64, cv32;
+    } hpd;
+    dev::HpGeo hgeo{};
+    int hp_lds_elems = 256, hp_nmax = 1, np_gath = 0, np_cell = 0;
+    size_t hp_setup_bytes = 0;
+    DevFdm<double> cfdm64;
+    DevFdm<float> cfdm32;
+    void build_hp();
+    void ensure_fdm_hp();
+    void set_data_hp(const double* f, const double* phi);
+    template <typename T>
+    dev::HpTabs<T> hp_tabs() const;
+    template <typename T>
+    void apply_G_hp(const T* x, T* y, double* part, const int* dn, hipStream_t s);
+    template <typename T>
+    void apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipStream_t s);
     // data
     std::vector<double> f_qp, phi_qp;
     bool have_f = false, have_phi = false;
@@ -173,6 +196,10 @@ struct Problem {
 }  // namespace hpg
 
 namespace hpg {
+template <typename TO>
+std::vector<TO> cast(const std::vector<double>& v) {
+    return std::vector<TO>(v.begin(), v.end());
+}
 // bytes hipMalloc'ed by DBuf on the calling thread (accounting for the server)
 size_t& device_bytes_counter();
 // serialises the calls that act on the whole device (allocation, synchronous
@@ -181,6 +208,14 @@ size_t& device_bytes_counter();
 std::recursive_mutex& device_api_mutex();
 // device memory of one problem's solve at the given precision (upper estimate)
 size_t footprint_bytes(const Mesh& M, int precision);
+size_t footprint_bytes_hp(const Mesh& M, int precision);
+// blocking host -> device copy into a freshly sized buffer
+template <typename T>
+void upload(DBuf& d, const std::vector<T>& h) {
+    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
+    d.alloc(h.size() * sizeof(T));
+    if (!h.empty()) HPG_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
 // solve options with defaults filled in and validated (throws Error)
 hpg_solve_opts checked_opts(const hpg_solve_opts* in);
 }  // namespace hpg

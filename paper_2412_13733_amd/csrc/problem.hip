@@ -110,6 +110,7 @@ void DBuf::alloc(size_t b) {
 // the Krylov work vectors and the fast-diagonalisation factors, plus a margin
 // for allocation granularity.
 size_t footprint_bytes(const Mesh& M, int precision) {
+    if (M.hp) return footprint_bytes_hp(M, precision);
     const double n = (double)(M.n_u + M.n_psi), nu = (double)M.n_u;
     const double nc = (double)M.n_cells;
     double b = 0.0;
@@ -141,16 +142,6 @@ size_t footprint_bytes(const Mesh& M, int precision) {
     return (size_t)(1.15 * b) + ((size_t)8 << 20);
 }
 
-template <typename T>
-static void upload(DBuf& d, const std::vector<T>& h) {
-    std::lock_guard<std::recursive_mutex> api(device_api_mutex());
-    d.alloc(h.size() * sizeof(T));
-    if (!h.empty()) HPG_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-}
-template <typename TO>
-static std::vector<TO> cast(const std::vector<double>& v) {
-    return std::vector<TO>(v.begin(), v.end());
-}
 
 // Dense-window form of the 1-D rows for p <= 3 (the fused apply's low-degree
 // path): row g + 1 holds the stiffness and mass entries of columns g - p .. g + p,
@@ -250,9 +241,8 @@ Problem::~Problem() {
 // ---------------------------------------------------------------------------
 // small host tensor helper: contract axis ax of a d-D tensor (dims din,
 // direction 0 fastest) with mat(i, j) = mat[i*ld + j] (or transposed)
-static std::vector<double> hcontract(const std::vector<double>& in, int d, int din[3], int ax,
-                                     int nout, const std::vector<double>& mat, int ld,
-                                     bool trans) {
+std::vector<double> hcontract(const std::vector<double>& in, int d, int din[3], int ax,
+                              int nout, const std::vector<double>& mat, int ld, bool trans) {
     int dout[3] = {din[0], din[1], din[2]};
     dout[ax] = nout;
     std::vector<double> out((size_t)dout[0] * dout[1] * dout[2], 0.0);
@@ -275,7 +265,7 @@ static std::vector<double> hcontract(const std::vector<double>& in, int d, int d
 }
 
 // dense Cholesky solve A X = B (A n x n SPD, B n x m), row-major
-static void chol_solve(int n, std::vector<double> A, std::vector<double>& B, int m) {
+void chol_solve(int n, std::vector<double> A, std::vector<double>& B, int m) {
     for (int j = 0; j < n; ++j) {
         double s = A[j * n + j];
         for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
@@ -315,7 +305,7 @@ static std::vector<double> kron(const std::vector<double>& A, int ar, int ac,
 
 // C_K = Bhat^T Ahat^{-1} Bhat for one cell shape (Sec. 4.5, alpha factored out):
 // Ahat = sum_k (x)(AY (2/h_k) in slot k, MY (h_k/2) elsewhere), Bhat = (x)_k BY h_k/2
-static std::vector<double> schur_block(const Mesh& M, const double* hk) {
+std::vector<double> schur_block(const Mesh& M, const double* hk) {
     const int P = M.P, d = M.d;
     const RefTables& T = M.ref;
     std::vector<double> Ah, Bh;
@@ -395,6 +385,10 @@ void Problem::build(const Mesh& mesh, int dev_) {
         lds_max = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
     }
     gradient = M.kind == HPG_GRADIENT;
+    if (M.hp) {
+        build_hp();
+        return;
+    }
     // geometry
     geo.d = M.d;
     geo.p = M.p;
@@ -617,6 +611,7 @@ std::map<std::pair<int, std::vector<double>>, std::shared_ptr<FdmEntry>> g_fdm_c
 }  // namespace
 
 void Problem::ensure_fdm() {
+    if (M.hp) return ensure_fdm_hp();
     std::lock_guard<std::recursive_mutex> api(device_api_mutex());
     if (fdm_ready) return;
     for (int k = 0; k < 3; ++k) {
@@ -658,6 +653,7 @@ void Problem::ensure_fdm() {
 
 // F_i = (f, v_i), Phi_i = (phi, zeta_i) by the Gauss-Legendre rule (sum-factorised)
 void Problem::set_data(const double* f, const double* phi) {
+    if (M.hp) return set_data_hp(f, phi);
     const int d = M.d, q = M.q, L = M.p + 1, P = M.P;
     const RefTables& T = M.ref;
     if (f) {
@@ -737,6 +733,23 @@ void Problem::set_data(const double* f, const double* phi) {
 }
 
 void Problem::ensure_linearisation_buffers() {
+    if (M.hp) {
+        // weights at every cell's Gauss points; -S_hat blocks formed in FP64 in place
+        // (and the per-local-function output of the cell pass: allocated here,
+        // outside any graph capture of the Krylov iteration)
+        const size_t nq = (size_t)M.n_qp, ns = (size_t)hph.sinv_off.back();
+        const size_t nl = (size_t)hph.loc_off.back();
+        sinv64.alloc(ns * sizeof(double));
+        if (precision == HPG_FP64) {
+            om64.alloc(nq * sizeof(double));
+            if (!hpd.yloc64.p) hpd.yloc64.alloc(nl * sizeof(double));
+        } else {
+            om32.alloc(nq * sizeof(float));
+            sinv32.alloc(ns * sizeof(float));
+            if (!hpd.yloc32.p) hpd.yloc32.alloc(nl * sizeof(float));
+        }
+        return;
+    }
     const size_t npair = (size_t)M.ncomp * (M.ncomp + 1) / 2;
     const size_t nq = (size_t)M.n_cells * M.Qd * npair;
     const size_t ns = (size_t)M.n_cells * M.psi_per_cell * M.psi_per_cell;
@@ -816,7 +829,13 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
     hparams[2] = 1.0 / alpha;
     HPG_HIP(hipMemcpyAsync(params.p, hparams, sizeof(hparams), hipMemcpyHostToDevice, s));
     tstart("setup", s);
-    if (gradient) {
+    if (M.hp) {
+        dev::launch_hp_setup(hgeo, hp_tabs<double>(), d_psi, alpha, beta, hpd.C.as<double>(),
+                             hpd.c_off.as<int64_t>(), hpd.cclass.as<int32_t>(),
+                             prec == HPG_FP64 ? om64.as<double>() : nullptr,
+                             prec == HPG_FP64 ? nullptr : om32.as<float>(), sinv64.as<double>(),
+                             prec == HPG_FP64 ? nullptr : sinv32.as<float>(), hp_setup_bytes, s);
+    } else if (gradient) {
         const bool hbm = dev::setup_grad_in_hbm(geo);
         dev::launch_setup_grad(geo, tab64.view(), d_psi, PhiQ.as<double>(), beta,
                                prec == HPG_FP64 ? om64.as<double>() : nullptr,
@@ -874,6 +893,7 @@ template <typename T>
 void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t s) {
     if (!linearised || precision != Sel<T>::prec)
         fail(HPG_ERR_INVALID_ARG, "operator not set up for this precision (call hpg_op_setup)");
+    if (M.hp) return apply_G_hp<T>(x, y, part, dn, s);
     const DevRows<T>* rw = Sel<T>::rows(*this);
     dev::URows<T> r[3] = {rw[0].view(), rw[1].view(), rw[2].view()};
     const double* prm = params.as<double>();
@@ -913,6 +933,7 @@ template <typename T>
 void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStream_t s) {
     if (!linearised || precision != Sel<T>::prec)
         fail(HPG_ERR_INVALID_ARG, "operator not set up for this precision (call hpg_op_setup)");
+    if (M.hp) return apply_prec_hp<T>(r, z, part, dn, s);
     KrylovWork<T>& kw = Sel<T>::kw(*this);
     kw.ensure(M.n_u + M.n_psi, M.n_u);
     ensure_fdm();
@@ -1124,7 +1145,17 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
             b += h[2 * i + 1];
         }
     } else {
-        if (gradient) {
+        if (M.hp) {
+            if (!hpd.yloc64.p) hpd.yloc64.alloc((size_t)hph.loc_off.back() * sizeof(double));
+            dev::launch_hp_cell<double>(hgeo, hp_tabs<double>(), alpha_, 0.0, nullptr, uu, pp,
+                                        pprev, nullptr, Phi.as<double>(), hpd.yloc64.as<double>(),
+                                        RR + M.n_u, part + np_u, np_cell, nullptr, dev::MODE_RES,
+                                        s);
+            dev::launch_hp_gather<double>(M.n_u, hpd.inc_ptr.as<int32_t>(),
+                                          hpd.inc_idx.as<int32_t>(), hpd.yloc64.as<double>(),
+                                          F.as<double>(), alpha_, uu, RR, part, np_gath, nullptr,
+                                          dev::MODE_RES, s);
+        } else if (gradient) {
             dev::launch_u_side_grad<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR,
                                             part, nullptr, dev::MODE_RES, s, nullptr);
             dev::launch_psi_side_grad<double>(geo, tab64.view(), cpb_psi, 0.0, uu, pp, nullptr,
@@ -1151,9 +1182,15 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
 
 double Problem::l2_diff(const double* a, const double* b, double* norm_a, hipStream_t s) {
     double* part = partial.as<double>();
-    dev::launch_l2(geo, tab64.view(), cpb_l2, a, b, part, s);
+    int nb;
+    if (M.hp) {
+        dev::launch_hp_l2(hgeo, hp_tabs<double>(), a, b, part, np_cell, s);
+        nb = std::min(hgeo.n_items, np_cell);
+    } else {
+        dev::launch_l2(geo, tab64.view(), cpb_l2, a, b, part, s);
+        nb = (int)((M.n_cells + cpb_l2 - 1) / cpb_l2);
+    }
     HPG_HIP(hipGetLastError());
-    const int nb = (int)((M.n_cells + cpb_l2 - 1) / cpb_l2);
     std::vector<double> h(2 * nb);
     HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HPG_HIP(hipStreamSynchronize(s));

@@ -99,7 +99,7 @@ def load():
                           ctypes.c_size_t)
     sig = {
         "hpg_last_error": ([], ctypes.c_char_p),
-        "hpg_create_mesh": ([ctypes.c_int, P, P, I32, I32, P], ctypes.c_int),
+        "hpg_create_mesh": ([ctypes.c_int, P, P, P, I32, I32, P], ctypes.c_int),
         "hpg_destroy_mesh": ([P], None),
         "hpg_get_mesh_info": ([P, P], ctypes.c_int),
         "hpg_quadrature_points": ([P, P], ctypes.c_int),
@@ -163,7 +163,10 @@ def default_opts(**kw):
 
 
 class Mesh:
-    def __init__(self, dim, ncells, p, constraint=OBSTACLE, breaks=None):
+    """Tensor mesh; ``degree`` (one value per cell, direction 0 fastest)
+    selects per-cell degrees (obstacle only; ``p`` is then ignored)."""
+
+    def __init__(self, dim, ncells, p, constraint=OBSTACLE, breaks=None, degree=None):
         lib = load()
         vals = [int(v) for v in ncells] + [1] * max(0, 3 - len(ncells))
         nc = (ctypes.c_int32 * len(vals))(*vals)
@@ -175,8 +178,14 @@ class Mesh:
             ptrs = (ctypes.c_void_p * 3)(*([a.ctypes.data for a in arrs] + [None] * (3 - len(arrs))))
             self._keep.append(ptrs)
             bp = ctypes.cast(ptrs, ctypes.c_void_p)
+        dp = None
+        if degree is not None:
+            deg = np.ascontiguousarray(np.asarray(degree).reshape(-1), dtype=np.int32)
+            self._keep.append(deg)
+            dp = ctypes.c_void_p(deg.ctypes.data)
+            p = 0
         h = ctypes.c_void_p()
-        _check(lib.hpg_create_mesh(dim, ctypes.cast(nc, ctypes.c_void_p), bp, p, constraint,
+        _check(lib.hpg_create_mesh(dim, ctypes.cast(nc, ctypes.c_void_p), bp, dp, p, constraint,
                                    ctypes.byref(h)))
         self.h = h
         inf = MeshInfo()
