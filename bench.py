@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="prefix of the 512-request serving stream to run")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--no-hp", action="store_true",
+                    help="skip the per-cell-degree workload (2-D 64x64, degrees 2..12)")
+    ap.add_argument("--hp-steps", type=int, default=2)
     ap.add_argument("--counters", action="store_true",
                     help="only a few operator launches for rocprofv3 --pmc passes: the "
                          "workload's G apply and preconditioner (FP32 and FP64), the 4096^2 "
@@ -93,8 +96,8 @@ def counters_run(args, torch, hpg, W):
     print(json.dumps({"counters_run": "done", "copy_bytes": a.numel() * 8}), flush=True)
 
 
-GROUPS = ["apply_G", "apply_G_u", "apply_G_psi", "fdm", "prec_psi", "minres_vec", "setup",
-          "residual"]
+GROUPS = ["apply_G", "apply_G_u", "apply_G_psi", "fdm", "prec_psi", "prec_u", "minres_vec",
+          "setup", "residual"]
 
 
 def group_work(mesh, b):
@@ -339,6 +342,56 @@ def serving_bench(args, hpg, W):
     }
 
 
+HP_DEGREES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                          "dip_64x64_degrees.txt")
+
+
+def hp_bench(args, torch, hpg, W):
+    """Per-cell degrees: the 2-D 64x64 dip-obstacle workload with degrees 2..12
+    graded away from the contact boundary; FP64 and mixed full solves."""
+    deg = np.loadtxt(HP_DEGREES, dtype=np.int32).reshape(-1)
+    f, phi = W.w2d_dip(0)
+    mesh = hpg.Mesh(2, [64, 64], 0, degree=deg)
+    x = mesh.quadrature_points()
+    prob = hpg.Problem(mesh, device=0)
+    prob.set_forcing(f(x))
+    prob.set_obstacle(phi(x))
+    n_dof = mesh.n_u + mesh.n_psi
+    d_u = torch.zeros(mesh.n_u, dtype=torch.float64, device="cuda")
+    d_psi = torch.zeros(mesh.n_psi, dtype=torch.float64, device="cuda")
+    d_u64 = torch.zeros_like(d_u)
+    out = {"workload": "2-D obstacle 64x64 cells, per-cell degree 2..12 (2 within 0.1 of the "
+                       "contact boundary of a p=2 pilot solve, 12 beyond 0.4), sine forcing seed 0, "
+                       "dip obstacle phi = 0.2 - 0.15 exp(-20|x-x0|^2), alpha_k=2^k, tol 1e-10",
+           "n_u": mesh.n_u, "n_psi": mesh.n_psi,
+           "degree_histogram": np.bincount(deg, minlength=13)[2:].tolist()}
+    for prec in ("fp64", "mixed"):
+        opts = hpg.default_opts(precision=hpg.FP64 if prec == "fp64" else hpg.MIXED)
+        if prec == "mixed":
+            opts.newton_tol = 1e-10
+            opts.krylov_rtol = 1e-6
+        prob.solve_device(d_u, d_psi, opts)   # warm-up (tables, graphs)
+        steps = 1 if prec == "fp64" else args.hp_steps
+        r = run_solves(prob, d_u, d_psi, opts, steps, torch)
+        ent = {"solves_per_s": steps / r["seconds"], "ms_per_solve": 1e3 * r["seconds"] / steps,
+               "dof_krylov_per_s": n_dof * r["krylov"] / r["seconds"],
+               "krylov_per_solve": r["krylov"] / steps, "newton_per_solve": r["newton"] / steps,
+               "prox_per_solve": r["prox"] / steps}
+        if prec == "fp64":
+            d_u64.copy_(d_u)
+        else:
+            diff, nrm = prob.l2_diff(d_u, d_u64)
+            ent["rel_l2_vs_fp64"] = diff / nrm
+            rt = run_solves(prob, d_u, d_psi, opts, 1, torch, group="all")
+            ent["kernel_groups"] = {g: {"launches": nl, "avg_us": 1e3 * ms / nl}
+                                    for g, (nl, ms) in rt["ktime"].items() if nl}
+        out["path_" + prec] = ent
+        print("[bench] hp %s: %.3f s per solve, krylov %d, newton %d"
+              % (prec, 1e-3 * ent["ms_per_solve"], ent["krylov_per_solve"],
+                 ent["newton_per_solve"]), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -476,6 +529,8 @@ def main():
         print("[bench] apply_G probe: %.1f us, %.0f GB/s" % (out["apply_G_probe"]["apply_us"],
                                                             out["apply_G_probe"]["achieved_GBs"]),
               file=sys.stderr, flush=True)
+    if not args.no_hp:
+        out["hp_dip_64x64"] = hp_bench(args, torch, hpg, W)
     if not args.no_serving:
         out["serving"] = serving_bench(args, hpg, W)
         sv = out["serving"]

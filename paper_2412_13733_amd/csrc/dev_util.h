@@ -313,8 +313,10 @@ __device__ inline void d_block3_direct(const double* w, const double* V, int P, 
 
 // In-place inverse of one SPD n x n block (row-major, any memory space) by
 // Gauss-Jordan elimination without pivoting; cr: 2n doubles of LDS for the
-// pivot column and row.  Every thread of the block takes part.
+// pivot column and row.  Every thread of the block takes part (blockDim a
+// multiple of 32): half-waves sweep rows, lanes sweep columns.
 __device__ inline void gauss_jordan_spd(double* Dm, int n, double* cr) {
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5, ny = blockDim.x >> 5;
     for (int k = 0; k < n; ++k) {
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             cr[i] = Dm[(int64_t)i * n + k];
@@ -322,10 +324,13 @@ __device__ inline void gauss_jordan_spd(double* Dm, int n, double* cr) {
         }
         __syncthreads();
         const double ip = 1.0 / cr[k];
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int i = e / n, j = e % n;
-            const double rk = (j == k ? 1.0 : cr[n + j]) * ip;
-            Dm[e] = (i == k) ? rk : ((j == k ? 0.0 : Dm[e]) - cr[i] * rk);
+        for (int i = ty; i < n; i += ny) {
+            const double ci = cr[i];
+            double* row = Dm + (int64_t)i * n;
+            for (int j = tx; j < n; j += 32) {
+                const double rk = (j == k ? 1.0 : cr[n + j]) * ip;
+                row[j] = (i == k) ? rk : ((j == k ? 0.0 : row[j]) - ci * rk);
+            }
         }
         __syncthreads();
     }

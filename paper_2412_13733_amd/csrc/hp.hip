@@ -279,9 +279,11 @@ __global__ __launch_bounds__(256) void k_hp_l2(HpGeo g, HpTabs<double> tb,
 
 // ---------------------------------------------------------------------------
 // Newton-step setup, one cell per block (sizes vary by cell): the block of
-// -S_hat_K is formed and inverted in place in s64 (global memory).
-template <int D>
-__global__ __launch_bounds__(256) void k_hp_setup(HpGeo g, HpTabs<double> tb,
+// -S_hat_K is formed and inverted in LDS (LDSD, when the largest block fits)
+// or in place in s64 (global memory).  1024 threads: one block holds a CU's
+// LDS, so its own waves hide the LDS latency of the elimination.
+template <int D, bool LDSD>
+__global__ __launch_bounds__(1024) void k_hp_setup(HpGeo g, HpTabs<double> tb,
                                                   const double* __restrict__ psi, double alpha,
                                                   double beta, const double* __restrict__ Cmat,
                                                   const int64_t* __restrict__ c_off,
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(256) void k_hp_setup(HpGeo g, HpTabs<double> tb,
     double* cr = T1 + sT1;
     const HpCellTabs<double> t = hp_tabs(tb, p);
     const int64_t po = g.psi_off[cell], qo = g.qp_off[cell];
-    double* Dm = s64 + g.sinv_off[cell];
+    double* Dm = LDSD ? cr + 2 * n : s64 + g.sinv_off[cell];
     for (int a = threadIdx.x; a < n; a += blockDim.x) bA[a] = psi[po + a];
     __syncthreads();
     double* vq = contract_all<double, D>(bA, bB, S, 1, P, q, t.Vpsi, P, false);
@@ -342,32 +344,46 @@ __global__ __launch_bounds__(256) void k_hp_setup(HpGeo g, HpTabs<double> tb,
     }
     __syncthreads();
     gauss_jordan_spd(Dm, n, cr);
+    const int64_t so = g.sinv_off[cell];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int i = e / n, j = e % n;
         if (j < i) continue;
         const double v = 0.5 * (Dm[(int64_t)i * n + j] + Dm[(int64_t)j * n + i]);
-        Dm[(int64_t)i * n + j] = v;
-        Dm[(int64_t)j * n + i] = v;
+        if (LDSD) {
+            if (s64) {
+                s64[so + (int64_t)i * n + j] = v;
+                s64[so + (int64_t)j * n + i] = v;
+            }
+        } else {
+            Dm[(int64_t)i * n + j] = v;
+            Dm[(int64_t)j * n + i] = v;
+        }
         if (s32) {
-            s32[g.sinv_off[cell] + (int64_t)i * n + j] = (float)v;
-            s32[g.sinv_off[cell] + (int64_t)j * n + i] = (float)v;
+            s32[so + (int64_t)i * n + j] = (float)v;
+            s32[so + (int64_t)j * n + i] = (float)v;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
+// z_psi = (-S_hat_K)^{-1} r_psi, one cell per block (largest blocks first):
+// the 256 threads split into nsplit groups that each sum a range of j for
+// every row i (the inverse is symmetric: row j read as column j, coalesced),
+// and the group sums are added in LDS in a fixed order
 template <typename T>
-__global__ __launch_bounds__(128) void k_hp_prec_psi(HpGeo g, const T* __restrict__ sinv,
+__global__ __launch_bounds__(256) void k_hp_prec_psi(HpGeo g, const T* __restrict__ sinv,
                                                      const T* __restrict__ r,
                                                      T* __restrict__ z,
                                                      double* __restrict__ partial,
                                                      const int* __restrict__ done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[2];
+    __shared__ double red[4];
+    __shared__ T acc_s[256];
     if (done && *done) return;
     T* rb = reinterpret_cast<T*>(smem_raw);
     double part = 0.0;
-    for (int64_t cell = blockIdx.x; cell < g.n_cells; cell += gridDim.x) {
+    for (int64_t b = blockIdx.x; b < g.n_cells; b += gridDim.x) {
+        const int64_t cell = g.order[b];
         const int P = g.cell_p[cell] - 1;
         int n = 1;
         for (int k = 0; k < g.d; ++k) n *= P;
@@ -375,13 +391,26 @@ __global__ __launch_bounds__(128) void k_hp_prec_psi(HpGeo g, const T* __restric
         for (int i = threadIdx.x; i < n; i += blockDim.x) rb[i] = r[po + i];
         __syncthreads();
         const T* Sb = sinv + g.sinv_off[cell];
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int nsplit = n >= 256 ? 1 : 256 / n;
+        const int chunk = (n + nsplit - 1) / nsplit;
+        for (int i0 = 0; i0 < n; i0 += 256 / nsplit) {
+            const int t = threadIdx.x;
+            const int grp = t / (256 / nsplit), i = i0 + t % (256 / nsplit);
             T acc = 0;
-            for (int j = 0; j < n; ++j) acc += Sb[(int64_t)j * n + i] * rb[j];
-            z[po + i] = acc;
-            part += (double)acc * (double)rb[i];
+            if (grp < nsplit && i < n) {
+                const int j1 = min(n, (grp + 1) * chunk);
+                for (int j = grp * chunk; j < j1; ++j) acc += Sb[(int64_t)j * n + i] * rb[j];
+            }
+            acc_s[t] = acc;
+            __syncthreads();
+            if (t < 256 / nsplit && i0 + t < n) {
+                T s = 0;
+                for (int q = 0; q < nsplit; ++q) s += acc_s[q * (256 / nsplit) + t];
+                z[po + i0 + t] = s;
+                part += (double)s * (double)rb[i0 + t];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     if (partial) {
         const double s = block_sum(part, red);
@@ -486,7 +515,7 @@ void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, con
         hipLaunchKernelGGL((k_hp_l2<3>), dim3(grid), dim3(256), shm, s, g, tb, a, b, partial);
 }
 
-size_t hp_setup_lds(int d, int pmax) {
+size_t hp_setup_lds(int d, int pmax, bool block_in_lds) {
     size_t best = 0;
     for (int p = 2; p <= pmax; ++p) {
         const size_t P = p - 1, q = p + 1;
@@ -496,7 +525,7 @@ size_t hp_setup_lds(int d, int pmax) {
             S *= q;
         }
         const size_t sT1 = d == 1 ? 1 : (d == 2 ? q * P * P : q * q * P * P);
-        best = std::max(best, (2 * S + sT1 + 2 * n) * sizeof(double));
+        best = std::max(best, (2 * S + sT1 + 2 * n + (block_in_lds ? n * n : 0)) * sizeof(double));
     }
     return best;
 }
@@ -504,14 +533,20 @@ size_t hp_setup_lds(int d, int pmax) {
 void launch_hp_setup(const HpGeo& g, const HpTabs<double>& tb, const double* psi, double alpha,
                      double beta, const double* C, const int64_t* c_off, const int32_t* cclass,
                      double* om64, float* om32, double* s64, float* s32, size_t lds_bytes,
-                     hipStream_t s) {
+                     bool block_in_lds, hipStream_t s) {
     const unsigned grid = (unsigned)g.n_cells;
-#define HPG_HS(DD)                                                                             \
-    hipLaunchKernelGGL((k_hp_setup<DD>), dim3(grid), dim3(256), lds_bytes, s, g, tb, psi, alpha, \
-                       beta, C, c_off, cclass, om64, om32, s64, s32)
-    if (g.d == 1) HPG_HS(1);
-    else if (g.d == 2) HPG_HS(2);
-    else HPG_HS(3);
+#define HPG_HS(DD, LL)                                                                       \
+    hipLaunchKernelGGL((k_hp_setup<DD, LL>), dim3(grid), dim3(1024), lds_bytes, s, g, tb, psi, \
+                       alpha, beta, C, c_off, cclass, om64, om32, s64, s32)
+    if (block_in_lds) {
+        if (g.d == 1) HPG_HS(1, true);
+        else if (g.d == 2) HPG_HS(2, true);
+        else HPG_HS(3, true);
+    } else {
+        if (g.d == 1) HPG_HS(1, false);
+        else if (g.d == 2) HPG_HS(2, false);
+        else HPG_HS(3, false);
+    }
 #undef HPG_HS
 }
 
@@ -519,7 +554,7 @@ template <typename T>
 void launch_hp_prec_psi(const HpGeo& g, const T* sinv, const T* r, T* z, double* partial,
                         int nblocks, int nmax, const int* done, hipStream_t s) {
     const unsigned grid = grid_of(g.n_cells, 1, nblocks);
-    hipLaunchKernelGGL((k_hp_prec_psi<T>), dim3(grid), dim3(128), (size_t)nmax * sizeof(T), s, g,
+    hipLaunchKernelGGL((k_hp_prec_psi<T>), dim3(grid), dim3(256), (size_t)nmax * sizeof(T), s, g,
                        sinv, r, z, partial, done);
 }
 

@@ -113,6 +113,7 @@ struct Problem {
     dev::HpGeo hgeo{};
     int hp_lds_elems = 256, hp_nmax = 1, np_gath = 0, np_cell = 0;
     size_t hp_setup_bytes = 0;
+    bool hp_setup_in_lds = false;
     DevFdm<double> cfdm64;
     DevFdm<float> cfdm32;
     void build_hp();

@@ -833,8 +833,10 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
         dev::launch_hp_setup(hgeo, hp_tabs<double>(), d_psi, alpha, beta, hpd.C.as<double>(),
                              hpd.c_off.as<int64_t>(), hpd.cclass.as<int32_t>(),
                              prec == HPG_FP64 ? om64.as<double>() : nullptr,
-                             prec == HPG_FP64 ? nullptr : om32.as<float>(), sinv64.as<double>(),
-                             prec == HPG_FP64 ? nullptr : sinv32.as<float>(), hp_setup_bytes, s);
+                             prec == HPG_FP64 ? nullptr : om32.as<float>(),
+                             (prec == HPG_FP64 || !hp_setup_in_lds) ? sinv64.as<double>() : nullptr,
+                             prec == HPG_FP64 ? nullptr : sinv32.as<float>(), hp_setup_bytes,
+                             hp_setup_in_lds, s);
     } else if (gradient) {
         const bool hbm = dev::setup_grad_in_hbm(geo);
         dev::launch_setup_grad(geo, tab64.view(), d_psi, PhiQ.as<double>(), beta,

@@ -38,7 +38,9 @@ void Problem::build_hp() {
     hp_lds_elems = std::max(256, Smax);
     if ((size_t)6 * hp_lds_elems * sizeof(double) > lds_max)
         fail(HPG_ERR_INVALID_ARG, "(p+1)^d too large for the per-cell-degree kernels");
-    hp_setup_bytes = dev::hp_setup_lds(M.d, M.p);
+    // Schur blocks formed in LDS when the largest one fits, else in place in HBM
+    hp_setup_in_lds = dev::hp_setup_lds(M.d, M.p, true) <= lds_max;
+    hp_setup_bytes = dev::hp_setup_lds(M.d, M.p, hp_setup_in_lds);
     if (hp_setup_bytes > lds_max)
         fail(HPG_ERR_INVALID_ARG, "P^d too large for the per-cell-degree Schur block setup");
     hp_nmax = nmax;
@@ -101,7 +103,7 @@ void Problem::build_hp() {
     np_u = np_gath;
     np_psi = np_cell;
     np_dot = 512;
-    np_prec = (int)std::min<int64_t>(M.n_cells, 1024);
+    np_prec = (int)std::min<int64_t>(M.n_cells, 4096);
     fdm_dot_fused = false;
     use_tile = false;
     np_cap = std::max({np_u + np_psi, np_dot + np_prec, 2 * np_cell});
@@ -232,11 +234,15 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
     ensure_fdm_hp();
     const DevFdm<T>& F = cfdm_of(*this, r);
     const double* prm = params.as<double>();
-    tstart("prec_psi", s);
+    // the psi-block on the side stream, concurrently with the A-block
+    const bool par = !timing && !single_stream;
+    hipStream_t s_psi = par ? side : s;
+    if (par) fork(s);
+    tstart("prec_psi", s_psi);
     const T* sinv = (dbl ? sinv64 : sinv32).template as<T>();
     dev::launch_hp_prec_psi<T>(hgeo, sinv, r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr,
-                               np_prec, hp_nmax, dn, s);
-    tstop("prec_psi", s);
+                               np_prec, hp_nmax, dn, s_psi);
+    tstop("prec_psi", s_psi);
     tstart("prec_u", s);
     // edge / face / interior entities
     const int64_t n_ent = (int64_t)hph.ent_n.size();
@@ -289,6 +295,7 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
     }
     if (part) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
     tstop("prec_u", s);
+    if (par) join(s);
 }
 
 template void Problem::apply_G_hp<double>(const double*, double*, double*, const int*, hipStream_t);
