@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-hp", action="store_true",
                     help="skip the per-cell-degree workload (2-D 64x64, degrees 2..12)")
     ap.add_argument("--hp-steps", type=int, default=2)
+    ap.add_argument("--hp-only", action="store_true",
+                    help="run only the per-cell-degree workload (for profiling)")
     ap.add_argument("--counters", action="store_true",
                     help="only a few operator launches for rocprofv3 --pmc passes: the "
                          "workload's G apply and preconditioner (FP32 and FP64), the 4096^2 "
@@ -405,6 +407,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_run(args, torch, hpg, W)
+        return
+    if args.hp_only:
+        print(json.dumps({"hp_dip_64x64": hp_bench(args, torch, hpg, W)}), flush=True)
         return
     f, phi = W.w2d(args.seed)
     mesh = hpg.Mesh(2, [args.m, args.m], args.p)

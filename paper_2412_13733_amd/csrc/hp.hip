@@ -399,7 +399,16 @@ __global__ __launch_bounds__(256) void k_hp_prec_psi(HpGeo g, const T* __restric
             T acc = 0;
             if (grp < nsplit && i < n) {
                 const int j1 = min(n, (grp + 1) * chunk);
-                for (int j = grp * chunk; j < j1; ++j) acc += Sb[(int64_t)j * n + i] * rb[j];
+                T a1 = 0, a2 = 0, a3 = 0;
+                int j = grp * chunk;
+                for (; j + 4 <= j1; j += 4) {
+                    acc += Sb[(int64_t)j * n + i] * rb[j];
+                    a1 += Sb[(int64_t)(j + 1) * n + i] * rb[j + 1];
+                    a2 += Sb[(int64_t)(j + 2) * n + i] * rb[j + 2];
+                    a3 += Sb[(int64_t)(j + 3) * n + i] * rb[j + 3];
+                }
+                for (; j < j1; ++j) acc += Sb[(int64_t)j * n + i] * rb[j];
+                acc = (acc + a1) + (a2 + a3);
             }
             acc_s[t] = acc;
             __syncthreads();
@@ -440,26 +449,40 @@ __global__ __launch_bounds__(256) void k_hp_vscatter(int64_t n, const int32_t* _
         z[idx[i]] = in[i];
 }
 
-// z_E = (1/alpha) Ainv_E r_E (Ainv_E symmetric: read by columns, coalesced)
+// z_E = (1/alpha) Ainv_E r_E, one thread per unknown of a non-vertex entity
+// (ent_of[g]: its entity, -1 for vertices).  An entity's unknowns are
+// consecutive, so a wave reads consecutive columns of row j of the symmetric
+// inverse (coalesced) and broadcasts r_j.
 template <typename T>
-__global__ __launch_bounds__(64) void k_hp_entity(int64_t n_ent, const int32_t* __restrict__ first,
-                                                  const int32_t* __restrict__ cnt,
-                                                  const int64_t* __restrict__ off,
-                                                  const T* __restrict__ inv,
-                                                  const double* __restrict__ prm,
-                                                  const T* __restrict__ r, T* __restrict__ z,
-                                                  const int* __restrict__ done) {
+__global__ __launch_bounds__(256) void k_hp_entity(int64_t n_u, const int32_t* __restrict__ ent_of,
+                                                   const int32_t* __restrict__ first,
+                                                   const int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ off,
+                                                   const T* __restrict__ inv,
+                                                   const double* __restrict__ prm,
+                                                   const T* __restrict__ r, T* __restrict__ z,
+                                                   const int* __restrict__ done) {
     if (done && *done) return;
     const T ia = (T)prm[2];
-    for (int64_t e = blockIdx.x; e < n_ent; e += gridDim.x) {
-        const int n = cnt[e];
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < n_u;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        const int e = ent_of[gi];
+        if (e < 0) continue;
         const int64_t f = first[e];
-        const T* A = inv + off[e];
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            T acc = 0;
-            for (int j = 0; j < n; ++j) acc += A[(int64_t)j * n + i] * r[f + j];
-            z[f + i] = ia * acc;
+        const int n = cnt[e], i = (int)(gi - f);
+        const T* A = inv + off[e] + i;
+        const T* rr = r + f;
+        // four independent partial sums keep several loads in flight
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            a0 += A[(int64_t)j * n] * rr[j];
+            a1 += A[(int64_t)(j + 1) * n] * rr[j + 1];
+            a2 += A[(int64_t)(j + 2) * n] * rr[j + 2];
+            a3 += A[(int64_t)(j + 3) * n] * rr[j + 3];
         }
+        for (; j < n; ++j) a0 += A[(int64_t)j * n] * rr[j];
+        z[gi] = ia * ((a0 + a1) + (a2 + a3));
     }
 }
 
@@ -573,11 +596,11 @@ void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const 
 }
 
 template <typename T>
-void launch_hp_entity(int64_t n_ent, const int32_t* first, const int32_t* cnt, const int64_t* off,
-                      const T* inv, const double* prm, const T* r, T* z, const int* done,
-                      hipStream_t s) {
-    hipLaunchKernelGGL((k_hp_entity<T>), dim3(grid_of(n_ent, 1, 8192)), dim3(64), 0, s, n_ent,
-                       first, cnt, off, inv, prm, r, z, done);
+void launch_hp_entity(int64_t n_u, const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
+                      const int64_t* off, const T* inv, const double* prm, const T* r, T* z,
+                      const int* done, hipStream_t s) {
+    hipLaunchKernelGGL((k_hp_entity<T>), dim3(grid_of(n_u, 256, 8192)), dim3(256), 0, s, n_u,
+                       ent_of, first, cnt, off, inv, prm, r, z, done);
 }
 
 #define HPG_INST(T)                                                                               \
@@ -593,9 +616,9 @@ void launch_hp_entity(int64_t n_ent, const int32_t* first, const int32_t* cnt, c
                                        hipStream_t);                                               \
     template void launch_hp_vscatter<T>(int64_t, const int32_t*, const T*, T*, const int*,        \
                                         hipStream_t);                                              \
-    template void launch_hp_entity<T>(int64_t, const int32_t*, const int32_t*, const int64_t*,    \
-                                      const T*, const double*, const T*, T*, const int*,          \
-                                      hipStream_t);
+    template void launch_hp_entity<T>(int64_t, const int32_t*, const int32_t*, const int32_t*,    \
+                                      const int64_t*, const T*, const double*, const T*, T*,      \
+                                      const int*, hipStream_t);
 HPG_INST(double)
 HPG_INST(float)
 #undef HPG_INST

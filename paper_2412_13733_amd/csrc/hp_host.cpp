@@ -326,6 +326,9 @@ void hp_build_host(const Mesh& M, int lds_elems, HpHost& H) {
                 H.ent_n.push_back(n);
                 H.ent_off.push_back(it->second);
             }
+    H.ent_of.assign(M.n_u, -1);
+    for (size_t e = 0; e < H.ent_n.size(); ++e)
+        for (int i = 0; i < H.ent_n[e]; ++i) H.ent_of[H.ent_first[e] + i] = (int32_t)e;
 }
 
 }  // namespace hpg

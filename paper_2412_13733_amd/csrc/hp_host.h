@@ -23,6 +23,7 @@ struct HpHost {
     std::vector<int32_t> vert;              // interior-vertex unknowns, tensor order
     int nv[3] = {1, 1, 1};                  // interior vertices per direction
     std::vector<int32_t> ent_first, ent_n;  // other entities: first unknown, count
+    std::vector<int32_t> ent_of;            // entity of each u unknown (-1: vertex)
     std::vector<int64_t> ent_off;           // offset of the entity's inverse in inv
     std::vector<double> inv;                // inverses of A restricted to an entity
 };

@@ -250,10 +250,11 @@ void launch_hp_vgather(int64_t n, const int32_t* idx, const T* r, T* out, const 
 template <typename T>
 void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const int* done,
                         hipStream_t s);
+// (ent_of: entity of each u unknown, -1 for vertices; one thread per unknown)
 template <typename T>
-void launch_hp_entity(int64_t n_ent, const int32_t* first, const int32_t* cnt, const int64_t* off,
-                      const T* inv, const double* prm, const T* r, T* z, const int* done,
-                      hipStream_t s);
+void launch_hp_entity(int64_t n_u, const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
+                      const int64_t* off, const T* inv, const double* prm, const T* r, T* z,
+                      const int* done, hipStream_t s);
 
 }  // namespace dev
 }  // namespace hpg

@@ -107,7 +107,7 @@ struct Problem {
     HpHost hph;
     struct HpDev {
         DBuf cell_p, loc_off, psi_off, qp_off, sinv_off, loc2glob, inc_ptr, inc_idx, order;
-        DBuf item_start, item_count, item_p, cclass, c_off, C, vert, ent_first, ent_n, ent_off;
+        DBuf item_start, item_count, item_p, cclass, c_off, C, vert, ent_first, ent_n, ent_off, ent_of;
         DBuf inv64, inv32, tab64, tab32, toff, h64[3], h32[3], yloc64, yloc32, cv64, cv32;
     } hpd;
     dev::HpGeo hgeo{};

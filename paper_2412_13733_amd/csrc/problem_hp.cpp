@@ -65,6 +65,7 @@ void Problem::build_hp() {
     upload(hpd.ent_first, H.ent_first.empty() ? std::vector<int32_t>(1, 0) : H.ent_first);
     upload(hpd.ent_n, H.ent_n.empty() ? std::vector<int32_t>(1, 0) : H.ent_n);
     upload(hpd.ent_off, H.ent_off.empty() ? std::vector<int64_t>(1, 0) : H.ent_off);
+    upload(hpd.ent_of, H.ent_of);
     upload(hpd.inv64, H.inv.empty() ? std::vector<double>(1, 0.0) : H.inv);
     upload(hpd.inv32, cast<float>(H.inv.empty() ? std::vector<double>(1, 0.0) : H.inv));
     upload(hpd.tab64, H.tab);
@@ -99,7 +100,7 @@ void Problem::build_hp() {
     // reduction layout: G apply = [gather blocks | cell blocks] (the u / psi
     // halves of the generic layout), preconditioner = [dot blocks | psi blocks]
     np_gath = (int)std::min<int64_t>((M.n_u + 255) / 256, 1024);
-    np_cell = std::min(hgeo.n_items, 1024);
+    np_cell = std::min(hgeo.n_items, 4096);   // one block per work item up to 4096
     np_u = np_gath;
     np_psi = np_cell;
     np_dot = 512;
@@ -245,11 +246,10 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
     tstop("prec_psi", s_psi);
     tstart("prec_u", s);
     // edge / face / interior entities
-    const int64_t n_ent = (int64_t)hph.ent_n.size();
-    if (n_ent > 0)
-        dev::launch_hp_entity<T>(n_ent, hpd.ent_first.as<int32_t>(), hpd.ent_n.as<int32_t>(),
-                                 hpd.ent_off.as<int64_t>(), (dbl ? hpd.inv64 : hpd.inv32).template as<T>(),
-                                 prm, r, z, dn, s);
+    if (!hph.ent_n.empty())
+        dev::launch_hp_entity<T>(M.n_u, hpd.ent_of.as<int32_t>(), hpd.ent_first.as<int32_t>(),
+                                 hpd.ent_n.as<int32_t>(), hpd.ent_off.as<int64_t>(),
+                                 (dbl ? hpd.inv64 : hpd.inv32).template as<T>(), prm, r, z, dn, s);
     // vertices: (alpha A_VV)^{-1} by fast diagonalisation on the interior-vertex grid
     const int64_t nv = (int64_t)hph.vert.size();
     if (nv > 0) {

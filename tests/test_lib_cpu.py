@@ -93,3 +93,23 @@ def test_gradient_footprint_counts_component_blocks():
     assert gr.n_psi == 8 * 8 * 2 * 16      # d components of P^d = p^d modes per cell
     # psi blocks (d P^d)^2 per cell dominate the difference
     assert gr.footprint(hpg.FP64) - ob.footprint(hpg.FP64) > 8 * 64 * (32 * 32 - 9 * 9)
+
+
+def test_per_cell_degree_mesh_matches_the_oracle_numbering_sizes():
+    # host-only: unknown counts and Gauss points of hp meshes against the oracle
+    from oracle.hpmesh import HpMesh
+    rng = np.random.default_rng(3)
+    for d, m in ((1, 6), (2, 4), (3, 2)):
+        deg = rng.integers(2, 8, size=m ** d)
+        br = [np.sort(np.r_[0.0, rng.uniform(0.05, 0.95, m - 1), 1.0]) for _ in range(d)]
+        g = hpg.Mesh(d, [m] * d, 0, breaks=br, degree=deg)
+        o = HpMesh(br, deg)
+        assert (g.n_u, g.n_psi, g.n_qp, g.p) == (o.n_u, o.n_psi, o.n_qp, int(deg.max()))
+        assert np.max(np.abs(g.quadrature_points() - o.quadrature_points())) < 1e-15
+    with pytest.raises(hpg.HpgError):
+        hpg.Mesh(2, [2, 2], 0, constraint=hpg.GRADIENT, degree=[2, 2, 2, 2])
+    with pytest.raises(hpg.HpgError):
+        hpg.Mesh(2, [2, 2], 0, degree=[2, 1, 3, 2])
+    a = hpg.Mesh(2, [16, 16], 0, degree=np.full(256, 6))
+    b = hpg.Mesh(2, [16, 16], 0, degree=np.r_[np.full(128, 6), np.full(128, 3)])
+    assert a.footprint(0) > b.footprint(0) > 0
