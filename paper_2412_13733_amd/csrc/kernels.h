@@ -125,6 +125,12 @@ void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const
                  int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, int batch,
                  const int* done, const GemmEpi<T>& ep, hipStream_t s,
                  const KernelEvents* ev = nullptr);
+// launch_gemm (batch 1, no strides) and launch_prec_psi in one launch: the
+// GEMM tiles and the psi-block cell groups are independent blocks of one grid
+template <typename T>
+void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+                      int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
+                      int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s);
 template <typename T>
 void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
                       const int* done, hipStream_t s);

@@ -476,20 +476,16 @@ __global__ __launch_bounds__(256) void k_setup_big(Geo g, PsiTabs<double> tb,
 // (the blocks are symmetric, so row i is read as column i: conflict-free).
 // Partial dot <z, r> fused.
 template <typename T>
-__global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cpb,
-                                                  const T* __restrict__ sinv,
-                                                  const T* __restrict__ r, T* __restrict__ z,
-                                                  double* __restrict__ partial,
-                                                  const int* __restrict__ done) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[4];
+__device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, int cpb,
+                                     const T* __restrict__ sinv, const T* __restrict__ r,
+                                     T* __restrict__ z, double* __restrict__ partial,
+                                     const int* __restrict__ done, T* Sb, double* red) {
     if (done && *done) return;
-    T* Sb = reinterpret_cast<T*>(smem_raw);
     const int nn = n * n;
     T* Rb = Sb + cpb * nn;
     double part = 0.0;
     const int64_t ngroups = (n_cells + cpb - 1) / cpb;
-    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    for (int64_t grp = bid; grp < ngroups; grp += nblk) {
         const int64_t cell0 = grp * cpb;
         const int nc = (int)min((int64_t)cpb, n_cells - cell0);
         const T* src = sinv + cell0 * (int64_t)nn;
@@ -518,8 +514,21 @@ __global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cp
     }
     if (partial) {
         double s2 = block_sum(part, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s2;
+        if (threadIdx.x == 0) partial[bid] = s2;
     }
+}
+
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cpb,
+                                                  const T* __restrict__ sinv,
+                                                  const T* __restrict__ r, T* __restrict__ z,
+                                                  double* __restrict__ partial,
+                                                  const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[4];
+    prec_psi_body<T>(blockIdx.x, gridDim.x, n_cells, n, cpb, sinv, r, z, partial, done,
+                     reinterpret_cast<T*>(smem_raw), red);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,22 +563,22 @@ struct Mfma<float> {
 // eigenvalues) (the eigen-space division of the fast diagonalisation) and/or
 // accumulate <C, dotv> per block into partial[block]
 
+// one 16x16 tile (bx, by) of batch bz; the partial of the fused dot goes to
+// partial[pidx]
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T* __restrict__ A,
-                                                   int64_t lda, int64_t sA,
-                                                   const T* __restrict__ B, int64_t ldb,
-                                                   int64_t sB, T* __restrict__ C, int64_t ldc,
-                                                   int64_t sC, const int* __restrict__ done,
-                                                   GemmEpi<T> ep) {
-    __shared__ T red[4][256];
-    __shared__ double rsum[4];
+__device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int M, int N, int K,
+                                      const T* __restrict__ A, int64_t lda, int64_t sA,
+                                      const T* __restrict__ B, int64_t ldb, int64_t sB,
+                                      T* __restrict__ C, int64_t ldc, int64_t sC,
+                                      const int* __restrict__ done, const GemmEpi<T>& ep,
+                                      T (*red)[256], double* rsum) {
     if (done && *done) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t b = blockIdx.z;
+    const int64_t b = bz;
     A += b * sA;
     B += b * sB;
     C += b * sC;
-    const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+    const int i0 = by * 16, j0 = bx * 16;
     const int ar = i0 + (lane & 15), kk = lane >> 4, bc = j0 + (lane & 15);
     const bool rok = ar < M, cok = bc < N;
     typename Mfma<T>::V acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
@@ -623,8 +632,48 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T*
     }
     if (ep.partial) {
         const double tot = block_sum(part, rsum);
-        if (threadIdx.x == 0)
-            ep.partial[blockIdx.x + gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z)] = tot;
+        if (threadIdx.x == 0) ep.partial[pidx] = tot;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T* __restrict__ A,
+                                                   int64_t lda, int64_t sA,
+                                                   const T* __restrict__ B, int64_t ldb,
+                                                   int64_t sB, T* __restrict__ C, int64_t ldc,
+                                                   int64_t sC, const int* __restrict__ done,
+                                                   GemmEpi<T> ep) {
+    __shared__ T red[4][256];
+    __shared__ double rsum[4];
+    gemm_tile_body<T>(blockIdx.x, blockIdx.y, blockIdx.z,
+                      blockIdx.x + gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z), M, N,
+                      K, A, lda, sA, B, ldb, sB, C, ldc, sC, done, ep, red, rsum);
+}
+
+// The first fast-diagonalisation pass (one GEMM, batch 1) and the psi-block
+// preconditioner in one launch: both read the same residual and are
+// independent, so blocks [0, gx gy) take GEMM tiles and the remaining np
+// blocks the psi-block cell groups.  Saves a dependent launch per iteration.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T* __restrict__ A,
+                                                   int64_t lda, const T* __restrict__ B,
+                                                   int64_t ldb, T* __restrict__ C, int64_t ldc,
+                                                   const int* __restrict__ done, GemmEpi<T> ep,
+                                                   int gx, int gy, int64_t n_cells, int n, int cpb,
+                                                   const T* __restrict__ sinv,
+                                                   const T* __restrict__ r, T* __restrict__ z,
+                                                   double* __restrict__ ppart) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T red[4][256];
+    __shared__ double rsum[4];
+    const int ng = gx * gy;
+    if ((int)blockIdx.x < ng) {
+        const int bx = blockIdx.x % gx, by = blockIdx.x / gx;
+        gemm_tile_body<T>(bx, by, 0, bx + (int64_t)gx * by, M, N, K, A, lda, 0, B, ldb, 0, C, ldc,
+                          0, done, ep, red, rsum);
+    } else {
+        prec_psi_body<T>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv, r, z, ppart,
+                         done, reinterpret_cast<T*>(smem_raw), rsum);
     }
 }
 
@@ -982,6 +1031,17 @@ void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const
 }
 
 template <typename T>
+void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+                      int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
+                      int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s) {
+    const int gx = (N + 15) / 16, gy = (M + 15) / 16;
+    const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
+    const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
+    hipLaunchKernelGGL((k_gemm_prec<T>), dim3(gx * gy + np), dim3(256), shm, s, M, N, K, A, lda, B,
+                       ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb, sinv, r, z, ppart);
+}
+
+template <typename T>
 void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
                       const int* done, hipStream_t s) {
     dim3 grid(nblk(g.n_u));
@@ -1061,6 +1121,9 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
     template void launch_gemm<T>(int, int, int, const T*, int64_t, int64_t, const T*, int64_t,    \
                                  int64_t, T*, int64_t, int64_t, int, const int*,                 \
                                  const GemmEpi<T>&, hipStream_t, const KernelEvents*);           \
+    template void launch_gemm_prec<T>(int, int, int, const T*, int64_t, const T*, int64_t, T*,   \
+                                      int64_t, const int*, const GemmEpi<T>&, int64_t, int, int,  \
+                                      const T*, const T*, T*, double*, hipStream_t);             \
     template void launch_fdm_scale<T>(const Geo&, const T*, const T*, const T*, T, T*,          \
                                       const int*, hipStream_t);                                  \
     template void launch_kr_start<T>(int64_t, KState*, const double*, int, double, int, const T*, \

@@ -84,10 +84,12 @@ struct Problem {
     hipStream_t side = nullptr;            // second stream for the concurrent psi-side work
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_enter = nullptr, ev_leave = nullptr;
     bool use_graphs = true;
-    // every launch on the one stream (no fork/join onto the side stream): set for
-    // problems solved concurrently by the server, where waits between streams
-    // that share hardware queues with other problems' streams could block them
-    bool single_stream = false;
+    // every launch on the one stream (no fork/join onto the side stream): the
+    // default, since a captured fork/join cost more per Krylov iteration than
+    // the overlap it bought (measured), and required for problems solved
+    // concurrently by the server, where waits between streams that share
+    // hardware queues with other problems' streams could block them
+    bool single_stream = true;
     bool use_tile = false;                 // fused tiled G apply / residual available for (d, p)
     std::map<GraphKey, hipGraphExec_t> graphs;
     bool fdm_dot_fused = true;

@@ -943,19 +943,25 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
     T* t1 = kw.t1.template as<T>();
     T* t2 = kw.t2.template as<T>();
     const double* prm = params.as<double>();
-    const bool par = !timing && !single_stream;
+    // psi-block: z_psi = (-S_hat_K)^{-1} r_psi.  Untimed, with LDS-staged
+    // blocks, it shares one launch with the first fast-diagonalisation pass
+    // (extra blocks of that grid); otherwise it runs on the side stream
+    // concurrently with the A-block (timed runs: one stream, one group each)
+    const bool merged = !prec_big && !timing;
+    const bool par = !merged && !timing && !single_stream;
     hipStream_t s_psi = par ? side : s;
     if (par) fork(s);
-    // psi-block: z_psi = (-S_hat_K)^{-1} r_psi, concurrently with the A-block
-    tstart("prec_psi", s_psi);
-    if (prec_big)
-        dev::launch_prec_psi_big<T>(M.n_cells, (int)M.psi_per_cell, Sel<T>::sinv(*this),
-                                    r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr, np_prec,
-                                    dn, s_psi);
-    else
-        dev::launch_prec_psi<T>(M.n_cells, (int)M.psi_per_cell, cpb_prec, Sel<T>::sinv(*this),
-                                r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr, dn, s_psi);
-    tstop("prec_psi", s_psi);
+    if (!merged) {
+        tstart("prec_psi", s_psi);
+        if (prec_big)
+            dev::launch_prec_psi_big<T>(M.n_cells, (int)M.psi_per_cell, Sel<T>::sinv(*this),
+                                        r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr,
+                                        np_prec, dn, s_psi);
+        else
+            dev::launch_prec_psi<T>(M.n_cells, (int)M.psi_per_cell, cpb_prec, Sel<T>::sinv(*this),
+                                    r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr, dn, s_psi);
+        tstop("prec_psi", s_psi);
+    }
     // A-block: z_u = (alpha A)^{-1} r_u by fast diagonalisation: d forward
     // passes with V^T (the last one divides by alpha (lam_0 + ... )), then d
     // backward passes with V (the last one forms the partial sums of <z_u, r_u>)
@@ -987,7 +993,14 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                 // Y (R x N) = X (R x N) Mat^T with Mat = V^T (forward) / V (backward)
                 const T* Bm = ph == 0 ? F.V[k].template as<T>() : F.Vt[k].template as<T>();
                 const int R = (int)(M.n_u / N);
-                dev::launch_gemm<T>(R, N, N, src, N, 0, Bm, N, 0, dst, N, 0, 1, dn, ep, s, &ke);
+                if (merged && pass == 1)
+                    dev::launch_gemm_prec<T>(R, N, N, src, N, Bm, N, dst, N, dn, ep, M.n_cells,
+                                             (int)M.psi_per_cell, cpb_prec, Sel<T>::sinv(*this),
+                                             r + M.n_u, z + M.n_u,
+                                             part ? part + np_dot : nullptr, s);
+                else
+                    dev::launch_gemm<T>(R, N, N, src, N, 0, Bm, N, 0, dst, N, 0, 1, dn, ep, s,
+                                        &ke);
             } else {
                 // Y_o (N x inner) = Mat (N x N) X_o (N x inner)
                 const T* Am = ph == 0 ? F.Vt[k].template as<T>() : F.V[k].template as<T>();

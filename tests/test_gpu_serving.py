@@ -122,3 +122,43 @@ def test_served_result_matches_oracle(dim, m, p):
     log("served vs oracle", dim, m, p, "rel L2", eu)
     assert st.status == 0 and eu < 1e-10
     srv.close()
+
+
+def test_serving_per_cell_degree_requests_equal_alone_and_in_mix():
+    # per-cell-degree (hp) meshes served together with uniform ones
+    from paper_2412_13733_amd import hpg
+    reqs = []
+    for i in range(6):
+        rng = np.random.default_rng(900 + i)
+        n = int(rng.integers(4, 9))
+        deg = rng.integers(2, 8, size=n * n) if i % 2 == 0 else None
+        reqs.append((n, deg, int(rng.integers(2, 7)), i % 3 == 2))
+
+    def build(n, deg, p, i):
+        mesh = hpg.Mesh(2, [n, n], p, degree=deg)
+        x = mesh.quadrature_points()
+        f, phi = W.w2d_dip(i) if deg is not None else W.w2d(i)
+        return mesh, f(x), phi(x)
+
+    alone = []
+    for i, (n, deg, p, mixed) in enumerate(reqs):
+        mesh, f, phi = build(n, deg, p, i)
+        prob = hpg.Problem(mesh)
+        prob.set_forcing(f)
+        prob.set_obstacle(phi)
+        u, psi, _, st = prob.solve(_opts(hpg, hpg.MIXED if mixed else hpg.FP64))
+        log("hp alone", i, n, "hp" if deg is not None else p, st.as_dict())
+        assert st.status == 0
+        alone.append((u, psi))
+        del prob
+    srv = hpg.Server(device=0, max_slots=3)
+    ts = []
+    for i, (n, deg, p, mixed) in enumerate(reqs):
+        mesh, f, phi = build(n, deg, p, i)
+        ts.append(srv.submit(mesh, f, phi, _opts(hpg, hpg.MIXED if mixed else hpg.FP64)))
+    for i, t in enumerate(ts):
+        u, psi, st, info = srv.wait(t)
+        assert st.status == 0
+        assert np.array_equal(u, alone[i][0]) and np.array_equal(psi, alone[i][1])
+        assert 0 < info.device_bytes <= info.footprint
+    srv.close()
