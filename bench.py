@@ -79,6 +79,9 @@ def counters_run(args, torch, hpg, W):
     g = torch.Generator(device="cuda")
     g.manual_seed(1)
     psi = 0.5 * torch.randn(mesh.n_psi, dtype=torch.float64, device="cuda", generator=g)
+    # kernel timing on: every group launched on its own, as in the timed pass
+    # whose per-kernel durations the roofline uses
+    prob.set_kernel_timing("all")
     for prec, dt in ((hpg.MIXED, torch.float32), (hpg.FP64, torch.float64)):
         prob.op_setup(psi, 4.0, 0.0, precision=prec)
         v = torch.randn(n, dtype=dt, device="cuda", generator=g)
@@ -87,6 +90,7 @@ def counters_run(args, torch, hpg, W):
             prob.op_apply_prec(v, w)
             prob.op_apply_G(v, w)
     torch.cuda.synchronize()
+    prob.set_kernel_timing(None)
     del prob
     args.probe_launches = 5
     apply_probe(args, torch, hpg)
