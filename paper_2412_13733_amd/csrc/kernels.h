@@ -143,11 +143,21 @@ void launch_kr_start(int64_t n, KState* st0, const double* partial, int np, doub
                      T* wcur, T* x, hipStream_t s);
 template <typename T>
 void launch_kr_vhat(int64_t n, KState* st, const double* partial, int np, const T* Gq,
-                    const T* vcur, T* vprev, hipStream_t s);
+                    const T* vcur, const T* vprev, T* vhat, hipStream_t s);
 template <typename T>
 void launch_kr_update(int64_t n, const KState* st_in, KState* st_out, const double* partial,
-                      int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* z,
-                      hipStream_t s);
+                      int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* vhat,
+                      const T* z, hipStream_t s);
+// launch_gemm_prec with the Lanczos step folded in: every block reduces the
+// G-apply partials gpart (npg) to delta = <q, Gq> (stored in st), and the
+// first pass (A = vhat, R x N with lda N, B = V, C) and the psi-block read
+// vhat = Gq - delta vcur - gamma vprev, which is also stored to vhat (n_u +
+// psi entries).  The psi-block partials go to ppart.
+template <typename T>
+void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep, int64_t n_cells,
+                           int n, int cpb, const T* sinv, T* z, double* ppart, KState* st,
+                           const double* gpart, int npg, const T* Gq, const T* vcur,
+                           const T* vprev, T* vhat, int64_t n_u, hipStream_t s);
 template <typename TI, typename TO>
 void launch_convert(int64_t n, const TI* a, TO* b, double scale, hipStream_t s);
 template <typename T>

@@ -475,11 +475,35 @@ __global__ __launch_bounds__(256) void k_setup_big(Geo g, PsiTabs<double> tb,
 // coalesced loads, then one thread per (cell, row) forms the row product
 // (the blocks are symmetric, so row i is read as column i: conflict-free).
 // Partial dot <z, r> fused.
+// fixed-order sum of np partials, identical in every block (valid in all threads)
+__device__ inline double reduce_partials(const double* __restrict__ p, int np, double* red,
+                                         double* bcast) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += p[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *bcast = s;
+    __syncthreads();
+    return *bcast;
+}
+
+// the next Lanczos vector formed where it is read: vhat = Gq - dl vcur - gm vprev
+// (element i), optionally stored to out[i] by the one block that reads it
 template <typename T>
+struct VhatSrc {
+    const T* Gq;
+    const T* vcur;
+    const T* vprev;
+    T* out;
+    T dl, gm;
+    __device__ inline T at(int64_t i) const { return Gq[i] - dl * vcur[i] - gm * vprev[i]; }
+};
+
+template <typename T, bool VH = false>
 __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, int cpb,
                                      const T* __restrict__ sinv, const T* __restrict__ r,
                                      T* __restrict__ z, double* __restrict__ partial,
-                                     const int* __restrict__ done, T* Sb, double* red) {
+                                     const int* __restrict__ done, T* Sb, double* red,
+                                     const VhatSrc<T>* vs = nullptr, int64_t voff = 0) {
     if (done && *done) return;
     const int nn = n * n;
     T* Rb = Sb + cpb * nn;
@@ -499,7 +523,16 @@ __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, 
             Sb[e + 768] = v3;
         }
         for (; e < tot; e += 256) Sb[e] = src[e];
-        for (int i = threadIdx.x; i < nc * n; i += 256) Rb[i] = r[cell0 * n + i];
+        for (int i = threadIdx.x; i < nc * n; i += 256) {
+            if (VH) {
+                const int64_t gi = voff + cell0 * n + i;
+                const T v = vs->at(gi);
+                vs->out[gi] = v;
+                Rb[i] = v;
+            } else {
+                Rb[i] = r[cell0 * n + i];
+            }
+        }
         __syncthreads();
         for (int i = threadIdx.x; i < nc * n; i += 256) {
             const int ci = i / n, row = i - ci * n;
@@ -565,13 +598,14 @@ struct Mfma<float> {
 
 // one 16x16 tile (bx, by) of batch bz; the partial of the fused dot goes to
 // partial[pidx]
-template <typename T>
+template <typename T, bool VH = false>
 __device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int M, int N, int K,
                                       const T* __restrict__ A, int64_t lda, int64_t sA,
                                       const T* __restrict__ B, int64_t ldb, int64_t sB,
                                       T* __restrict__ C, int64_t ldc, int64_t sC,
                                       const int* __restrict__ done, const GemmEpi<T>& ep,
-                                      T (*red)[256], double* rsum) {
+                                      T (*red)[256], double* rsum,
+                                      const VhatSrc<T>* vs = nullptr) {
     if (done && *done) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t b = bz;
@@ -589,7 +623,19 @@ __device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int 
 #pragma unroll
         for (int u = 0; u < 12; ++u) {
             const int ka = k0 + 16 * u + kk;
-            a[u] = (rok && ka < K) ? A[(int64_t)ar * lda + ka] : (T)0;
+            if (VH) {
+                // A = vhat (batch 0, no stride): formed here; the blocks of the
+                // first tile column store it (each element once)
+                T v = (T)0;
+                if (rok && ka < K) {
+                    const int64_t gi = (int64_t)ar * lda + ka;
+                    v = vs->at(gi);
+                    if (bx == 0) vs->out[gi] = v;
+                }
+                a[u] = v;
+            } else {
+                a[u] = (rok && ka < K) ? A[(int64_t)ar * lda + ka] : (T)0;
+            }
             bb[u] = (cok && ka < K) ? B[(int64_t)ka * ldb + bc] : (T)0;
         }
 #pragma unroll
@@ -654,6 +700,41 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T*
 // preconditioner in one launch: both read the same residual and are
 // independent, so blocks [0, gx gy) take GEMM tiles and the remaining np
 // blocks the psi-block cell groups.  Saves a dependent launch per iteration.
+// As k_gemm_prec, with the MINRES step that forms the next Lanczos vector
+// folded in: every block reduces the G-apply partials of <q, Gq> in the same
+// fixed order (delta, stored by block 0), then the GEMM tiles and the
+// psi-block cells read vhat = Gq - delta v_cur - gamma v_prev where they load
+// the residual, and store it to vhat (each element by exactly one block).
+template <typename T>
+__global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, const T* __restrict__ B,
+                                                        int64_t ldb, T* __restrict__ C,
+                                                        int64_t ldc, GemmEpi<T> ep, int gx,
+                                                        int gy, int64_t n_cells, int n, int cpb,
+                                                        const T* __restrict__ sinv,
+                                                        T* __restrict__ z,
+                                                        double* __restrict__ ppart, KState* st,
+                                                        const double* __restrict__ gpart, int npg,
+                                                        const T* Gq, const T* vcur,
+                                                        const T* vprev, T* vhat, int64_t n_u) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T red[4][256];
+    __shared__ double rsum[4];
+    __shared__ double bc;
+    if (st->done) return;
+    const double delta = reduce_partials(gpart, npg, rsum, &bc);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->delta = delta;
+    VhatSrc<T> vs{Gq, vcur, vprev, vhat, (T)delta, (T)st->gamma};
+    const int ng = gx * gy;
+    if ((int)blockIdx.x < ng) {
+        const int bx = blockIdx.x % gx, by = blockIdx.x / gx;
+        gemm_tile_body<T, true>(bx, by, 0, bx + (int64_t)gx * by, M, N, K, nullptr, N, 0, B, ldb,
+                                0, C, ldc, 0, nullptr, ep, red, rsum, &vs);
+    } else {
+        prec_psi_body<T, true>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv, nullptr,
+                               z, ppart, nullptr, reinterpret_cast<T*>(smem_raw), rsum, &vs, n_u);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T* __restrict__ A,
                                                    int64_t lda, const T* __restrict__ B,
@@ -710,16 +791,6 @@ __global__ __launch_bounds__(256) void k_fdm_scale(Geo g, const T* __restrict__ 
 // reads a field that another block of the same kernel writes.  Once a state
 // is marked done every later kernel of the loop returns at once.
 
-// fixed-order sum of np partials, identical in every block (valid in all threads)
-__device__ inline double reduce_partials(const double* __restrict__ p, int np, double* red,
-                                         double* bcast) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += p[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) *bcast = s;
-    __syncthreads();
-    return *bcast;
-}
 
 // start: gamma1 = sqrt(<z1, b>), v_cur = b/gamma1, q = z1/gamma1, w = v_prev = x = 0
 template <typename T>
@@ -761,7 +832,8 @@ __global__ __launch_bounds__(256) void k_kr_start(int64_t n, KState* st0, const 
 // delta = <G q, q>;  vhat = G q - delta v_cur - gamma v_prev   (over v_prev)
 template <typename T>
 __global__ __launch_bounds__(256) void k_kr_vhat(int64_t n, KState* st, const double* partial,
-                                                 int np, const T* Gq, const T* vcur, T* vprev) {
+                                                 int np, const T* Gq, const T* vcur,
+                                                 const T* vprev, T* vhat) {
     __shared__ double red[4];
     __shared__ double bc;
     if (st->done) return;
@@ -770,7 +842,7 @@ __global__ __launch_bounds__(256) void k_kr_vhat(int64_t n, KState* st, const do
     const T dl = (T)delta, gm = (T)st->gamma;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        vprev[i] = Gq[i] - dl * vcur[i] - gm * vprev[i];
+        vhat[i] = Gq[i] - dl * vcur[i] - gm * vprev[i];
 }
 
 // gamma_new = sqrt(<z, vhat>), Givens rotation, then
@@ -779,7 +851,8 @@ __global__ __launch_bounds__(256) void k_kr_vhat(int64_t n, KState* st, const do
 template <typename T>
 __global__ __launch_bounds__(256) void k_kr_update(int64_t n, const KState* st_in, KState* st_out,
                                                    const double* partial, int np, T* q, T* wprev,
-                                                   const T* wcur, T* x, T* vprev, const T* z) {
+                                                   const T* wcur, T* x, T* vprev, const T* vhat,
+                                                   const T* z) {
     __shared__ double red[4];
     __shared__ double bc;
     __shared__ double sc[6];   // a1, a2, a3, step, 1/gamma_new, skip
@@ -833,7 +906,7 @@ __global__ __launch_bounds__(256) void k_kr_update(int64_t n, const KState* st_i
         const T wn = (T)((double)(q[i] - a3 * wprev[i] - a2 * wcur[i]) * ia1);
         wprev[i] = wn;
         x[i] += step * wn;
-        vprev[i] = (T)((double)vprev[i] * ig);
+        vprev[i] = (T)((double)vhat[i] * ig);
         q[i] = (T)((double)z[i] * ig);
     }
 }
@@ -1042,6 +1115,19 @@ void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, 
 }
 
 template <typename T>
+void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep, int64_t n_cells,
+                           int n, int cpb, const T* sinv, T* z, double* ppart, KState* st,
+                           const double* gpart, int npg, const T* Gq, const T* vcur,
+                           const T* vprev, T* vhat, int64_t n_u, hipStream_t s) {
+    const int gx = (N + 15) / 16, gy = (M + 15) / 16;
+    const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
+    const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
+    hipLaunchKernelGGL((k_vhat_gemm_prec<T>), dim3(gx * gy + np), dim3(256), shm, s, M, N, N, B, N,
+                       C, N, ep, gx, gy, n_cells, n, cpb, sinv, z, ppart, st, gpart, npg, Gq, vcur,
+                       vprev, vhat, n_u);
+}
+
+template <typename T>
 void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
                       const int* done, hipStream_t s) {
     dim3 grid(nblk(g.n_u));
@@ -1074,16 +1160,16 @@ void launch_kr_start(int64_t n, KState* st0, const double* partial, int np, doub
 }
 template <typename T>
 void launch_kr_vhat(int64_t n, KState* st, const double* partial, int np, const T* Gq,
-                    const T* vcur, T* vprev, hipStream_t s) {
+                    const T* vcur, const T* vprev, T* vhat, hipStream_t s) {
     hipLaunchKernelGGL((k_kr_vhat<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st, partial, np, Gq,
-                       vcur, vprev);
+                       vcur, vprev, vhat);
 }
 template <typename T>
 void launch_kr_update(int64_t n, const KState* st_in, KState* st_out, const double* partial,
-                      int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* z,
-                      hipStream_t s) {
+                      int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* vhat,
+                      const T* z, hipStream_t s) {
     hipLaunchKernelGGL((k_kr_update<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st_in, st_out,
-                       partial, np, q, wprev, wcur, x, vprev, z);
+                       partial, np, q, wprev, wcur, x, vprev, vhat, z);
 }
 template <typename TI, typename TO>
 void launch_convert(int64_t n, const TI* a, TO* b, double scale, hipStream_t s) {
@@ -1128,10 +1214,14 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
                                       const int*, hipStream_t);                                  \
     template void launch_kr_start<T>(int64_t, KState*, const double*, int, double, int, const T*, \
                                      const T*, T*, T*, T*, T*, T*, T*, hipStream_t);             \
-    template void launch_kr_vhat<T>(int64_t, KState*, const double*, int, const T*, const T*, T*, \
-                                    hipStream_t);                                                \
+    template void launch_kr_vhat<T>(int64_t, KState*, const double*, int, const T*, const T*,   \
+                                    const T*, T*, hipStream_t);                                  \
     template void launch_kr_update<T>(int64_t, const KState*, KState*, const double*, int, T*, T*, \
-                                      const T*, T*, T*, const T*, hipStream_t);                  \
+                                      const T*, T*, T*, const T*, const T*, hipStream_t);        \
+    template void launch_vhat_gemm_prec<T>(int, int, const T*, T*, const GemmEpi<T>&, int64_t,   \
+                                           int, int, const T*, T*, double*, KState*,             \
+                                           const double*, int, const T*, const T*, const T*, T*, \
+                                           int64_t, hipStream_t);                                \
     template void launch_axpy_to<T>(int64_t, const double*, double, const T*, double*,          \
                                     hipStream_t);                                                \
     template void launch_dot<T>(int64_t, const T*, const T*, double*, int, const int*, hipStream_t);

@@ -55,12 +55,27 @@ struct DevFdm {
     DBuf V[3], Vt[3], lam[3];
 };
 
-// MINRES workspace of one precision
+// MINRES workspace of one precision (vhat: the next Lanczos vector before
+// normalisation)
 template <typename T>
 struct KrylovWork {
-    DBuf z, vcur, vprev, q, Gq, wprev, wcur, t1, t2;
+    DBuf z, vcur, vprev, vhat, q, Gq, wprev, wcur, t1, t2;
     int64_t n = 0;
     void ensure(int64_t n_, int64_t n_u);
+};
+
+// the Lanczos step folded into the preconditioner's first launch: its input
+// vhat = Gq - delta vcur - gamma vprev is formed there from the G-apply
+// partials gpart (npg of them) and the MINRES state st, and stored to vhat
+template <typename T>
+struct VhatIn {
+    dev::KState* st;
+    const double* gpart;
+    int npg;
+    const T* Gq;
+    const T* vcur;
+    const T* vprev;
+    T* vhat;
 };
 
 struct TimingGroup {
@@ -144,7 +159,7 @@ struct Problem {
     // Krylov
     KrylovWork<double> kw64;
     KrylovWork<float> kw32;
-    DBuf partial, kstate;
+    DBuf partial, partial_g, kstate;       // partial_g: the G apply's partial sums
     int np_u = 0, np_psi = 0, np_dot = 0, np_prec = 0, np_cap = 0;
     // Newton state
     DBuf u, psi, psi_prev, ut, pt, R, u_old, delta64, delta32, rhs32, xk64;
@@ -168,7 +183,8 @@ struct Problem {
     template <typename T>
     void apply_G(const T* x, T* y, double* partial, const int* done, hipStream_t s);
     template <typename T>
-    void apply_prec(const T* r, T* z, double* partial, const int* done, hipStream_t s);
+    void apply_prec(const T* r, T* z, double* partial, const int* done, hipStream_t s,
+                    const VhatIn<T>* vin = nullptr);
     template <typename T>
     int minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s);
     template <typename T>

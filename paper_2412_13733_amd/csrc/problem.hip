@@ -210,6 +210,7 @@ void KrylovWork<T>::ensure(int64_t n_, int64_t n_u) {
     z.alloc(b);
     vcur.alloc(b);
     vprev.alloc(b);
+    vhat.alloc(b);
     q.alloc(b);
     Gq.alloc(b);
     wprev.alloc(b);
@@ -595,6 +596,7 @@ void Problem::build(const Mesh& mesh, int dev_) {
     use_tile = dev::tile_supported(geo) && std::getenv("HPG_GENERIC_APPLY") == nullptr;
     np_cap = std::max({np_u + np_psi, np_dot + np_prec, np_l2, 2 * dev::tile_grid(geo)});
     partial.alloc((size_t)np_cap * sizeof(double));
+    partial_g.alloc((size_t)np_cap * sizeof(double));
     params.alloc(4 * sizeof(double));
     kstate.alloc(2 * sizeof(dev::KState));
 }
@@ -932,7 +934,8 @@ void Problem::apply_G(const T* x, T* y, double* part, const int* dn, hipStream_t
 }
 
 template <typename T>
-void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStream_t s) {
+void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStream_t s,
+                         const VhatIn<T>* vin) {
     if (!linearised || precision != Sel<T>::prec)
         fail(HPG_ERR_INVALID_ARG, "operator not set up for this precision (call hpg_op_setup)");
     if (M.hp) return apply_prec_hp<T>(r, z, part, dn, s);
@@ -948,6 +951,8 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
     // (extra blocks of that grid); otherwise it runs on the side stream
     // concurrently with the A-block (timed runs: one stream, one group each)
     const bool merged = !prec_big && !timing;
+    if (vin && (!merged || r != vin->vhat))
+        fail(HPG_ERR_INVALID_ARG, "internal: folded Lanczos step without the merged first pass");
     const bool par = !merged && !timing && !single_stream;
     hipStream_t s_psi = par ? side : s;
     if (par) fork(s);
@@ -993,7 +998,14 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                 // Y (R x N) = X (R x N) Mat^T with Mat = V^T (forward) / V (backward)
                 const T* Bm = ph == 0 ? F.V[k].template as<T>() : F.Vt[k].template as<T>();
                 const int R = (int)(M.n_u / N);
-                if (merged && pass == 1)
+                if (vin && pass == 1)
+                    dev::launch_vhat_gemm_prec<T>(R, N, Bm, dst, ep, M.n_cells,
+                                                  (int)M.psi_per_cell, cpb_prec,
+                                                  Sel<T>::sinv(*this), z + M.n_u,
+                                                  part ? part + np_dot : nullptr, vin->st,
+                                                  vin->gpart, vin->npg, vin->Gq, vin->vcur,
+                                                  vin->vprev, vin->vhat, M.n_u, s);
+                else if (merged && pass == 1)
                     dev::launch_gemm_prec<T>(R, N, N, src, N, Bm, N, dst, N, dn, ep, M.n_cells,
                                              (int)M.psi_per_cell, cpb_prec, Sel<T>::sinv(*this),
                                              r + M.n_u, z + M.n_u,
@@ -1031,20 +1043,29 @@ void Problem::minres_iterations(int count, int par0, T*& vcur, T*& vprev, T*& wp
                                 T* q, T* Gq, T* z, T* x, hipStream_t s) {
     auto* st = kstate.as<dev::KState>();
     double* part = partial.as<double>();
+    double* gpart = partial_g.as<double>();   // the G apply's partials, apart from the preconditioner's
+    T* vhat = Sel<T>::kw(*this).vhat.template as<T>();
     const int64_t n = M.n_u + M.n_psi;
     const int npG = use_tile ? dev::tile_grid(geo) : np_u + np_psi, npP = np_dot + np_prec;
+    // untimed uniform-degree solves form vhat inside the preconditioner's first launch
+    const bool fold = !M.hp && !prec_big && !timing;
     int par = par0;
     for (int j = 0; j < count; ++j) {
         dev::KState* cur = st + par;
         dev::KState* nxt = st + (1 - par);
         const int* dn = &cur->done;
-        apply_G<T>(q, Gq, part, dn, s);
+        apply_G<T>(q, Gq, gpart, dn, s);
+        if (fold) {
+            const VhatIn<T> vin{cur, gpart, npG, Gq, vcur, vprev, vhat};
+            apply_prec<T>(vhat, z, part, dn, s, &vin);
+        } else {
+            tstart("minres_vec", s);
+            dev::launch_kr_vhat<T>(n, cur, gpart, npG, Gq, vcur, vprev, vhat, s);
+            tstop("minres_vec", s);
+            apply_prec<T>(vhat, z, part, dn, s);
+        }
         tstart("minres_vec", s);
-        dev::launch_kr_vhat<T>(n, cur, part, npG, Gq, vcur, vprev, s);
-        tstop("minres_vec", s);
-        apply_prec<T>(vprev, z, part, dn, s);
-        tstart("minres_vec", s);
-        dev::launch_kr_update<T>(n, cur, nxt, part, npP, q, wprev, wcur, x, vprev, z, s);
+        dev::launch_kr_update<T>(n, cur, nxt, part, npP, q, wprev, wcur, x, vprev, vhat, z, s);
         tstop("minres_vec", s);
         std::swap(vprev, vcur);
         std::swap(wprev, wcur);
@@ -1388,8 +1409,10 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
 
 template void Problem::apply_G<double>(const double*, double*, double*, const int*, hipStream_t);
 template void Problem::apply_G<float>(const float*, float*, double*, const int*, hipStream_t);
-template void Problem::apply_prec<double>(const double*, double*, double*, const int*, hipStream_t);
-template void Problem::apply_prec<float>(const float*, float*, double*, const int*, hipStream_t);
+template void Problem::apply_prec<double>(const double*, double*, double*, const int*, hipStream_t,
+                                          const VhatIn<double>*);
+template void Problem::apply_prec<float>(const float*, float*, double*, const int*, hipStream_t,
+                                         const VhatIn<float>*);
 template int Problem::minres<double>(const double*, double*, double, int, int, hipStream_t);
 template int Problem::minres_on<double>(const double*, double*, double, int, int, hipStream_t);
 template int Problem::minres_on<float>(const float*, float*, double, int, int, hipStream_t);

@@ -109,6 +109,7 @@ void Problem::build_hp() {
     use_tile = false;
     np_cap = std::max({np_u + np_psi, np_dot + np_prec, 2 * np_cell});
     partial.alloc((size_t)np_cap * sizeof(double));
+    partial_g.alloc((size_t)np_cap * sizeof(double));
     params.alloc(4 * sizeof(double));
     kstate.alloc(2 * sizeof(dev::KState));
 }
