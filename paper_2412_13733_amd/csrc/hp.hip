@@ -9,7 +9,7 @@
 // direction (stiffness A_K = sum_k J (2/h_k)^2 A1 (x) M1 ..., coupling
 // B_K = J (x) B1, paper Sec. 3-4), and writes one value per local function;
 // a second pass sums those values into each global unknown in a fixed order
-// (deterministic, no atomics).  The psi side (Bᵀ u, D_psi, E(psi), the Schur
+// (deterministic, no atomics).  The psi side (B^T u, D_psi, E(psi), the Schur
 // blocks) is cell-local as in the uniform kernels.
 #include <hip/hip_runtime.h>
 
@@ -371,18 +371,12 @@ __global__ __launch_bounds__(1024) void k_hp_setup(HpGeo g, HpTabs<double> tb,
 // every row i (the inverse is symmetric: row j read as column j, coalesced),
 // and the group sums are added in LDS in a fixed order
 template <typename T>
-__global__ __launch_bounds__(256) void k_hp_prec_psi(HpGeo g, const T* __restrict__ sinv,
-                                                     const T* __restrict__ r,
-                                                     T* __restrict__ z,
-                                                     double* __restrict__ partial,
-                                                     const int* __restrict__ done) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[4];
-    __shared__ T acc_s[256];
-    if (done && *done) return;
-    T* rb = reinterpret_cast<T*>(smem_raw);
+__device__ inline void hp_prec_psi_body(int bid, int nblk, const HpGeo& g,
+                                        const T* __restrict__ sinv, const T* __restrict__ r,
+                                        T* __restrict__ z, double* __restrict__ partial, T* rb,
+                                        T* acc_s, double* red) {
     double part = 0.0;
-    for (int64_t b = blockIdx.x; b < g.n_cells; b += gridDim.x) {
+    for (int64_t b = bid; b < g.n_cells; b += nblk) {
         const int64_t cell = g.order[b];
         const int P = g.cell_p[cell] - 1;
         int n = 1;
@@ -423,8 +417,22 @@ __global__ __launch_bounds__(256) void k_hp_prec_psi(HpGeo g, const T* __restric
     }
     if (partial) {
         const double s = block_sum(part, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) partial[bid] = s;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hp_prec_psi(HpGeo g, const T* __restrict__ sinv,
+                                                     const T* __restrict__ r,
+                                                     T* __restrict__ z,
+                                                     double* __restrict__ partial,
+                                                     const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[4];
+    __shared__ T acc_s[256];
+    if (done && *done) return;
+    hp_prec_psi_body<T>(blockIdx.x, gridDim.x, g, sinv, r, z, partial,
+                        reinterpret_cast<T*>(smem_raw), acc_s, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,20 +460,18 @@ __global__ __launch_bounds__(256) void k_hp_vscatter(int64_t n, const int32_t* _
 // z_E = (1/alpha) Ainv_E r_E, one thread per unknown of a non-vertex entity
 // (ent_of[g]: its entity, -1 for vertices).  An entity's unknowns are
 // consecutive, so a wave reads consecutive columns of row j of the symmetric
-// inverse (coalesced) and broadcasts r_j.
+// inverse (coalesced) and broadcasts r_j.  Optionally the block's share of
+// <z, r> over those unknowns goes to partial[bid].
 template <typename T>
-__global__ __launch_bounds__(256) void k_hp_entity(int64_t n_u, const int32_t* __restrict__ ent_of,
-                                                   const int32_t* __restrict__ first,
-                                                   const int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ off,
-                                                   const T* __restrict__ inv,
-                                                   const double* __restrict__ prm,
-                                                   const T* __restrict__ r, T* __restrict__ z,
-                                                   const int* __restrict__ done) {
-    if (done && *done) return;
-    const T ia = (T)prm[2];
-    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < n_u;
-         gi += (int64_t)gridDim.x * blockDim.x) {
+__device__ inline void hp_entity_body(int64_t bid, int64_t nblk, int64_t n_u,
+                                      const int32_t* __restrict__ ent_of,
+                                      const int32_t* __restrict__ first,
+                                      const int32_t* __restrict__ cnt,
+                                      const int64_t* __restrict__ off, const T* __restrict__ inv,
+                                      T ia, const T* __restrict__ r, T* __restrict__ z,
+                                      double* __restrict__ partial, double* red) {
+    double part = 0.0;
+    for (int64_t gi = bid * blockDim.x + threadIdx.x; gi < n_u; gi += nblk * blockDim.x) {
         const int e = ent_of[gi];
         if (e < 0) continue;
         const int64_t f = first[e];
@@ -482,7 +488,85 @@ __global__ __launch_bounds__(256) void k_hp_entity(int64_t n_u, const int32_t* _
             a3 += A[(int64_t)(j + 3) * n] * rr[j + 3];
         }
         for (; j < n; ++j) a0 += A[(int64_t)j * n] * rr[j];
-        z[gi] = ia * ((a0 + a1) + (a2 + a3));
+        const T zv = ia * ((a0 + a1) + (a2 + a3));
+        z[gi] = zv;
+        part += (double)zv * (double)r[gi];
+    }
+    if (partial) {
+        const double s = block_sum(part, red);
+        if (threadIdx.x == 0) partial[bid] = s;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hp_entity(int64_t n_u, const int32_t* __restrict__ ent_of,
+                                                   const int32_t* __restrict__ first,
+                                                   const int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ off,
+                                                   const T* __restrict__ inv,
+                                                   const double* __restrict__ prm,
+                                                   const T* __restrict__ r, T* __restrict__ z,
+                                                   const int* __restrict__ done) {
+    __shared__ double red[4];
+    if (done && *done) return;
+    hp_entity_body<T>(blockIdx.x, gridDim.x, n_u, ent_of, first, cnt, off, inv, (T)prm[2], r, z,
+                      nullptr, red);
+}
+
+// The three independent parts of the block preconditioner in one grid:
+// blocks [0, np) the psi-block cells, [np, np + ne) the entity unknowns (with
+// their share of <z, r> in epart), the rest gathers the vertex residual.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hp_prec_fused(HpGeo g, const T* __restrict__ sinv,
+                                                       int np, int ne, const int32_t* ent_of,
+                                                       const int32_t* first, const int32_t* cnt,
+                                                       const int64_t* off, const T* inv,
+                                                       const double* __restrict__ prm,
+                                                       const int32_t* __restrict__ vidx,
+                                                       int64_t nv, T* __restrict__ cv,
+                                                       const T* __restrict__ r, T* __restrict__ z,
+                                                       double* __restrict__ ppart,
+                                                       double* __restrict__ epart,
+                                                       const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[4];
+    __shared__ T acc_s[256];
+    if (done && *done) return;
+    const int b = blockIdx.x;
+    if (b < np) {
+        hp_prec_psi_body<T>(b, np, g, sinv, r + g.n_u, z + g.n_u, ppart,
+                            reinterpret_cast<T*>(smem_raw), acc_s, red);
+    } else if (b < np + ne) {
+        hp_entity_body<T>(b - np, ne, g.n_u, ent_of, first, cnt, off, inv, (T)prm[2], r, z,
+                          epart, red);
+    } else {
+        const int64_t nb = gridDim.x - np - ne;
+        for (int64_t i = (int64_t)(b - np - ne) * blockDim.x + threadIdx.x; i < nv;
+             i += nb * blockDim.x)
+            cv[i] = r[vidx[i]];
+    }
+}
+
+// z at the vertices from the coarse solution, with their share of <z, r>
+template <typename T>
+__global__ __launch_bounds__(256) void k_hp_vscatter_dot(int64_t n, const int32_t* __restrict__ idx,
+                                                         const T* __restrict__ in,
+                                                         const T* __restrict__ r,
+                                                         T* __restrict__ z,
+                                                         double* __restrict__ partial,
+                                                         const int* __restrict__ done) {
+    __shared__ double red[4];
+    if (done && *done) return;
+    double part = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t gi = idx[i];
+        z[gi] = in[i];
+        part += (double)in[i] * (double)r[gi];
+    }
+    if (partial) {
+        const double s = block_sum(part, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
     }
 }
 
@@ -603,6 +687,28 @@ void launch_hp_entity(int64_t n_u, const int32_t* ent_of, const int32_t* first, 
                        ent_of, first, cnt, off, inv, prm, r, z, done);
 }
 
+int hp_prec_entity_blocks(int64_t n_u) { return (int)grid_of(n_u, 256, 2048); }
+int hp_vscatter_blocks(int64_t nv) { return (int)grid_of(nv, 256, 256); }
+
+template <typename T>
+void launch_hp_prec_fused(const HpGeo& g, const T* sinv, int np, int nmax, int ne,
+                          const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
+                          const int64_t* off, const T* inv, const double* prm, const int32_t* vidx,
+                          int64_t nv, T* cv, const T* r, T* z, double* ppart, double* epart,
+                          const int* done, hipStream_t s) {
+    const int nvb = nv > 0 ? (int)grid_of(nv, 256, 64) : 0;
+    hipLaunchKernelGGL((k_hp_prec_fused<T>), dim3(np + ne + nvb), dim3(256),
+                       (size_t)nmax * sizeof(T), s, g, sinv, np, ne, ent_of, first, cnt, off, inv,
+                       prm, vidx, nv, cv, r, z, ppart, epart, done);
+}
+
+template <typename T>
+void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T* r, T* z,
+                            double* partial, const int* done, hipStream_t s) {
+    hipLaunchKernelGGL((k_hp_vscatter_dot<T>), dim3(hp_vscatter_blocks(nv)), dim3(256), 0, s, nv,
+                       idx, in, r, z, partial, done);
+}
+
 #define HPG_INST(T)                                                                               \
     template void launch_hp_cell<T>(const HpGeo&, const HpTabs<T>&, T, T, const double*, const T*, \
                                     const T*, const T*, const T*, const double*, T*, T*, double*,  \
@@ -616,6 +722,13 @@ void launch_hp_entity(int64_t n_u, const int32_t* ent_of, const int32_t* first, 
                                        hipStream_t);                                               \
     template void launch_hp_vscatter<T>(int64_t, const int32_t*, const T*, T*, const int*,        \
                                         hipStream_t);                                              \
+    template void launch_hp_prec_fused<T>(const HpGeo&, const T*, int, int, int, const int32_t*,  \
+                                          const int32_t*, const int32_t*, const int64_t*,         \
+                                          const T*, const double*, const int32_t*, int64_t, T*,   \
+                                          const T*, T*, double*, double*, const int*,             \
+                                          hipStream_t);                                            \
+    template void launch_hp_vscatter_dot<T>(int64_t, const int32_t*, const T*, const T*, T*,     \
+                                            double*, const int*, hipStream_t);                     \
     template void launch_hp_entity<T>(int64_t, const int32_t*, const int32_t*, const int32_t*,    \
                                       const int64_t*, const T*, const double*, const T*, T*,      \
                                       const int*, hipStream_t);

@@ -266,6 +266,21 @@ void launch_hp_vgather(int64_t n, const int32_t* idx, const T* r, T* out, const 
 template <typename T>
 void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const int* done,
                         hipStream_t s);
+// The psi-block (np blocks, LDS nmax values), the entity blocks (ne blocks,
+// their <z, r> shares in epart[0..ne)) and the vertex gather (into cv) in one
+// launch; hp_prec_entity_blocks gives ne for n_u unknowns.  The vertex
+// scatter then adds its <z, r> shares (hp_vscatter_blocks(nv) of them).
+int hp_prec_entity_blocks(int64_t n_u);
+int hp_vscatter_blocks(int64_t nv);
+template <typename T>
+void launch_hp_prec_fused(const HpGeo& g, const T* sinv, int np, int nmax, int ne,
+                          const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
+                          const int64_t* off, const T* inv, const double* prm, const int32_t* vidx,
+                          int64_t nv, T* cv, const T* r, T* z, double* ppart, double* epart,
+                          const int* done, hipStream_t s);
+template <typename T>
+void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T* r, T* z,
+                            double* partial, const int* done, hipStream_t s);
 // (ent_of: entity of each u unknown, -1 for vertices; one thread per unknown)
 template <typename T>
 void launch_hp_entity(int64_t n_u, const int32_t* ent_of, const int32_t* first, const int32_t* cnt,

@@ -103,7 +103,9 @@ void Problem::build_hp() {
     np_cell = std::min(hgeo.n_items, 4096);   // one block per work item up to 4096
     np_u = np_gath;
     np_psi = np_cell;
-    np_dot = 512;
+    // <z_u, r_u>: the entity blocks' shares, then the vertex scatter's
+    np_dot = dev::hp_prec_entity_blocks(M.n_u) +
+             (H.vert.empty() ? 0 : dev::hp_vscatter_blocks((int64_t)H.vert.size()));
     np_prec = (int)std::min<int64_t>(M.n_cells, 4096);
     fdm_dot_fused = false;
     use_tile = false;
@@ -236,29 +238,37 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
     ensure_fdm_hp();
     const DevFdm<T>& F = cfdm_of(*this, r);
     const double* prm = params.as<double>();
-    // the psi-block on the side stream, concurrently with the A-block
-    const bool par = !timing && !single_stream;
-    hipStream_t s_psi = par ? side : s;
-    if (par) fork(s);
-    tstart("prec_psi", s_psi);
     const T* sinv = (dbl ? sinv64 : sinv32).template as<T>();
-    dev::launch_hp_prec_psi<T>(hgeo, sinv, r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr,
-                               np_prec, hp_nmax, dn, s_psi);
-    tstop("prec_psi", s_psi);
-    tstart("prec_u", s);
-    // edge / face / interior entities
-    if (!hph.ent_n.empty())
-        dev::launch_hp_entity<T>(M.n_u, hpd.ent_of.as<int32_t>(), hpd.ent_first.as<int32_t>(),
-                                 hpd.ent_n.as<int32_t>(), hpd.ent_off.as<int64_t>(),
-                                 (dbl ? hpd.inv64 : hpd.inv32).template as<T>(), prm, r, z, dn, s);
-    // vertices: (alpha A_VV)^{-1} by fast diagonalisation on the interior-vertex grid
+    const T* inv = (dbl ? hpd.inv64 : hpd.inv32).template as<T>();
     const int64_t nv = (int64_t)hph.vert.size();
+    const int ne = dev::hp_prec_entity_blocks(M.n_u);
+    T* cv = (dbl ? hpd.cv64 : hpd.cv32).template as<T>();
+    const int32_t* vidx = hpd.vert.as<int32_t>();
+    if (timing) {
+        // one launch per part, each bracketed by its timing group
+        tstart("prec_psi", s);
+        dev::launch_hp_prec_psi<T>(hgeo, sinv, r + M.n_u, z + M.n_u,
+                                   part ? part + np_dot : nullptr, np_prec, hp_nmax, dn, s);
+        tstop("prec_psi", s);
+        tstart("prec_u", s);
+        if (!hph.ent_n.empty())
+            dev::launch_hp_entity<T>(M.n_u, hpd.ent_of.as<int32_t>(), hpd.ent_first.as<int32_t>(),
+                                     hpd.ent_n.as<int32_t>(), hpd.ent_off.as<int64_t>(), inv, prm,
+                                     r, z, dn, s);
+        if (nv > 0) dev::launch_hp_vgather<T>(nv, vidx, r, cv, dn, s);
+    } else {
+        // psi-block, entity blocks (with their <z, r> shares) and the vertex
+        // gather in one launch
+        tstart("prec_u", s);
+        dev::launch_hp_prec_fused<T>(hgeo, sinv, np_prec, hp_nmax, ne, hpd.ent_of.as<int32_t>(),
+                                     hpd.ent_first.as<int32_t>(), hpd.ent_n.as<int32_t>(),
+                                     hpd.ent_off.as<int64_t>(), inv, prm, vidx, nv, cv, r, z,
+                                     part ? part + np_dot : nullptr, part, dn, s);
+    }
+    // vertices: (alpha A_VV)^{-1} by fast diagonalisation on the interior-vertex grid
     if (nv > 0) {
-        T* cv = (dbl ? hpd.cv64 : hpd.cv32).template as<T>();
         T* t1 = kw.t1.template as<T>();
         T* t2 = kw.t2.template as<T>();
-        const int32_t* vidx = hpd.vert.as<int32_t>();
-        dev::launch_hp_vgather<T>(nv, vidx, r, cv, dn, s);
         const int d = M.d;
         const int* n1 = hph.nv;
         const T* src = cv;
@@ -292,11 +302,13 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
                 }
                 src = dst;
             }
-        dev::launch_hp_vscatter<T>(nv, vidx, cv, z, dn, s);
+        if (timing)
+            dev::launch_hp_vscatter<T>(nv, vidx, cv, z, dn, s);
+        else
+            dev::launch_hp_vscatter_dot<T>(nv, vidx, cv, r, z, part ? part + ne : nullptr, dn, s);
     }
-    if (part) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
+    if (part && timing) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
     tstop("prec_u", s);
-    if (par) join(s);
 }
 
 template void Problem::apply_G_hp<double>(const double*, double*, double*, const int*, hipStream_t);
