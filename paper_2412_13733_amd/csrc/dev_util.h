@@ -336,6 +336,70 @@ __device__ inline void gauss_jordan_spd(double* Dm, int n, double* cr) {
     }
 }
 
+// The same elimination with the block held in registers: blockDim = 1024
+// threads as a 32 x 32 grid, thread (ty, tx) owning the 4 x 4 elements
+// (ty + 32 a, tx + 32 b), so n <= 128.  Per pass the owners publish the pivot
+// column and row to cr (LDS) and every thread updates its elements in
+// registers; the arithmetic per element is that of gauss_jordan_spd.  The
+// block is read from and written back to Dm.
+__device__ inline void gauss_jordan_spd_reg(double* Dm, int n, double* cr) {
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double v[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 32 * a, j = tx + 32 * b;
+            v[a][b] = (i < n && j < n) ? Dm[i * n + j] : 0.0;
+        }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const int kb = k >> 5, kr = k & 31;
+        if (tx == kr)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                double c = 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) c = (b == kb) ? v[a][b] : c;
+                const int i = ty + 32 * a;
+                if (i < n) cr[i] = c;
+            }
+        if (ty == kr)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                double c = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) c = (a == kb) ? v[a][b] : c;
+                const int j = tx + 32 * b;
+                if (j < n) cr[n + j] = c;
+            }
+        __syncthreads();
+        const double ip = 1.0 / cr[k];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = ty + 32 * a;
+            const double ci = i < n ? cr[i] : 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = tx + 32 * b;
+                if (i < n && j < n) {
+                    const double rk = (j == k ? 1.0 : cr[n + j]) * ip;
+                    v[a][b] = (i == k) ? rk : ((j == k ? 0.0 : v[a][b]) - ci * rk);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 32 * a, j = tx + 32 * b;
+            if (i < n && j < n) Dm[i * n + j] = v[a][b];
+        }
+    __syncthreads();
+}
+
 template <typename T, int D>
 __device__ inline T cell_jac(const Geo& g, const T* const* hw, int64_t cell, T* hk) {
     T J = 1;

@@ -343,7 +343,10 @@ __global__ __launch_bounds__(1024) void k_hp_setup(HpGeo g, HpTabs<double> tb,
         Dm[e] = v;
     }
     __syncthreads();
-    gauss_jordan_spd(Dm, n, cr);
+    if (LDSD && n <= 128)
+        gauss_jordan_spd_reg(Dm, n, cr);   // 1024 threads: the block in registers
+    else
+        gauss_jordan_spd(Dm, n, cr);
     const int64_t so = g.sinv_off[cell];
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int i = e / n, j = e % n;
