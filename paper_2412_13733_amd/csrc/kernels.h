@@ -132,9 +132,6 @@ void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, 
                       int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
                       int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s);
 template <typename T>
-void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
-                      const int* done, hipStream_t s);
-template <typename T>
 void launch_dot(int64_t n, const T* a, const T* b, double* partial, int nblocks, const int* done,
                 hipStream_t s);
 template <typename T>

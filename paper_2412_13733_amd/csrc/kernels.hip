@@ -758,28 +758,6 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
     }
 }
 
-// z *= 1 / (alpha (lam_0[i0] + lam_1[i1] + lam_2[i2]))  (eigen-space division)
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_fdm_scale(Geo g, const T* __restrict__ l0,
-                                                   const T* __restrict__ l1,
-                                                   const T* __restrict__ l2, T inv_alpha,
-                                                   T* __restrict__ z,
-                                                   const int* __restrict__ done) {
-    if (done && *done) return;
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= g.n_u) return;
-    int64_t t = I;
-    const int i0 = (int)(t % g.n1[0]);
-    t /= g.n1[0];
-    T lam = l0[i0];
-    if (D >= 2) {
-        lam += l1[(int)(t % g.n1[1])];
-        t /= g.n1[1];
-    }
-    if (D >= 3) lam += l2[(int)t];
-    z[I] *= inv_alpha / lam;
-}
-
 // ---------------------------------------------------------------------------
 // Preconditioned MINRES for the symmetric indefinite G with an SPD
 // preconditioner M (Lanczos on M^{-1} G in the M-inner product, QR of the
@@ -1128,21 +1106,6 @@ void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep,
 }
 
 template <typename T>
-void launch_fdm_scale(const Geo& g, const T* l0, const T* l1, const T* l2, T inv_alpha, T* z,
-                      const int* done, hipStream_t s) {
-    dim3 grid(nblk(g.n_u));
-    if (g.d == 1)
-        hipLaunchKernelGGL((k_fdm_scale<T, 1>), grid, dim3(256), 0, s, g, l0, l1, l2, inv_alpha,
-                           z, done);
-    else if (g.d == 2)
-        hipLaunchKernelGGL((k_fdm_scale<T, 2>), grid, dim3(256), 0, s, g, l0, l1, l2, inv_alpha,
-                           z, done);
-    else
-        hipLaunchKernelGGL((k_fdm_scale<T, 3>), grid, dim3(256), 0, s, g, l0, l1, l2, inv_alpha,
-                           z, done);
-}
-
-template <typename T>
 void launch_dot(int64_t n, const T* a, const T* b, double* partial, int nblocks, const int* done,
                 hipStream_t s) {
     hipLaunchKernelGGL((k_dot<T>), dim3(nblocks), dim3(256), 0, s, n, a, b, partial, done);
@@ -1210,8 +1173,6 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
     template void launch_gemm_prec<T>(int, int, int, const T*, int64_t, const T*, int64_t, T*,   \
                                       int64_t, const int*, const GemmEpi<T>&, int64_t, int, int,  \
                                       const T*, const T*, T*, double*, hipStream_t);             \
-    template void launch_fdm_scale<T>(const Geo&, const T*, const T*, const T*, T, T*,          \
-                                      const int*, hipStream_t);                                  \
     template void launch_kr_start<T>(int64_t, KState*, const double*, int, double, int, const T*, \
                                      const T*, T*, T*, T*, T*, T*, T*, hipStream_t);             \
     template void launch_kr_vhat<T>(int64_t, KState*, const double*, int, const T*, const T*,   \
