@@ -138,6 +138,25 @@ static std::vector<double> spd_inverse(int n, const std::vector<double>& A) {
     return X;
 }
 
+void hp_make_items(const Mesh& M, int lds_elems, int item_elems, HpHost& H) {
+    const int64_t N = M.n_cells;
+    H.item_start.clear();
+    H.item_count.clear();
+    H.item_p.clear();
+    for (int64_t i = 0; i < N;) {
+        const int p = M.deg[H.order[i]];
+        int S = 1;
+        for (int k = 0; k < M.d; ++k) S *= p + 1;
+        const int cap = std::max(1, std::min(lds_elems, item_elems) / S);
+        int64_t j = i;
+        while (j < N && M.deg[H.order[j]] == p && j - i < cap) ++j;
+        H.item_start.push_back((int32_t)i);
+        H.item_count.push_back((int32_t)(j - i));
+        H.item_p.push_back(p);
+        i = j;
+    }
+}
+
 void hp_build_host(const Mesh& M, int lds_elems, HpHost& H) {
     const int d = M.d;
     const int64_t N = M.n_cells;
@@ -185,26 +204,11 @@ void hp_build_host(const Mesh& M, int lds_elems, HpHost& H) {
         if (g >= 0) H.inc_idx[fill[g]++] = (int32_t)l;
     }
     // work items: cells sorted by degree (largest first), runs of equal degree
-    // of at most lds_elems / (p+1)^d cells (and at most 256 / (p+1)^d + 1)
     H.order.resize(N);
     for (int64_t c = 0; c < N; ++c) H.order[c] = (int32_t)c;
     std::stable_sort(H.order.begin(), H.order.end(),
                      [&](int32_t a, int32_t b) { return M.deg[a] > M.deg[b]; });
-    H.item_start.clear();
-    H.item_count.clear();
-    H.item_p.clear();
-    for (int64_t i = 0; i < N;) {
-        const int p = M.deg[H.order[i]];
-        int S = 1;
-        for (int k = 0; k < d; ++k) S *= p + 1;
-        const int cap = std::max(1, std::min(lds_elems / S, std::max(1, 256 / S)));
-        int64_t j = i;
-        while (j < N && M.deg[H.order[j]] == p && j - i < cap) ++j;
-        H.item_start.push_back((int32_t)i);
-        H.item_count.push_back((int32_t)(j - i));
-        H.item_p.push_back(p);
-        i = j;
-    }
+    hp_make_items(M, lds_elems, 256, H);
     // C_K = Bhat^T Ahat^{-1} Bhat per (degree, widths) class
     std::map<std::vector<double>, int> cls;
     H.cclass.assign(N, 0);

@@ -30,5 +30,8 @@ struct HpHost {
 
 // lds_elems: LDS elements per buffer of the cell kernels (bounds cells per item)
 void hp_build_host(const Mesh& M, int lds_elems, HpHost& H);
+// the work items over H.order: runs of equal-degree cells whose local
+// coefficients total at most min(lds_elems, item_elems) (at least one cell)
+void hp_make_items(const Mesh& M, int lds_elems, int item_elems, HpHost& H);
 
 }  // namespace hpg

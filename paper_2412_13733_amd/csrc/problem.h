@@ -133,7 +133,10 @@ struct Problem {
     bool hp_setup_in_lds = false;
     DevFdm<double> cfdm64;
     DevFdm<float> cfdm32;
+    int hp_smax = 1, hp_item_elems = 256;  // (p_max+1)^d; the tuned work-item budget
     void build_hp();
+    void set_hp_items(int item_elems);
+    void tune_hp_items();
     void ensure_fdm_hp();
     void set_data_hp(const double* f, const double* phi);
     template <typename T>

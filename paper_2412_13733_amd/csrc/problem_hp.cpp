@@ -6,6 +6,8 @@
 // uniform meshes.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "problem.h"
 
@@ -38,6 +40,7 @@ void Problem::build_hp() {
     hp_lds_elems = std::max(256, Smax);
     if ((size_t)6 * hp_lds_elems * sizeof(double) > lds_max)
         fail(HPG_ERR_INVALID_ARG, "(p+1)^d too large for the per-cell-degree kernels");
+    hp_smax = Smax;
     // Schur blocks formed in LDS when the largest one fits, else in place in HBM
     hp_setup_in_lds = dev::hp_setup_lds(M.d, M.p, true) <= lds_max;
     hp_setup_bytes = dev::hp_setup_lds(M.d, M.p, hp_setup_in_lds);
@@ -97,6 +100,7 @@ void Problem::build_hp() {
     hgeo.item_start = hpd.item_start.as<int32_t>();
     hgeo.item_count = hpd.item_count.as<int32_t>();
     hgeo.item_p = hpd.item_p.as<int32_t>();
+    tune_hp_items();
     // reduction layout: G apply = [gather blocks | cell blocks] (the u / psi
     // halves of the generic layout), preconditioner = [dot blocks | psi blocks]
     np_gath = (int)std::min<int64_t>((M.n_u + 255) / 256, 1024);
@@ -114,6 +118,81 @@ void Problem::build_hp() {
     partial_g.alloc((size_t)np_cap * sizeof(double));
     params.alloc(4 * sizeof(double));
     kstate.alloc(2 * sizeof(dev::KState));
+}
+
+// Work items of the cell pass (a project-side autotuner): the cell pass is
+// timed, as an FP32 G apply on zero data, with items of at most 256, 512 and
+// 1024 local functions (more cells per item amortise its barriers, fewer
+// give more blocks), and the fastest is kept.  HPG_HP_ITEM_ELEMS fixes it.
+void Problem::set_hp_items(int item_elems) {
+    const int lds = std::max(item_elems, hp_smax);
+    hp_make_items(M, lds, item_elems, hph);
+    upload(hpd.item_start, hph.item_start);
+    upload(hpd.item_count, hph.item_count);
+    upload(hpd.item_p, hph.item_p);
+    hp_lds_elems = lds;
+    hgeo.n_items = (int)hph.item_p.size();
+    hgeo.lds_elems = lds;
+    hgeo.item_start = hpd.item_start.as<int32_t>();
+    hgeo.item_count = hpd.item_count.as<int32_t>();
+    hgeo.item_p = hpd.item_p.as<int32_t>();
+    hp_item_elems = item_elems;
+}
+
+void Problem::tune_hp_items() {
+    std::vector<int> cands;
+    if (const char* e = std::getenv("HPG_HP_ITEM_ELEMS")) {
+        cands.push_back(std::max(1, std::atoi(e)));
+    } else {
+        for (int c : {256, 512, 1024})
+            if ((size_t)6 * std::max(c, hp_smax) * sizeof(double) <= lds_max) cands.push_back(c);
+    }
+    if (cands.size() == 1) {
+        set_hp_items(cands[0]);
+        return;
+    }
+    const int64_t n = M.n_u + M.n_psi, nloc = hph.loc_off.back();
+    DBuf x, y, om, yl;
+    x.alloc(n * sizeof(float));
+    y.alloc(n * sizeof(float));
+    om.alloc(M.n_qp * sizeof(float));
+    yl.alloc(nloc * sizeof(float));
+    HPG_HIP(hipMemset(x.p, 0, x.bytes));
+    HPG_HIP(hipMemset(om.p, 0, om.bytes));
+    hipEvent_t e0, e1;
+    HPG_HIP(hipEventCreate(&e0));
+    HPG_HIP(hipEventCreate(&e1));
+    const hipStream_t s = own_stream;
+    float best = 1e30f;
+    int best_c = cands[0];
+    for (int c : cands) {
+        set_hp_items(c);
+        auto run = [&]() {
+            dev::launch_hp_cell<float>(hgeo, hp_tabs<float>(), 1.0f, 0.0f, nullptr, x.as<float>(),
+                                       x.as<float>() + M.n_u, nullptr, om.as<float>(), nullptr,
+                                       yl.as<float>(), y.as<float>() + M.n_u, nullptr,
+                                       std::min(hgeo.n_items, 4096), nullptr, dev::MODE_APPLY, s);
+        };
+        run();
+        run();
+        HPG_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r) run();
+        HPG_HIP(hipEventRecord(e1, s));
+        HPG_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HPG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (std::getenv("HPG_TRACE"))
+            std::fprintf(stderr, "[hpg] cell pass with work items of <= %d local functions: "
+                                 "%d items, %.1f us\n", c, hgeo.n_items, 1e3 * ms / 5);
+        if (ms < best) {
+            best = ms;
+            best_c = c;
+        }
+    }
+    HPG_HIP(hipEventDestroy(e0));
+    HPG_HIP(hipEventDestroy(e1));
+    HPG_HIP(hipGetLastError());
+    if (best_c != hp_item_elems) set_hp_items(best_c);
 }
 
 // Q1 stiffness / mass of the interior vertices of direction k (tridiagonal):
