@@ -268,8 +268,10 @@ def request_opts(hpg, r, precision):
     """Obstacle requests: alpha_k = 2^k to the 1e-10 proximal tolerance.
     Gradient requests: the paper's schedule for that problem class,
     alpha_1 = 2^-7, alpha_{k+1} = min(sqrt(2) alpha_k, 4), 20 steps.  A Newton
-    stall is accepted at error 1e-8 (the serving accuracy target)."""
-    kw = dict(stall_tol=1e-8)
+    stall is accepted at error 1e-8 (the serving accuracy target); up to 100
+    Newton steps per subproblem (high-degree requests need ~35 damped steps
+    before the quadratic phase)."""
+    kw = dict(stall_tol=1e-8, max_newton=100)
     if r["kind"] == "gradient":
         kw.update(alpha0=2.0 ** -7, alpha_factor=2.0 ** 0.5, alpha_max=4.0, fixed_prox_steps=20)
     if precision == hpg.MIXED:
