@@ -153,8 +153,10 @@ typedef struct hpg_solve_stats {
     double newton_error;    /* last Newton error of the last subproblem */
     double seconds;         /* wall time of the solve */
     double alpha_last;
-    int32_t fp64_fallbacks; /* HPG_MIXED: Newton steps whose FP32 Krylov direction the line
-                               search rejected and that were recomputed with the FP64 operator */
+    int32_t fp64_fallbacks; /* HPG_MIXED: Newton directions computed with the FP64 operator:
+                               those whose FP32 Krylov solve broke down, hit its cap or was
+                               rejected by the line search, and, after three of those within
+                               one proximal step, the rest of that step's directions */
 } hpg_solve_stats;
 
 /* Solve; u_out[n_u], psi_out[n_psi] (psi may be NULL), lam_out[n_psi]

@@ -1243,6 +1243,10 @@ double Problem::l2_diff(const double* a, const double* b, double* norm_a, hipStr
 // FP64 path's default): a direction accurate only to the FP32 tolerance does
 // not reduce the merit function near the Newton tolerance
 constexpr double kFallbackKrylovRtol = 1e-10;
+// after this many FP64 recomputations within one proximal step, a mixed solve
+// computes the remaining Newton directions of that step in FP64 directly (a
+// subproblem whose FP32 solves keep breaking down would pay for both)
+constexpr int kMaxFallbacksPerStep = 3;
 
 // Newton direction with the FP64 operator: b = -R, MINRES into xk64, delta = xk64
 int Problem::newton_direction64(const double* dR, double* dd, double eta, const hpg_solve_opts& o,
@@ -1298,6 +1302,7 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
         HPG_HIP(hipMemcpyAsync(u_old.p, du, M.n_u * sizeof(double), hipMemcpyDeviceToDevice, s));
         // ---- Newton on the subproblem with (alpha_k, psi_prev)
         bool conv = false;
+        int fb_step = 0;   // FP64 recomputations in this proximal step (mixed)
         for (int it = 0; it <= o.max_newton; ++it) {
             double nu2, np2;
             residual(du, dp, dpp, alpha_k, dR, s, &nu2, &np2);
@@ -1309,7 +1314,8 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                 break;
             }
             if (it == o.max_newton) break;
-            setup(dp, alpha_k, o.beta, mixed ? HPG_MIXED : HPG_FP64, s);
+            const bool use32 = mixed && fb_step < kMaxFallbacksPerStep;
+            setup(dp, alpha_k, o.beta, use32 ? HPG_MIXED : HPG_FP64, s);
             // inexact Newton (optional): a linear-solve tolerance proportional
             // to the current error.  MINRES measures the residual in the
             // preconditioner's norm, which is much looser than the Newton
@@ -1319,13 +1325,16 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                                    : o.krylov_rtol;
             int its;
             bool need64 = false;   // FP32 Krylov solve broke down or hit its cap
-            if (mixed) {
+            if (use32) {
                 float* b32 = rhs32.as<float>();
                 float* x32 = delta32.as<float>();
                 dev::launch_convert<double, float>(n, dR, b32, -1.0, s);
                 its = minres<float>(b32, x32, eta, o.max_krylov, o.krylov_chunk, s);
                 dev::launch_convert<float, double>(n, x32, dd, 1.0, s);
                 need64 = last_minres_breakdown || its >= o.max_krylov;
+            } else if (mixed) {
+                its = newton_direction64(dR, dd, std::min(eta, kFallbackKrylovRtol), o, s);
+                S.fp64_fallbacks += 1;
             } else {
                 its = newton_direction64(dR, dd, eta, o, s);
             }
@@ -1336,13 +1345,14 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
             const double m0 = std::sqrt(nu2 / (alpha_k * alpha_k) + np2);
             double t = 1.0;
             bool acc = false;
-            for (int attempt = need64 ? 1 : 0; attempt < (mixed ? 2 : 1) && !acc; ++attempt) {
+            for (int attempt = need64 ? 1 : 0; attempt < (use32 ? 2 : 1) && !acc; ++attempt) {
                 if (attempt == 1) {
                     residual(du, dp, dpp, alpha_k, dR, s, &nu2, &np2);
                     setup(dp, alpha_k, o.beta, HPG_FP64, s);
                     its = newton_direction64(dR, dd, std::min(eta, kFallbackKrylovRtol), o, s);
                     S.krylov_iters += its;
                     S.fp64_fallbacks += 1;   // the next Newton step sets up FP32 again
+                    ++fb_step;
                 }
                 t = 1.0;
                 for (int hv = 0; hv <= 30; ++hv) {
