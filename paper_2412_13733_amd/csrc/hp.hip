@@ -47,6 +47,28 @@ __device__ inline T hp_jac(const HpGeo& g, const HpTabs<T>& tb, int64_t cell, T*
     return J;
 }
 
+// LDS layout of the 2-D cell pass: per-cell offsets (int64), then the
+// buffers of lds_elems elements, the 1-D tables of the largest degree and the
+// per-cell factors
+struct HpCell2Lds {
+    int cmax, nbuf, l2;
+    size_t off_t, bytes;
+};
+__host__ __device__ inline HpCell2Lds hp_cell2_layout(int lds_elems, int lmax, int ts, int mode) {
+    HpCell2Lds o;
+    o.cmax = lds_elems / 9 + 1;   // (p + 1)^2 >= 9 local functions per cell
+    o.nbuf = mode == MODE_RES ? 9 : 8;
+    o.l2 = lmax * lmax;
+    o.off_t = (size_t)3 * o.cmax * sizeof(int64_t);
+    o.bytes = o.off_t + (size_t)ts * ((size_t)o.nbuf * lds_elems + 4 * o.l2 + 2 * lmax + 3 * o.cmax);
+    return o;
+}
+
+size_t hp_cell_lds(int d, int lds_elems, int lmax, size_t tsize, int mode) {
+    if (d == 2) return hp_cell2_layout(lds_elems, lmax, (int)tsize, mode).bytes;
+    return (size_t)6 * lds_elems * tsize;
+}
+
 // ---------------------------------------------------------------------------
 template <typename T, int D, int MODE>
 __global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha, T beta,
@@ -186,6 +208,222 @@ __global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha,
                 const T y = bT[ci * S + a] - dx[ci * S + a] - beta * md * bX[ci * S + a];
                 ypsi[o] = y;
                 part += (double)y * (double)bX[ci * S + a];
+            }
+        }
+        __syncthreads();   // the LDS buffers are reused by the next item
+    }
+    if (partial) {
+        const double s = block_sum(part, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same cell pass in 2-D with the contractions grouped by axis: every
+// quantity is contracted along direction 1 first, all of them in one step
+// from one read of the input column (x_K: M1, A1, B1^T; x_psi: B1, Vpsi),
+// then along direction 0 (A_K x_K and B_K x_psi go straight to y_loc), so an
+// item takes five barriers.  The 1-D tables of the item's degree and the
+// per-cell factors and offsets are staged in LDS; index arithmetic uses a
+// float reciprocal with an exact integer correction.
+
+// floor(n / d) for 0 <= n < 2^22, 1 <= d, rd = 1 / d
+__device__ inline int hp_div(int n, int d, float rd) {
+    int q = (int)((float)n * rd);
+    const int r = n - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_hp_cell2(HpGeo g, HpTabs<T> tb, T alpha, T beta,
+                                                  const double* __restrict__ prm,
+                                                  const T* __restrict__ xu,
+                                                  const T* __restrict__ xpsi,
+                                                  const T* __restrict__ xpsi_prev,
+                                                  const T* __restrict__ omega,
+                                                  const double* __restrict__ Phi,
+                                                  T* __restrict__ yloc, T* __restrict__ ypsi,
+                                                  double* __restrict__ partial,
+                                                  const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[4];
+    if (done && *done) return;
+    if (prm) {
+        alpha = (T)prm[0];
+        beta = (T)prm[1];
+    }
+    const HpCell2Lds lay = hp_cell2_layout(g.lds_elems, g.lmax, (int)sizeof(T), MODE);
+    int64_t* cLo = reinterpret_cast<int64_t*>(smem_raw);   // per cell: local, psi, qp offsets
+    int64_t* cPo = cLo + lay.cmax;
+    int64_t* cQo = cPo + lay.cmax;
+    T* const base = reinterpret_cast<T*>(smem_raw + lay.off_t);
+    const int SB = g.lds_elems;
+    T* bU = base;             // x_K; later the weighted values at the Gauss points
+    T* bX = base + SB;        // x_psi (RES: psi - psi_prev)
+    T* tM = base + 2 * SB;    // M1 along direction 1 of x_K; later Vpsi^T along 1
+    T* tA = base + 3 * SB;    // A1 along direction 1 of x_K
+    T* tBt = base + 4 * SB;   // B1^T along direction 1 of x_K
+    T* tB = base + 5 * SB;    // B1 along direction 1 of x_psi
+    T* tV = base + 6 * SB;    // Vpsi along direction 1 of x_psi (RES: of psi)
+    T* bT = base + 7 * SB;    // J B_K^T x_K
+    T* bP = MODE == MODE_RES ? base + 8 * SB : bX;   // psi (RES)
+    T* sA1 = base + lay.nbuf * SB;
+    T* sM1 = sA1 + lay.l2;
+    T* sB1 = sM1 + lay.l2;
+    T* sV = sB1 + lay.l2;
+    T* sMd = sV + lay.l2;
+    T* sw = sMd + g.lmax;
+    T* cJ = sw + g.lmax;
+    T* cC0 = cJ + lay.cmax;
+    T* cC1 = cC0 + lay.cmax;
+    double part = 0.0;
+    for (int it = blockIdx.x; it < g.n_items; it += gridDim.x) {
+        const int p = g.item_p[it], L = p + 1, P = p - 1;
+        const int S = L * L, LP = L * P, PP = P * P;
+        const float rS = 1.0f / (float)S, rL = 1.0f / (float)L, rP = 1.0f / (float)P;
+        const float rLP = 1.0f / (float)LP, rPP = 1.0f / (float)PP;
+        const int start = g.item_start[it], ncell = g.item_count[it];
+        const HpCellTabs<T> t = hp_tabs(tb, p);
+        for (int e = threadIdx.x; e < S; e += blockDim.x) {
+            sA1[e] = t.A1[e];
+            sM1[e] = t.M1[e];
+        }
+        for (int e = threadIdx.x; e < LP; e += blockDim.x) {
+            sB1[e] = t.B1[e];
+            sV[e] = t.Vpsi[e];
+        }
+        for (int e = threadIdx.x; e < L; e += blockDim.x) {
+            if (e < P) sMd[e] = t.Mdiag[e];
+            sw[e] = t.w[e];
+        }
+        for (int ci = threadIdx.x; ci < ncell; ci += blockDim.x) {
+            const int64_t cell = g.order[start + ci];
+            T hk[3];
+            const T J = hp_jac<T, 2>(g, tb, cell, hk);
+            cJ[ci] = J;
+            cC0[ci] = J * ((T)2 / hk[0]) * ((T)2 / hk[0]);
+            cC1[ci] = J * ((T)2 / hk[1]) * ((T)2 / hk[1]);
+            cLo[ci] = g.loc_off[cell];
+            cPo[ci] = g.psi_off[cell];
+            cQo[ci] = g.qp_off[cell];
+        }
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = hp_div(e, S, rS);
+            const int64_t cell = g.order[start + ci];
+            const int gi = g.loc2glob[g.loc_off[cell] + (e - ci * S)];
+            bU[e] = gi >= 0 ? xu[gi] : (T)0;
+        }
+        for (int e = threadIdx.x; e < ncell * PP; e += blockDim.x) {
+            const int ci = hp_div(e, PP, rPP), a = e - ci * PP;
+            const int64_t o = g.psi_off[g.order[start + ci]] + a;
+            if (MODE == MODE_RES) {
+                bX[ci * S + a] = xpsi[o] - xpsi_prev[o];
+                bP[ci * S + a] = xpsi[o];
+            } else {
+                bX[ci * S + a] = xpsi[o];
+            }
+        }
+        __syncthreads();
+        // ---- direction 1: x_K columns -> M1, A1 (L rows), B1^T (P rows)
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = hp_div(e, S, rS), r = e - ci * S;
+            const int i1 = hp_div(r, L, rL), j0 = r - i1 * L;
+            const T* col = bU + ci * S + j0;
+            T am = 0, aa = 0, ab = 0;
+            for (int j1 = 0; j1 < L; ++j1) {
+                const T xv = col[j1 * L];
+                am += sM1[i1 * L + j1] * xv;
+                aa += sA1[i1 * L + j1] * xv;
+                if (i1 < P) ab += sB1[j1 * P + i1] * xv;
+            }
+            tM[e] = am;
+            tA[e] = aa;
+            if (i1 < P) tBt[ci * S + j0 + L * i1] = ab;
+        }
+        // x_psi columns -> B1 (L rows), Vpsi (q = L rows)
+        for (int e = threadIdx.x; e < ncell * LP; e += blockDim.x) {
+            const int ci = hp_div(e, LP, rLP), r = e - ci * LP;
+            const int i1 = hp_div(r, P, rP), a0 = r - i1 * P;
+            const T* colx = bX + ci * S + a0;
+            const T* colp = bP + ci * S + a0;
+            T sb = 0, sv = 0;
+            for (int a1 = 0; a1 < P; ++a1) {
+                sb += sB1[i1 * P + a1] * colx[a1 * P];
+                sv += sV[i1 * P + a1] * colp[a1 * P];
+            }
+            tB[ci * S + r] = sb;
+            tV[ci * S + r] = sv;
+        }
+        __syncthreads();
+        // ---- direction 0: y_loc = alpha (c0 A1 (x) M1 + c1 M1 (x) A1) x_K + J B1 (x) B1 x_psi
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = hp_div(e, S, rS), r = e - ci * S;
+            const int i1 = hp_div(r, L, rL), i0 = r - i1 * L;
+            const T* rm = tM + ci * S + L * i1;
+            const T* ra = tA + ci * S + L * i1;
+            const T* rb = tB + ci * S + P * i1;
+            T s0 = 0, s1 = 0, sb = 0;
+            for (int j0 = 0; j0 < L; ++j0) {
+                s0 += sA1[i0 * L + j0] * rm[j0];
+                s1 += sM1[i0 * L + j0] * ra[j0];
+            }
+            for (int a0 = 0; a0 < P; ++a0) sb += sB1[i0 * P + a0] * rb[a0];
+            yloc[cLo[ci] + r] = alpha * (cC0[ci] * s0 + cC1[ci] * s1) + cJ[ci] * sb;
+        }
+        // J B1^T (x) B1^T x_K
+        for (int e = threadIdx.x; e < ncell * PP; e += blockDim.x) {
+            const int ci = hp_div(e, PP, rPP), r = e - ci * PP;
+            const int a1 = hp_div(r, P, rP), a0 = r - a1 * P;
+            const T* rb = tBt + ci * S + L * a1;
+            T sb = 0;
+            for (int j0 = 0; j0 < L; ++j0) sb += sB1[j0 * P + a0] * rb[j0];
+            bT[ci * S + r] = cJ[ci] * sb;
+        }
+        // psi_h at the Gauss points (q = L per direction), times the weights
+        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
+            const int ci = hp_div(e, S, rS), r = e - ci * S;
+            const int j1 = hp_div(r, L, rL), j0 = r - j1 * L;
+            const T* rv = tV + ci * S + P * j1;
+            T v = 0;
+            for (int a0 = 0; a0 < P; ++a0) v += sV[j0 * P + a0] * rv[a0];
+            if (MODE == MODE_RES) {
+                const T wq = cJ[ci] * sw[j0] * sw[j1];
+                const double arg = -(double)v;
+                bU[e] = (T)((double)wq * exp(arg < 700.0 ? arg : 700.0));
+            } else {
+                bU[e] = omega[cQo[ci] + r] * v;
+            }
+        }
+        __syncthreads();
+        // ---- back to the Legendre modes: Vpsi^T along direction 1 ...
+        for (int e = threadIdx.x; e < ncell * LP; e += blockDim.x) {
+            const int ci = hp_div(e, LP, rLP), r = e - ci * LP;
+            const int a1 = hp_div(r, L, rL), j0 = r - a1 * L;
+            const T* col = bU + ci * S + j0;
+            T sv = 0;
+            for (int j1 = 0; j1 < L; ++j1) sv += sV[j1 * P + a1] * col[j1 * L];
+            tM[ci * S + r] = sv;
+        }
+        __syncthreads();
+        // ... and along direction 0; y_psi
+        for (int e = threadIdx.x; e < ncell * PP; e += blockDim.x) {
+            const int ci = hp_div(e, PP, rPP), r = e - ci * PP;
+            const int a1 = hp_div(r, P, rP), a0 = r - a1 * P;
+            const T* rw = tM + ci * S + L * a1;
+            T dx = 0;
+            for (int j0 = 0; j0 < L; ++j0) dx += sV[j0 * P + a0] * rw[j0];
+            const int64_t o = cPo[ci] + r;
+            if (MODE == MODE_RES) {
+                const double res = (double)bT[ci * S + r] + (double)dx - Phi[o];
+                ypsi[o] = (T)res;
+                part += res * res;
+            } else {
+                const T xp = bX[ci * S + r];
+                const T md = cJ[ci] * sMd[a0] * sMd[a1];
+                const T y = bT[ci * S + r] - dx - beta * md * xp;
+                ypsi[o] = y;
+                part += (double)y * (double)xp;
             }
         }
         __syncthreads();   // the LDS buffers are reused by the next item
@@ -584,17 +822,26 @@ void launch_hp_cell(const HpGeo& g, const HpTabs<T>& tb, T alpha, T beta, const 
                     const double* Phi, T* yloc, T* ypsi, double* partial, int nblocks,
                     const int* done, int mode, hipStream_t s) {
     const unsigned grid = (unsigned)std::max(1, std::min(g.n_items, nblocks));
-    const size_t shm = (size_t)6 * g.lds_elems * sizeof(T);
+    const size_t shm = hp_cell_lds(g.d, g.lds_elems, g.lmax, sizeof(T), mode);
+    if (g.d == 2) {
+        if (mode == MODE_RES)
+            hipLaunchKernelGGL((k_hp_cell2<T, MODE_RES>), dim3(grid), dim3(256), shm, s, g, tb,
+                               alpha, beta, prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi,
+                               partial, done);
+        else
+            hipLaunchKernelGGL((k_hp_cell2<T, MODE_APPLY>), dim3(grid), dim3(256), shm, s, g, tb,
+                               alpha, beta, prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi,
+                               partial, done);
+        return;
+    }
 #define HPG_HC(DD, MM)                                                                          \
     hipLaunchKernelGGL((k_hp_cell<T, DD, MM>), dim3(grid), dim3(256), shm, s, g, tb, alpha, beta, \
                        prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi, partial, done)
     if (mode == MODE_RES) {
         if (g.d == 1) HPG_HC(1, MODE_RES);
-        else if (g.d == 2) HPG_HC(2, MODE_RES);
         else HPG_HC(3, MODE_RES);
     } else {
         if (g.d == 1) HPG_HC(1, MODE_APPLY);
-        else if (g.d == 2) HPG_HC(2, MODE_APPLY);
         else HPG_HC(3, MODE_APPLY);
     }
 #undef HPG_HC

@@ -210,6 +210,7 @@ struct HpGeo {
     int m[3];
     int64_t n_cells, n_u, n_psi;
     int n_items, lds_elems;   // lds_elems: per-buffer LDS elements of the cell kernels
+    int lmax;                 // largest p + 1
     const int32_t* cell_p;
     const int64_t* loc_off;   // prefix sums of (p_K+1)^d
     const int64_t* psi_off;   // prefix sums of P_K^d
@@ -227,6 +228,8 @@ constexpr int MODE_L2 = 2;
 // residual (MODE_RES: x_psi = psi, xpsi_prev = psi_{k-1}; y_loc = alpha A_K u_K
 // + B_K (psi - psi_prev), y_psi = B_K^T u_K + E_K(psi) - Phi_K, partial
 // |y_psi|^2).  y_loc is per local function, summed into y_u by launch_hp_gather.
+// LDS bytes of the cell pass (element size tsize, MODE_APPLY or MODE_RES)
+size_t hp_cell_lds(int d, int lds_elems, int lmax, size_t tsize, int mode);
 template <typename T>
 void launch_hp_cell(const HpGeo& g, const HpTabs<T>& tb, T alpha, T beta, const double* prm,
                     const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,

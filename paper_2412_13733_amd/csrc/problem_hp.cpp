@@ -38,7 +38,7 @@ void Problem::build_hp() {
         nmax *= M.p - 1;
     }
     hp_lds_elems = std::max(256, Smax);
-    if ((size_t)6 * hp_lds_elems * sizeof(double) > lds_max)
+    if (dev::hp_cell_lds(M.d, hp_lds_elems, M.p + 1, sizeof(double), dev::MODE_RES) > lds_max)
         fail(HPG_ERR_INVALID_ARG, "(p+1)^d too large for the per-cell-degree kernels");
     hp_smax = Smax;
     // Schur blocks formed in LDS when the largest one fits, else in place in HBM
@@ -90,6 +90,7 @@ void Problem::build_hp() {
     hgeo.n_psi = M.n_psi;
     hgeo.n_items = (int)H.item_p.size();
     hgeo.lds_elems = hp_lds_elems;
+    hgeo.lmax = M.p + 1;
     hgeo.cell_p = hpd.cell_p.as<int32_t>();
     hgeo.loc_off = hpd.loc_off.as<int64_t>();
     hgeo.psi_off = hpd.psi_off.as<int64_t>();
@@ -145,7 +146,9 @@ void Problem::tune_hp_items() {
         cands.push_back(std::max(1, std::atoi(e)));
     } else {
         for (int c : {256, 512, 1024})
-            if ((size_t)6 * std::max(c, hp_smax) * sizeof(double) <= lds_max) cands.push_back(c);
+            if (dev::hp_cell_lds(M.d, std::max(c, hp_smax), M.p + 1, sizeof(double),
+                                 dev::MODE_RES) <= lds_max)
+                cands.push_back(c);
     }
     if (cands.size() == 1) {
         set_hp_items(cands[0]);
