@@ -339,9 +339,11 @@ __device__ inline void gauss_jordan_spd(double* Dm, int n, double* cr) {
 // The same elimination with the block held in registers: blockDim = 1024
 // threads as a 32 x 32 grid, thread (ty, tx) owning the 4 x 4 elements
 // (ty + 32 a, tx + 32 b), so n <= 128.  Per pass the owners publish the pivot
-// column and row to cr (LDS) and every thread updates its elements in
-// registers; the arithmetic per element is that of gauss_jordan_spd.  The
-// block is read from and written back to Dm.
+// column (cr[0, 128)) and row (cr[128, 256)) to LDS and every thread updates
+// its elements in registers; the arithmetic per element is that of
+// gauss_jordan_spd.  Elements beyond n are zero and stay zero (their pivot
+// column and row entries are zero), so the update runs without bounds tests.
+// cr: 256 doubles.  The block is read from and written back to Dm.
 __device__ inline void gauss_jordan_spd_reg(double* Dm, int n, double* cr) {
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     double v[4][4];
@@ -354,39 +356,51 @@ __device__ inline void gauss_jordan_spd_reg(double* Dm, int n, double* cr) {
         }
     __syncthreads();
     for (int k = 0; k < n; ++k) {
+        // k lies in register column / row kb (uniform) of the owners tx = kr / ty = kr
         const int kb = k >> 5, kr = k & 31;
-        if (tx == kr)
+        if (tx == kr) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                double c = 0.0;
+            for (int b = 0; b < 4; ++b)
+                if (b == kb)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) c = (b == kb) ? v[a][b] : c;
-                const int i = ty + 32 * a;
-                if (i < n) cr[i] = c;
-            }
-        if (ty == kr)
+                    for (int a = 0; a < 4; ++a) cr[ty + 32 * a] = v[a][b];
+        }
+        if (ty == kr) {
+            // the row's own pivot entry is published as 1, so rk = cr[128 + j] / pivot
+            // needs no case for j = k
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                double c = 0.0;
+            for (int a = 0; a < 4; ++a)
+                if (a == kb)
 #pragma unroll
-                for (int a = 0; a < 4; ++a) c = (a == kb) ? v[a][b] : c;
-                const int j = tx + 32 * b;
-                if (j < n) cr[n + j] = c;
-            }
+                    for (int b = 0; b < 4; ++b)
+                        cr[128 + tx + 32 * b] = (tx == kr && b == kb) ? 1.0 : v[a][b];
+        }
         __syncthreads();
         const double ip = 1.0 / cr[k];
+        double rk[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) rk[b] = cr[128 + tx + 32 * b] * ip;
+        // column k restarts from zero (its new value is -c_i rk_k) ...
+        if (tx == kr) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b == kb)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) v[a][b] = 0.0;
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int i = ty + 32 * a;
-            const double ci = i < n ? cr[i] : 0.0;
+            const double ci = cr[ty + 32 * a];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int j = tx + 32 * b;
-                if (i < n && j < n) {
-                    const double rk = (j == k ? 1.0 : cr[n + j]) * ip;
-                    v[a][b] = (i == k) ? rk : ((j == k ? 0.0 : v[a][b]) - ci * rk);
-                }
-            }
+            for (int b = 0; b < 4; ++b) v[a][b] -= ci * rk[b];
+        }
+        // ... and row k becomes rk
+        if (ty == kr) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (a == kb)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) v[a][b] = rk[b];
         }
         __syncthreads();
     }

@@ -529,10 +529,10 @@ __global__ __launch_bounds__(1024) void k_hp_setup(HpGeo g, HpTabs<double> tb,
                                                   double* __restrict__ om64,
                                                   float* __restrict__ om32,
                                                   double* __restrict__ s64,
-                                                  float* __restrict__ s32) {
+                                                  float* __restrict__ s32, int o0) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
-    const int64_t cell = blockIdx.x;
+    const int64_t cell = g.order[o0 + (int)blockIdx.x];
     const int p = g.cell_p[cell], P = p - 1, q = p + 1;
     int n = 1, S = 1;
     for (int k = 0; k < D; ++k) {
@@ -546,7 +546,8 @@ __global__ __launch_bounds__(1024) void k_hp_setup(HpGeo g, HpTabs<double> tb,
     double* cr = T1 + sT1;
     const HpCellTabs<double> t = hp_tabs(tb, p);
     const int64_t po = g.psi_off[cell], qo = g.qp_off[cell];
-    double* Dm = LDSD ? cr + 2 * n : s64 + g.sinv_off[cell];
+    // cr: the pivot column and row (2n; 256 for the register elimination)
+    double* Dm = LDSD ? cr + (2 * n > 256 ? 2 * n : 256) : s64 + g.sinv_off[cell];
     for (int a = threadIdx.x; a < n; a += blockDim.x) bA[a] = psi[po + a];
     __syncthreads();
     double* vq = contract_all<double, D>(bA, bB, S, 1, P, q, t.Vpsi, P, false);
@@ -872,29 +873,32 @@ void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, con
         hipLaunchKernelGGL((k_hp_l2<3>), dim3(grid), dim3(256), shm, s, g, tb, a, b, partial);
 }
 
+size_t hp_setup_lds_p(int d, int p, bool block_in_lds) {
+    const size_t P = p - 1, q = p + 1;
+    size_t n = 1, S = 1;
+    for (int k = 0; k < d; ++k) {
+        n *= P;
+        S *= q;
+    }
+    const size_t sT1 = d == 1 ? 1 : (d == 2 ? q * P * P : q * q * P * P);
+    return (2 * S + sT1 + std::max<size_t>(2 * n, 256) + (block_in_lds ? n * n : 0)) *
+           sizeof(double);
+}
+
 size_t hp_setup_lds(int d, int pmax, bool block_in_lds) {
     size_t best = 0;
-    for (int p = 2; p <= pmax; ++p) {
-        const size_t P = p - 1, q = p + 1;
-        size_t n = 1, S = 1;
-        for (int k = 0; k < d; ++k) {
-            n *= P;
-            S *= q;
-        }
-        const size_t sT1 = d == 1 ? 1 : (d == 2 ? q * P * P : q * q * P * P);
-        best = std::max(best, (2 * S + sT1 + 2 * n + (block_in_lds ? n * n : 0)) * sizeof(double));
-    }
+    for (int p = 2; p <= pmax; ++p) best = std::max(best, hp_setup_lds_p(d, p, block_in_lds));
     return best;
 }
 
 void launch_hp_setup(const HpGeo& g, const HpTabs<double>& tb, const double* psi, double alpha,
                      double beta, const double* C, const int64_t* c_off, const int32_t* cclass,
                      double* om64, float* om32, double* s64, float* s32, size_t lds_bytes,
-                     bool block_in_lds, hipStream_t s) {
-    const unsigned grid = (unsigned)g.n_cells;
+                     bool block_in_lds, int o0, int ncell, hipStream_t s) {
+    const unsigned grid = (unsigned)ncell;
 #define HPG_HS(DD, LL)                                                                       \
     hipLaunchKernelGGL((k_hp_setup<DD, LL>), dim3(grid), dim3(1024), lds_bytes, s, g, tb, psi, \
-                       alpha, beta, C, c_off, cclass, om64, om32, s64, s32)
+                       alpha, beta, C, c_off, cclass, om64, om32, s64, s32, o0)
     if (block_in_lds) {
         if (g.d == 1) HPG_HS(1, true);
         else if (g.d == 2) HPG_HS(2, true);

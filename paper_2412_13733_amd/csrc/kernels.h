@@ -246,14 +246,17 @@ void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, con
                   double* partial, int nblocks, hipStream_t s);
 // Newton-step setup: omega_q = w_q |J| exp(-psi_h) at qp_off, and the inverse of
 // -S_hat_K = D_K + beta M_K + C_K / alpha (C of cell K at C + c_off[cclass[K]]),
-// one cell per block, written to s64 / s32 + sinv_off (either may be null
-// when block_in_lds; otherwise the block is inverted in place in s64)
+// one cell per block for the cells order[o0 .. o0 + ncell) (one degree per
+// launch, so lds_bytes = hp_setup_lds_p of that degree), written to s64 / s32
+// + sinv_off (either may be null when block_in_lds; otherwise the block is
+// inverted in place in s64)
 void launch_hp_setup(const HpGeo& g, const HpTabs<double>& tb, const double* psi, double alpha,
                      double beta, const double* C, const int64_t* c_off, const int32_t* cclass,
                      double* om64, float* om32, double* s64, float* s32, size_t lds_bytes,
-                     bool block_in_lds, hipStream_t s);
+                     bool block_in_lds, int o0, int ncell, hipStream_t s);
 // LDS bytes of that setup for degrees 2..pmax
 size_t hp_setup_lds(int d, int pmax, bool block_in_lds);
+size_t hp_setup_lds_p(int d, int p, bool block_in_lds);   // one degree
 // z_psi = (-S_hat_K)^{-1} r_psi per cell, partial <z_psi, r_psi>
 template <typename T>
 void launch_hp_prec_psi(const HpGeo& g, const T* sinv, const T* r, T* z, double* partial,

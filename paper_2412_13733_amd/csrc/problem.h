@@ -131,6 +131,10 @@ struct Problem {
     int hp_lds_elems = 256, hp_nmax = 1, np_gath = 0, np_cell = 0;
     size_t hp_setup_bytes = 0;
     bool hp_setup_in_lds = false;
+    struct HpRun {
+        int p, first, count;   // cells order[first .. first + count) have degree p
+    };
+    std::vector<HpRun> hp_runs;
     DevFdm<double> cfdm64;
     DevFdm<float> cfdm32;
     int hp_smax = 1, hp_item_elems = 256;  // (p_max+1)^d; the tuned work-item budget

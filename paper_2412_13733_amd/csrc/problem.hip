@@ -832,13 +832,18 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
     HPG_HIP(hipMemcpyAsync(params.p, hparams, sizeof(hparams), hipMemcpyHostToDevice, s));
     tstart("setup", s);
     if (M.hp) {
-        dev::launch_hp_setup(hgeo, hp_tabs<double>(), d_psi, alpha, beta, hpd.C.as<double>(),
-                             hpd.c_off.as<int64_t>(), hpd.cclass.as<int32_t>(),
-                             prec == HPG_FP64 ? om64.as<double>() : nullptr,
-                             prec == HPG_FP64 ? nullptr : om32.as<float>(),
-                             (prec == HPG_FP64 || !hp_setup_in_lds) ? sinv64.as<double>() : nullptr,
-                             prec == HPG_FP64 ? nullptr : sinv32.as<float>(), hp_setup_bytes,
-                             hp_setup_in_lds, s);
+        // one launch per degree (cells are ordered by degree), each with the LDS
+        // of its own blocks, so low-degree cells are not held to the largest
+        for (const HpRun& r : hp_runs) {
+            const bool in_lds = dev::hp_setup_lds_p(M.d, r.p, true) <= lds_max;
+            dev::launch_hp_setup(hgeo, hp_tabs<double>(), d_psi, alpha, beta, hpd.C.as<double>(),
+                                 hpd.c_off.as<int64_t>(), hpd.cclass.as<int32_t>(),
+                                 prec == HPG_FP64 ? om64.as<double>() : nullptr,
+                                 prec == HPG_FP64 ? nullptr : om32.as<float>(),
+                                 (prec == HPG_FP64 || !in_lds) ? sinv64.as<double>() : nullptr,
+                                 prec == HPG_FP64 ? nullptr : sinv32.as<float>(),
+                                 dev::hp_setup_lds_p(M.d, r.p, in_lds), in_lds, r.first, r.count, s);
+        }
     } else if (gradient) {
         const bool hbm = dev::setup_grad_in_hbm(geo);
         dev::launch_setup_grad(geo, tab64.view(), d_psi, PhiQ.as<double>(), beta,

@@ -49,6 +49,14 @@ void Problem::build_hp() {
     hp_nmax = nmax;
     hp_build_host(M, hp_lds_elems, hph);
     const HpHost& H = hph;
+    hp_runs.clear();
+    for (size_t i = 0; i < H.order.size();) {
+        size_t j = i;
+        const int p = M.deg[H.order[i]];
+        while (j < H.order.size() && M.deg[H.order[j]] == p) ++j;
+        hp_runs.push_back({p, (int)i, (int)(j - i)});
+        i = j;
+    }
     upload(hpd.cell_p, M.deg);
     upload(hpd.loc_off, H.loc_off);
     upload(hpd.psi_off, M.psi_off);
