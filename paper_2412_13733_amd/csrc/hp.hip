@@ -813,6 +813,176 @@ __global__ __launch_bounds__(256) void k_hp_vscatter_dot(int64_t n, const int32_
 }
 
 // ---------------------------------------------------------------------------
+// The vertex block of the 2-D preconditioner in one workgroup: (alpha A_VV)^{-1}
+// r_V by fast diagonalisation, V1 [(V1^T R V0) / (alpha (lam1_i + lam0_j))] V0^T
+// with R the interior-vertex residual as an n1 x n0 array, when the grid is at
+// most 64 x 64.  The eigenvector matrices, R and the intermediates stay in LDS
+// (zero-padded to multiples of 16; row pitch one more than that), and each
+// product is a 16 x 16 MFMA tile per wave; gather, the four products, scatter
+// and the vertex share of <z, r> take one launch instead of six.
+typedef double hp_v4d __attribute__((ext_vector_type(4)));
+typedef float hp_v4f __attribute__((ext_vector_type(4)));
+__device__ inline hp_v4d hp_mfma(double a, double b, hp_v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline hp_v4f hp_mfma(float a, float b, hp_v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T>
+struct HpV4 {
+    using V = hp_v4d;
+};
+template <>
+struct HpV4<float> {
+    using V = hp_v4f;
+};
+
+// C (M x N) = op(A) op(B), K terms, all dimensions multiples of 16 (K of 4);
+// TA: op(A)[i][k] = A[k][i]; TB: op(B)[k][j] = B[j][k].  (ri, ci): the tile
+// row and column of each of the lane's four results.  epi(i, j, s) is stored.
+template <typename T, bool TA, bool TB, typename Epi>
+__device__ inline void hp_lds_gemm(const T* A, int lda, const T* B, int ldb, T* C, int ldc, int M,
+                                   int N, int K, const int* ri, const int* ci, Epi epi) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int tn = N / 16, r = lane & 15, kk = lane >> 4;
+    for (int t = w; t < (M / 16) * tn; t += nw) {
+        const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+        // two accumulators (even / odd slabs of 4 terms) halve the MFMA chain
+        typename HpV4<T>::V acc = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            const int k = k0 + kk;
+            const T a = TA ? A[k * lda + i0 + r] : A[(i0 + r) * lda + k];
+            const T b = TB ? B[(j0 + r) * ldb + k] : B[k * ldb + j0 + r];
+            acc = hp_mfma(a, b, acc);
+            if (k0 + 4 < K) {
+                const T a1 = TA ? A[(k + 4) * lda + i0 + r] : A[(i0 + r) * lda + k + 4];
+                const T b1 = TB ? B[(j0 + r) * ldb + k + 4] : B[(k + 4) * ldb + j0 + r];
+                acc1 = hp_mfma(a1, b1, acc1);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + ri[v], j = j0 + ci[v];
+            C[i * ldc + j] = epi(i, j, acc[v] + acc1[v]);
+        }
+    }
+}
+
+__host__ __device__ inline int hp_pad16(int n) { return (n + 15) & ~15; }
+
+size_t hp_vsolve2_lds(int n0, int n1, size_t tsize) {
+    const size_t N0 = hp_pad16(n0), N1 = hp_pad16(n1);
+    return tsize * (N0 * (N0 + 1) + N1 * (N1 + 1) + 2 * N1 * (N0 + 1));
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_hp_vsolve2(int n0, int n1,
+                                                     const int32_t* __restrict__ vidx,
+                                                     const T* __restrict__ V0,
+                                                     const T* __restrict__ V1,
+                                                     const T* __restrict__ l0,
+                                                     const T* __restrict__ l1,
+                                                     const double* __restrict__ prm,
+                                                     const T* __restrict__ r, T* __restrict__ z,
+                                                     double* __restrict__ partial, int npart,
+                                                     const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[16];
+    __shared__ T sl0[64], sl1[64];
+    if (done && *done) return;
+    const int N0 = hp_pad16(n0), N1 = hp_pad16(n1), P0 = N0 + 1, P1 = N1 + 1;
+    T* sV0 = reinterpret_cast<T*>(smem_raw);   // N0 x N0, pitch P0
+    T* sV1 = sV0 + N0 * P0;                      // N1 x N1, pitch P1
+    T* X = sV1 + N1 * P1;                        // N1 x N0, pitch P0
+    T* Y = X + N1 * P0;
+    // every global load is issued before the first LDS store (each thread has
+    // at most 4 entries of each 64 x 64 array), so the prologue waits for two
+    // memory round trips: the vertex indices, then the residual through them
+    constexpr int NT = 1024, NE = 4;
+    const int tid = (int)threadIdx.x, nv = n0 * n1;
+    T a0[NE], a1[NE], rr[NE];
+    int gi[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        const int e = tid + NT * m;
+        const int i0 = e / N0, j0 = e - i0 * N0, i1 = e / N1, j1 = e - i1 * N1;
+        a0[m] = (i0 < n0 && j0 < n0) ? V0[i0 * n0 + j0] : (T)0;
+        a1[m] = (i1 < n1 && j1 < n1) ? V1[i1 * n1 + j1] : (T)0;
+        gi[m] = e < nv ? vidx[e] : 0;
+    }
+    T el0 = tid < n0 ? l0[tid] : (T)1, el1 = tid < n1 ? l1[tid] : (T)1;
+#pragma unroll
+    for (int m = 0; m < NE; ++m) rr[m] = tid + NT * m < nv ? r[gi[m]] : (T)0;
+    if (tid < 64) {
+        sl0[tid] = el0;
+        sl1[tid] = el1;
+    }
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        const int e = tid + NT * m;
+        if (e < N0 * N0) sV0[(e / N0) * P0 + e % N0] = a0[m];
+        if (e < N1 * N1) sV1[(e / N1) * P1 + e % N1] = a1[m];
+        if (e < N1 * N0) {   // padding of X
+            const int i = e / N0, j = e - i * N0;
+            if (i >= n1 || j >= n0) X[i * P0 + j] = (T)0;
+        }
+        if (e < nv) X[(e / n0) * P0 + e % n0] = rr[m];
+    }
+    // tile positions of the four results of this lane: an MFMA with
+    // A[i][0] = i, B[0][j] = 1 gives i, one with A[i][0] = 1, B[0][j] = j gives j
+    const int lane = threadIdx.x & 63, kk = lane >> 4;
+    const typename HpV4<T>::V zero = {0, 0, 0, 0};
+    const typename HpV4<T>::V rid =
+        hp_mfma(kk == 0 ? (T)(lane & 15) : (T)0, kk == 0 ? (T)1 : (T)0, zero);
+    const typename HpV4<T>::V cid =
+        hp_mfma(kk == 0 ? (T)1 : (T)0, kk == 0 ? (T)(lane & 15) : (T)0, zero);
+    int ri[4], ci[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        ri[v] = (int)rid[v] & 15;
+        ci[v] = (int)cid[v] & 15;
+    }
+    __syncthreads();
+    auto same = [](int, int, T s) { return s; };
+    hp_lds_gemm<T, false, false>(X, P0, sV0, P0, Y, P0, N1, N0, N0, ri, ci, same);   // R V0
+    __syncthreads();
+    const T ia = (T)prm[2];
+    hp_lds_gemm<T, true, false>(sV1, P1, Y, P0, X, P0, N1, N0, N1, ri, ci,
+                                [&](int i, int j, T s) {
+                                    return (i < n1 && j < n0) ? s * ia / (sl1[i] + sl0[j]) : (T)0;
+                                });   // V1^T (.), eigen-space division
+    __syncthreads();
+    hp_lds_gemm<T, false, true>(X, P0, sV0, P0, Y, P0, N1, N0, N0, ri, ci, same);    // (.) V0^T
+    __syncthreads();
+    hp_lds_gemm<T, false, false>(sV1, P1, Y, P0, X, P0, N1, N0, N1, ri, ci, same);   // V1 (.)
+    __syncthreads();
+    double part = 0.0;
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        const int e = tid + NT * m;
+        if (e < nv) {
+            const T v = X[(e / n0) * P0 + e % n0];
+            z[gi[m]] = v;
+            part += (double)v * (double)rr[m];
+        }
+    }
+    if (partial) {
+        const double sum = block_sum(part, red);
+        if (threadIdx.x == 0) partial[0] = sum;
+        for (int i = 1 + (int)threadIdx.x; i < npart; i += blockDim.x) partial[i] = 0.0;
+    }
+}
+
+template <typename T>
+void launch_hp_vsolve2(int n0, int n1, const int32_t* vidx, const T* V0, const T* V1, const T* l0,
+                       const T* l1, const double* prm, const T* r, T* z, double* partial,
+                       int npart, const int* done, hipStream_t s) {
+    hipLaunchKernelGGL((k_hp_vsolve2<T>), dim3(1), dim3(1024), hp_vsolve2_lds(n0, n1, sizeof(T)),
+                       s, n0, n1, vidx, V0, V1, l0, l1, prm, r, z, partial, npart, done);
+}
+
+// ---------------------------------------------------------------------------
 static inline unsigned grid_of(int64_t n, int b, int cap) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + b - 1) / b, cap));
 }
@@ -983,6 +1153,9 @@ void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T
                                           hipStream_t);                                            \
     template void launch_hp_vscatter_dot<T>(int64_t, const int32_t*, const T*, const T*, T*,     \
                                             double*, const int*, hipStream_t);                     \
+    template void launch_hp_vsolve2<T>(int, int, const int32_t*, const T*, const T*, const T*,    \
+                                       const T*, const double*, const T*, T*, double*, int,        \
+                                       const int*, hipStream_t);                                   \
     template void launch_hp_entity<T>(int64_t, const int32_t*, const int32_t*, const int32_t*,    \
                                       const int64_t*, const T*, const double*, const T*, T*,      \
                                       const int*, hipStream_t);

@@ -334,6 +334,11 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
     const int ne = dev::hp_prec_entity_blocks(M.n_u);
     T* cv = (dbl ? hpd.cv64 : hpd.cv32).template as<T>();
     const int32_t* vidx = hpd.vert.as<int32_t>();
+    // 2-D vertex grids up to 64 x 64: gather, solve and scatter in one workgroup
+    const bool vs2 = nv > 0 && M.d == 2 && hph.nv[0] <= 64 && hph.nv[1] <= 64 &&
+                     dev::hp_vsolve2_lds(hph.nv[0], hph.nv[1], sizeof(T)) <= lds_max;
+    if (vs2 && (int64_t)hph.nv[0] * hph.nv[1] != nv)
+        fail(HPG_ERR_NUMERIC, "interior-vertex list does not match its grid");
     if (timing) {
         // one launch per part, each bracketed by its timing group
         tstart("prec_psi", s);
@@ -345,18 +350,24 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
             dev::launch_hp_entity<T>(M.n_u, hpd.ent_of.as<int32_t>(), hpd.ent_first.as<int32_t>(),
                                      hpd.ent_n.as<int32_t>(), hpd.ent_off.as<int64_t>(), inv, prm,
                                      r, z, dn, s);
-        if (nv > 0) dev::launch_hp_vgather<T>(nv, vidx, r, cv, dn, s);
+        if (nv > 0 && !vs2) dev::launch_hp_vgather<T>(nv, vidx, r, cv, dn, s);
     } else {
         // psi-block, entity blocks (with their <z, r> shares) and the vertex
         // gather in one launch
         tstart("prec_u", s);
         dev::launch_hp_prec_fused<T>(hgeo, sinv, np_prec, hp_nmax, ne, hpd.ent_of.as<int32_t>(),
                                      hpd.ent_first.as<int32_t>(), hpd.ent_n.as<int32_t>(),
-                                     hpd.ent_off.as<int64_t>(), inv, prm, vidx, nv, cv, r, z,
-                                     part ? part + np_dot : nullptr, part, dn, s);
+                                     hpd.ent_off.as<int64_t>(), inv, prm, vidx, vs2 ? 0 : nv, cv,
+                                     r, z, part ? part + np_dot : nullptr, part, dn, s);
     }
     // vertices: (alpha A_VV)^{-1} by fast diagonalisation on the interior-vertex grid
-    if (nv > 0) {
+    if (vs2) {
+        dev::launch_hp_vsolve2<T>(hph.nv[0], hph.nv[1], vidx, F.V[0].template as<T>(),
+                                  F.V[1].template as<T>(), F.lam[0].template as<T>(),
+                                  F.lam[1].template as<T>(), prm, r, z,
+                                  (part && !timing) ? part + ne : nullptr,
+                                  dev::hp_vscatter_blocks(nv), dn, s);
+    } else if (nv > 0) {
         T* t1 = kw.t1.template as<T>();
         T* t2 = kw.t2.template as<T>();
         const int d = M.d;
