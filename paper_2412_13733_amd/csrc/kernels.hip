@@ -478,8 +478,22 @@ __global__ __launch_bounds__(256) void k_setup_big(Geo g, PsiTabs<double> tb,
 // fixed-order sum of np partials, identical in every block (valid in all threads)
 __device__ inline double reduce_partials(const double* __restrict__ p, int np, double* red,
                                          double* bcast) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += p[i];
+    // eight loads in flight per thread (a loop of single loads waits one L2
+    // round trip per element); the eight sums are combined in a fixed order
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int bd = (int)blockDim.x;
+    int i = (int)threadIdx.x;
+    for (; i + 7 * bd < np; i += 8 * bd) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[i + u * bd];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 7; ++u)   // fewer than eight left per thread
+        if (i + u * bd < np) a[u] += p[i + u * bd];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = block_sum(s, red);
     if (threadIdx.x == 0) *bcast = s;
     __syncthreads();
