@@ -2,8 +2,9 @@
 
 Operators (G, the block preconditioner with its block-Jacobi A-block, the
 Newton residual) element by element on small hp meshes in 1-D, 2-D and 3-D
-(random degrees, graded breakpoints, a single cell, degrees up to 12, a 70 x 3
-grid whose vertex solve exceeds the one-workgroup size), FP64
+(random degrees, graded breakpoints, a single cell, degrees up to 14 with the
+largest Schur blocks inverted in HBM beside LDS-sized ones, a 70 x 3 grid whose
+vertex solve exceeds the one-workgroup size), FP64
 (1e-12 / 1e-10) and FP32 (2e-5 / 1e-4); full LVPP solves (FP64 to 1e-10 rel-L2,
 mixed to 1e-8); and the 2-D 64 x 64 workload with degrees 2..12 graded away
 from the contact boundary (tests/golden/dip_64x64_degrees.txt): G and the
@@ -70,13 +71,15 @@ def _case(name):
         return [W.uniform_breaks(6)] * 2, np.full(36, 2)
     if name == "2d-wide":   # 69 interior vertices in direction 0: the batched-GEMM vertex solve
         return [W.uniform_breaks(70), W.uniform_breaks(3)], rng.integers(2, 5, 210)
+    if name == "2d-big":   # degrees 13, 14: Schur blocks inverted in HBM next to LDS ones
+        return [W.uniform_breaks(3), W.uniform_breaks(2)], np.array([2, 13, 5, 14, 3, 12])
     if name == "3d":
         return [W.uniform_breaks(3), _graded(3, 5), W.uniform_breaks(3)], rng.integers(2, 6, 27)
     raise KeyError(name)
 
 
 CASES = ["1d-graded", "2d-graded", "2d-high", "2d-aniso", "2d-one-cell", "2d-all-p2", "2d-wide",
-         "3d"]
+         "2d-big", "3d"]
 
 
 @pytest.mark.parametrize("name", CASES)
