@@ -326,7 +326,32 @@ __global__ __launch_bounds__(256) void k_apply_tile(Geo g, URows<T> r0, URows<T>
         if constexpr (C::DENSE) {
             // ---- u-side stiffness / mass, one direction at a time, window taps
             constexpr int WN = C::WN, WS = C::WS;
-            if constexpr (D == 2) {
+            if constexpr (D == 2 && PP == 2) {
+                // a thread takes R consecutive rows q1 of one box column b0 and
+                // reads the R + WN - 1 box values they share once (p = 2; at p = 3
+                // the registers would cost occupancy)
+                constexpr int R = 4;
+                static_assert(OW % R == 0, "owned rows in groups of R");
+                for (int it = threadIdx.x; it < XW * (OW / R); it += blockDim.x) {
+                    const int q1b = (it / XW) * R, b0 = it - (it / XW) * XW;
+                    T xv[R + WN - 1];
+#pragma unroll
+                    for (int r = 0; r < R + WN - 1; ++r) xv[r] = X[(q1b + r) * XW + b0];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const T* w = WIN + (OW + q1b + i) * WS;
+                        T sa = 0, sm = 0;
+#pragma unroll
+                        for (int j = 0; j < WN; ++j) {
+                            sa += w[j] * xv[i + j];
+                            sm += w[WN + j] * xv[i + j];
+                        }
+                        UA[(q1b + i) * XW + b0] = sa;
+                        UM[(q1b + i) * XW + b0] = sm;
+                    }
+                }
+                __syncthreads();
+            } else if constexpr (D == 2) {
                 for (int e = threadIdx.x; e < OW * XW; e += blockDim.x) {
                     const int q1 = e / XW, b0 = e - q1 * XW;
                     const T* w = WIN + (OW + q1) * WS;
@@ -419,7 +444,60 @@ __global__ __launch_bounds__(256) void k_apply_tile(Geo g, URows<T> r0, URows<T>
             }
         }
         // ---- u-side: owned unknowns
-        for (int e = threadIdx.x; e < C::OWD; e += blockDim.x) {
+        if constexpr (C::DENSE && D == 2 && PP == 2) {
+            // a thread takes R consecutive rows q1 of one owned column q0 and
+            // keeps the column's window taps (stiffness, mass, psi coupling) in
+            // registers; the arithmetic per unknown is that of the loop below
+            constexpr int WN = C::WN, WS = C::WS, R = 4;
+            for (int it = threadIdx.x; it < OW * (OW / R); it += blockDim.x) {
+                const int q1b = (it / OW) * R, q0 = it - (it / OW) * OW;
+                const int g0 = o0[0] + q0;
+                if (g0 < 0 || g0 >= g.n1[0]) continue;
+                T wa[WN], wm[WN], b0w[2 * P];
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    wa[j] = WIN[q0 * WS + j];
+                    wm[j] = WIN[q0 * WS + WN + j];
+                }
+#pragma unroll
+                for (int i0 = 0; i0 < 2 * P; ++i0) b0w[i0] = WIN[q0 * WS + 2 * WN + i0];
+                const int s0 = (q0 + PP - 1) / PP;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int q1 = q1b + i, g1 = o0[1] + q1;
+                    if (g1 < 0 || g1 >= g.n1[1]) continue;
+                    const int ub = q1 * XW + q0;
+                    T acc = 0;
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) acc += wa[j] * UM[ub + j] + wm[j] * UA[ub + j];
+                    acc *= alpha;
+                    const T* b1w = WIN + (OW + q1) * WS + 2 * WN;
+                    const int s1 = (q1 + PP - 1) / PP;
+#pragma unroll
+                    for (int i1 = 0; i1 < 2 * P; ++i1) {
+                        const int sc1 = i1 / P, a1 = i1 - sc1 * P;
+                        const T v1 = b1w[i1];
+                        const T* ps = PS + ((s1 + sc1) * CW + s0) * C::PD + a1 * P;
+#pragma unroll
+                        for (int i0 = 0; i0 < 2 * P; ++i0) {
+                            const int sc0 = i0 / P, a0 = i0 - sc0 * P;
+                            acc += b0w[i0] * v1 * ps[sc0 * C::PD + a0];
+                        }
+                    }
+                    const int64_t flat = g0 + (int64_t)g1 * g.n1[0];
+                    if (MODE == MODE_RES) {
+                        const double r = (double)acc - (double)alpha * F[flat];
+                        yu[flat] = (T)r;
+                        part_u += r * r;
+                    } else {
+                        yu[flat] = acc;
+                        part_u += (double)acc * (double)X[(q0 + PP) + XW * (q1 + PP)];
+                    }
+                }
+            }
+        }
+        for (int e = threadIdx.x; e < (C::DENSE && D == 2 && PP == 2 ? 0 : C::OWD);
+             e += blockDim.x) {
             const int q0 = e % OW, q1 = (e / OW) % OW, q2 = e / (OW * OW);
             int gi[3] = {o0[0] + q0, D > 1 ? o0[1] + q1 : 0, D > 2 ? o0[2] + q2 : 0};
             bool ok = gi[0] >= 0 && gi[0] < g.n1[0];
