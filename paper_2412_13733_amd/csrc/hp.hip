@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha,
 // quantity is contracted along direction 1 first, all of them in one step
 // from one read of the input column (x_K: M1, A1, B1^T; x_psi: B1, Vpsi),
 // then along direction 0 (A_K x_K and B_K x_psi go straight to y_loc), so an
-// item takes five barriers.  The 1-D tables of the item's degree and the
+// item takes six barriers.  The 1-D tables of the item's degree and the
 // per-cell factors and offsets are staged in LDS; index arithmetic uses a
 // float reciprocal with an exact integer correction.
 
@@ -308,15 +308,17 @@ __global__ __launch_bounds__(256) void k_hp_cell2(HpGeo g, HpTabs<T> tb, T alpha
             cPo[ci] = g.psi_off[cell];
             cQo[ci] = g.qp_off[cell];
         }
+        // the gathers index through the offsets staged above (two dependent
+        // global reads instead of four)
+        __syncthreads();
         for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
             const int ci = hp_div(e, S, rS);
-            const int64_t cell = g.order[start + ci];
-            const int gi = g.loc2glob[g.loc_off[cell] + (e - ci * S)];
+            const int gi = g.loc2glob[cLo[ci] + (e - ci * S)];
             bU[e] = gi >= 0 ? xu[gi] : (T)0;
         }
         for (int e = threadIdx.x; e < ncell * PP; e += blockDim.x) {
             const int ci = hp_div(e, PP, rPP), a = e - ci * PP;
-            const int64_t o = g.psi_off[g.order[start + ci]] + a;
+            const int64_t o = cPo[ci] + a;
             if (MODE == MODE_RES) {
                 bX[ci * S + a] = xpsi[o] - xpsi_prev[o];
                 bP[ci * S + a] = xpsi[o];
