@@ -533,6 +533,21 @@ def main():
         if "rel_l2_vs_fp64" in r:
             s["rel_l2_vs_fp64"] = r["rel_l2_vs_fp64"]
         out["path_" + prec] = s
+    # the headline path again with the optional extension of full Newton steps
+    # (not the paper's line search, which only backtracks; same subproblem
+    # solutions): reported beside it, never as the headline
+    if "mixed" in results:
+        opts = results["mixed"]["opts"]
+        opts.step_extension = 1
+        prob.solve_device(d_u, d_psi, opts)
+        r = run_solves(prob, d_u, d_psi, opts, args.steps, torch)
+        s = summary(r)
+        if "fp64" in results:
+            diff, nrm = prob.l2_diff(d_u, d_u64)
+            s["rel_l2_vs_fp64"] = diff / nrm
+        out["path_mixed_step_extension"] = s
+        print("[bench] mixed with step extension: %d solves in %.3f s, newton %d"
+              % (args.steps, r["seconds"], r["newton"]), file=sys.stderr, flush=True)
     if not args.no_probe:
         del prob
         torch.cuda.empty_cache()

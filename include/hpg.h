@@ -140,6 +140,10 @@ typedef struct hpg_solve_opts {
     int32_t krylov_chunk;   /* iterations enqueued between convergence checks (default 16) */
     int32_t inexact_newton; /* 1: MINRES tolerance eta_k = clamp(1e-6 err_k, krylov_rtol, 1e-6)
                                from the current Newton error err_k (default 0: krylov_rtol) */
+    int32_t step_extension; /* 1: when the full Newton step passes the line search, steps of
+                               2, 4 and 8 times the direction are tried in turn and the last
+                               one that lowers the merit further is taken (default 0: the
+                               backtracking search alone) */
 } hpg_solve_opts;
 
 void hpg_default_opts(hpg_solve_opts* opts);
@@ -157,6 +161,7 @@ typedef struct hpg_solve_stats {
                                those whose FP32 Krylov solve broke down, hit its cap or was
                                rejected by the line search, and, after three of those within
                                one proximal step, the rest of that step's directions */
+    int32_t step_extensions; /* Newton steps lengthened beyond the full step (step_extension) */
 } hpg_solve_stats;
 
 /* Solve; u_out[n_u], psi_out[n_psi] (psi may be NULL), lam_out[n_psi]

@@ -36,6 +36,8 @@ hpg_solve_opts checked_opts(const hpg_solve_opts* in) {
     if (o.precision != HPG_FP64 && o.precision != HPG_MIXED)
         fail(HPG_ERR_INVALID_ARG, "precision must be HPG_FP64 or HPG_MIXED");
     if (!(o.beta >= 0)) fail(HPG_ERR_INVALID_ARG, "beta must be >= 0");
+    if (o.step_extension != 0 && o.step_extension != 1)
+        fail(HPG_ERR_INVALID_ARG, "step_extension must be 0 or 1");
     return o;
 }
 
@@ -291,6 +293,7 @@ void hpg_default_opts(hpg_solve_opts* o) {
     o->precision = HPG_FP64;
     o->krylov_chunk = 16;
     o->inexact_newton = 0;
+    o->step_extension = 0;
 }
 
 

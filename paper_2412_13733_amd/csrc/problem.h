@@ -170,6 +170,7 @@ struct Problem {
     int np_u = 0, np_psi = 0, np_dot = 0, np_prec = 0, np_cap = 0;
     // Newton state
     DBuf u, psi, psi_prev, ut, pt, R, u_old, delta64, delta32, rhs32, xk64;
+    DBuf ux, px;   // trial iterate of an extended Newton step
     // timing
     bool timing = false;
     std::string timing_group;

@@ -1281,6 +1281,10 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
     } else {
         xk64.alloc(n * sizeof(double));
     }
+    if (o.step_extension) {
+        ux.alloc(M.n_u * sizeof(double));
+        px.alloc(M.n_psi * sizeof(double));
+    }
     double* du = u.as<double>();
     double* dp = psi.as<double>();
     double* dpp = psi_prev.as<double>();
@@ -1368,6 +1372,24 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                     const double m1 = std::sqrt(a2 / (alpha_k * alpha_k) + b2);
                     if (m1 <= (1.0 - 1e-4 * t) * m0) {
                         acc = true;
+                        // optional extension of a full step (2, 4, 8 times the
+                        // direction) while the merit keeps falling
+                        double mb = m1;
+                        for (double te = 2.0; o.step_extension && t == 1.0 && te <= 8.0; te *= 2.0) {
+                            double* ue = ux.as<double>();
+                            double* pe = px.as<double>();
+                            dev::launch_axpy_to<double>(M.n_u, du, te, dd, ue, s);
+                            dev::launch_axpy_to<double>(M.n_psi, dp, te, dd + M.n_u, pe, s);
+                            residual(ue, pe, dpp, alpha_k, dR, s, &a2, &b2);
+                            const double me = std::sqrt(a2 / (alpha_k * alpha_k) + b2);
+                            if (!(me < mb)) break;
+                            mb = me;
+                            HPG_HIP(hipMemcpyAsync(dut, ue, M.n_u * sizeof(double),
+                                                   hipMemcpyDeviceToDevice, s));
+                            HPG_HIP(hipMemcpyAsync(dpt, pe, M.n_psi * sizeof(double),
+                                                   hipMemcpyDeviceToDevice, s));
+                            S.step_extensions += 1;
+                        }
                         break;
                     }
                     t *= 0.5;

@@ -39,7 +39,8 @@ class SolveOpts(ctypes.Structure):
                 ("stall_tol", ctypes.c_double), ("max_newton", ctypes.c_int32),
                 ("krylov_rtol", ctypes.c_double), ("max_krylov", ctypes.c_int32),
                 ("beta", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("krylov_chunk", ctypes.c_int32), ("inexact_newton", ctypes.c_int32)]
+                ("krylov_chunk", ctypes.c_int32), ("inexact_newton", ctypes.c_int32),
+                ("step_extension", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -47,7 +48,7 @@ class SolveStats(ctypes.Structure):
                 ("newton_iters", ctypes.c_int32), ("line_search_halvings", ctypes.c_int32),
                 ("krylov_iters", ctypes.c_int64), ("newton_error", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("alpha_last", ctypes.c_double),
-                ("fp64_fallbacks", ctypes.c_int32)]
+                ("fp64_fallbacks", ctypes.c_int32), ("step_extensions", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

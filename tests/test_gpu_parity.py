@@ -181,3 +181,30 @@ def test_full_solve_mixed_precision(dim, m, p, which):
     log("  gpu", st.as_dict(), "rel L2 u", eu)
     assert st.status == 0
     assert eu < 1e-8
+
+
+@pytest.mark.parametrize("dim,m,p,which,precision", [(1, 16, 4, "w1d", 0), (2, 6, 4, "w2d", 0),
+                                                     (2, 6, 4, "w2d", 1), (3, 3, 3, "w3d", 0)])
+def test_step_extension_same_solution(dim, m, p, which, precision):
+    # the optional extension of full Newton steps changes the Newton path, not
+    # the subproblem solutions: the result still matches the oracle (whose
+    # line search only backtracks)
+    log("step extension", dim, m, p, which, "precision", precision)
+    data = {"w1d": W.w1d(), "w2d": W.w2d(0), "w3d": W.w3d()}[which]
+    mesh, prob, sysm = build_pair(dim, m, p, data)
+    ro = lvpp.solve(sysm, lvpp.Options())
+    kw = dict(newton_tol=1e-10, krylov_rtol=1e-6) if precision else {}
+    opts = prob_opts(fixed=ro.prox_steps, precision=precision, step_extension=1, **kw)
+    u, psi, lam, st = prob.solve(opts, want_lambda=True)
+    eu = sysm.l2_norm_u(u - ro.u) / sysm.l2_norm_u(ro.u)
+    log("  gpu", st.as_dict(), "rel L2 u", eu)
+    assert st.status == 0
+    assert eu < (1e-8 if precision else 1e-10)
+
+
+def test_step_extension_rejects_other_values():
+    from paper_2412_13733_amd import hpg
+    mesh, prob, sysm = build_pair(1, 4, 2, W.w1d())
+    with pytest.raises(hpg.HpgError) as e:
+        prob.solve(prob_opts(step_extension=2))
+    assert e.value.status == hpg.ERR_INVALID_ARG
