@@ -1252,6 +1252,8 @@ constexpr double kFallbackKrylovRtol = 1e-10;
 // computes the remaining Newton directions of that step in FP64 directly (a
 // subproblem whose FP32 solves keep breaking down would pay for both)
 constexpr int kMaxFallbacksPerStep = 3;
+// longest extended Newton step (step_extension), in multiples of the direction
+constexpr double kMaxStepExtension = 8.0;
 
 // Newton direction with the FP64 operator: b = -R, MINRES into xk64, delta = xk64
 int Problem::newton_direction64(const double* dR, double* dd, double eta, const hpg_solve_opts& o,
@@ -1375,7 +1377,9 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                         // optional extension of a full step (2, 4, 8 times the
                         // direction) while the merit keeps falling
                         double mb = m1;
-                        for (double te = 2.0; o.step_extension && t == 1.0 && te <= 8.0; te *= 2.0) {
+                        const bool full = t == 1.0;
+                        for (double te = 2.0; o.step_extension && full && te <= kMaxStepExtension;
+                             te *= 2.0) {
                             double* ue = ux.as<double>();
                             double* pe = px.as<double>();
                             dev::launch_axpy_to<double>(M.n_u, du, te, dd, ue, s);
@@ -1389,6 +1393,7 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                             HPG_HIP(hipMemcpyAsync(dpt, pe, M.n_psi * sizeof(double),
                                                    hipMemcpyDeviceToDevice, s));
                             S.step_extensions += 1;
+                            t = te;
                         }
                         break;
                     }
