@@ -1358,6 +1358,10 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
             bool acc = false;
             for (int attempt = need64 ? 1 : 0; attempt < (use32 ? 2 : 1) && !acc; ++attempt) {
                 if (attempt == 1) {
+                    if (trace)
+                        std::fprintf(stderr, "hpg: prox %d newton %d fp32 direction %s, fp64 recomputed\n",
+                                     k, it, need64 ? (last_minres_breakdown ? "broke down" : "hit the cap")
+                                                   : "rejected by the line search");
                     residual(du, dp, dpp, alpha_k, dR, s, &nu2, &np2);
                     setup(dp, alpha_k, o.beta, HPG_FP64, s);
                     its = newton_direction64(dR, dd, std::min(eta, kFallbackKrylovRtol), o, s);
