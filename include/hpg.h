@@ -264,6 +264,9 @@ typedef struct hpg_serving_stats {
     uint64_t hbm_budget, hbm_reserved, hbm_peak_reserved;
 } hpg_serving_stats;
 
+/* Device bytes one solve of this mesh holds at precision (HPG_FP64 / HPG_MIXED)
+ * with default options; a request with step_extension on is admitted with
+ * (n_u + n_psi) doubles more. */
 hpg_status hpg_problem_footprint(const hpg_mesh* mesh, int32_t precision, uint64_t* bytes);
 hpg_status hpg_server_create(int device, uint64_t hbm_budget, int32_t max_slots,
                              hpg_server** out);

@@ -287,6 +287,8 @@ hpg_status hpg_server_submit(hpg_server* srv, const hpg_mesh* mesh, const double
                 fail(HPG_ERR_INVALID_ARG, "gradient constraint needs phi > 0");
         }
         r->footprint = footprint_bytes(r->mesh, r->opts.precision);
+        if (r->opts.step_extension)   // the trial iterate of an extended Newton step
+            r->footprint += (size_t)(r->mesh.n_u + r->mesh.n_psi) * sizeof(double);
         if (r->footprint > S.budget)
             fail(HPG_ERR_BUDGET, "request footprint exceeds the server's HBM budget");
         {
