@@ -160,7 +160,8 @@ typedef struct hpg_solve_stats {
     int32_t fp64_fallbacks; /* HPG_MIXED: Newton directions computed with the FP64 operator:
                                those whose FP32 Krylov solve broke down, hit its cap or was
                                rejected by the line search, and, after three of those within
-                               one proximal step, the rest of that step's directions */
+                               one proximal step, the rest of that step's directions (after
+                               twelve over the solve, every later direction) */
     int32_t step_extensions; /* Newton steps lengthened beyond the full step (step_extension) */
 } hpg_solve_stats;
 

@@ -1252,6 +1252,8 @@ constexpr double kFallbackKrylovRtol = 1e-10;
 // computes the remaining Newton directions of that step in FP64 directly (a
 // subproblem whose FP32 solves keep breaking down would pay for both)
 constexpr int kMaxFallbacksPerStep = 3;
+// ... and after this many over the whole solve, every later direction
+constexpr int kMaxFallbacksPerSolve = 12;
 // longest extended Newton step (step_extension), in multiples of the direction
 constexpr double kMaxStepExtension = 8.0;
 
@@ -1325,7 +1327,8 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                 break;
             }
             if (it == o.max_newton) break;
-            const bool use32 = mixed && fb_step < kMaxFallbacksPerStep;
+            const bool use32 = mixed && fb_step < kMaxFallbacksPerStep &&
+                               S.fp64_fallbacks < kMaxFallbacksPerSolve;
             setup(dp, alpha_k, o.beta, use32 ? HPG_MIXED : HPG_FP64, s);
             // inexact Newton (optional): a linear-solve tolerance proportional
             // to the current error.  MINRES measures the residual in the
