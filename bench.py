@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="prefix of the 512-request serving stream to run")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-chunk", type=int, default=16,
+                    help="MINRES iterations per captured chunk of a serving request")
     ap.add_argument("--no-hp", action="store_true",
                     help="skip the per-cell-degree workload (2-D 64x64, degrees 2..12)")
     ap.add_argument("--hp-steps", type=int, default=2)
@@ -264,6 +266,9 @@ def serving_requests(hpg, W, n_req):
     return arrivals[:n_req], built
 
 
+SERVE_KRYLOV_CHUNK = 16   # MINRES iterations per captured chunk of a serving request
+
+
 def request_opts(hpg, r, precision):
     """Obstacle requests: alpha_k = 2^k to the 1e-10 proximal tolerance.
     Gradient requests: the paper's schedule for that problem class,
@@ -271,7 +276,7 @@ def request_opts(hpg, r, precision):
     stall is accepted at error 1e-8 (the serving accuracy target); up to 100
     Newton steps per subproblem (high-degree requests need ~35 damped steps
     before the quadratic phase)."""
-    kw = dict(stall_tol=1e-8, max_newton=100)
+    kw = dict(stall_tol=1e-8, max_newton=100, krylov_chunk=SERVE_KRYLOV_CHUNK)
     if r["kind"] == "gradient":
         kw.update(alpha0=2.0 ** -7, alpha_factor=2.0 ** 0.5, alpha_max=4.0, fixed_prox_steps=20)
     if precision == hpg.MIXED:
@@ -402,6 +407,8 @@ def hp_bench(args, torch, hpg, W):
 
 def main():
     args = parse()
+    global SERVE_KRYLOV_CHUNK
+    SERVE_KRYLOV_CHUNK = args.serve_chunk
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this hpG build is single-GPU "
               "(no collectives); use --gpus 1", file=sys.stderr)
