@@ -19,7 +19,9 @@ SOURCES = ["tables.cpp", "kernels.hip", "tile.hip", "tile_d1.hip", "tile_d2.hip"
            "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# packed-fp32 instructions are disabled for all device code
+# the compiler's packed two-wide FP32 arithmetic is disabled for all device
+# code: some of its forms have given silently wrong results on this GPU, and
+# the FP32 paths here do not depend on it for speed
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
           "-Wall", "-Wno-unused-result"]
