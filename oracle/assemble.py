@@ -18,7 +18,8 @@ Gradient (Sec. 4.2, eq. (pG:gradient)):
     [D_psi] = Frechet derivative of N,
     [E_beta]_ij = beta (grad_h eta_i, grad_h eta_j), eta in Phi_h^d (Y_n basis,
     identified index-for-index with zeta; Y_0..Y_{P-1} per direction).
-Exponent guard (reading Q5): exp(-psi) is evaluated as exp(min(-psi, 700)).
+Exponent guard (a reading: the paper does not say how exp(-psi) is kept
+finite): exp(-psi) is evaluated as exp(min(-psi, 700)).
 """
 import numpy as np
 import scipy.sparse as sp

@@ -146,7 +146,8 @@ def solve(system, opts=None):
     return res
 
 
-# ---- diagnostics (readings Q13/Q14) -----------------------------------------
+# ---- diagnostics: feasibility and complementarity (readings of how the paper's
+# feasible and complementary iterates are measured on the discrete level) -----
 def complementarity(system, psi, lam):
     """CR = sum_K sum_q w |J| |lambda_h(x_q)| exp(-psi_h(x_q)), and its relative
     form CR / (||lambda||_{L1,h} ||phi||_inf) (obstacle only)."""
@@ -161,5 +162,6 @@ def complementarity(system, psi, lam):
 
 
 def max_violation(system, u):
-    """max over quadrature points of u_h - phi (reading Q13, F3)."""
+    """max over quadrature points of u_h - phi (pointwise feasibility at the
+    Gauss points, a reading of the constraint u <= phi on the discrete level)."""
     return float(np.max(system.u_at_points(u) - system.phi_qp))

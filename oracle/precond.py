@@ -12,7 +12,8 @@ complement S = -(D_psi + E_beta + B^T A_alpha^{-1} B) is replaced by
 * gradient, eq. (schur-preconditioner:gradient): S_hat = -D_psi - E_beta.
 
 A symmetric Krylov method needs a positive definite preconditioner, so the
-operator returned is the SPD form diag(alpha A, -S_hat) (reading Q12).
+operator returned is the SPD form diag(alpha A, -S_hat) (a reading: the paper
+writes P_D = diag(A_alpha, S_hat) for FGMRES, where the sign does not matter).
 
 With one degree per cell (``HpMesh``) the u space is no longer a tensor
 product and the A-block is replaced (reading) by the block-Jacobi operator
