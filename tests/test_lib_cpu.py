@@ -113,3 +113,14 @@ def test_per_cell_degree_mesh_matches_the_oracle_numbering_sizes():
     a = hpg.Mesh(2, [16, 16], 0, degree=np.full(256, 6))
     b = hpg.Mesh(2, [16, 16], 0, degree=np.r_[np.full(128, 6), np.full(128, 3)])
     assert a.footprint(0) > b.footprint(0) > 0
+
+
+def test_solve_options_struct_matches_the_library():
+    # the binding's hpg_solve_opts layout must be the library's: the size field
+    # hpg_default_opts writes is sizeof(hpg_solve_opts) in C, and every field
+    # keeps its documented default
+    o = hpg.default_opts()
+    assert o.size == ctypes.sizeof(hpg.SolveOpts)
+    assert (o.alpha0, o.alpha_factor, o.max_prox, o.max_newton, o.max_krylov) == (2.0, 2.0, 60, 60, 2000)
+    assert (o.newton_tol, o.krylov_rtol, o.beta, o.precision) == (1e-12, 1e-10, 0.0, hpg.FP64)
+    assert (o.krylov_chunk, o.inexact_newton, o.step_extension) == (16, 0, 0)
