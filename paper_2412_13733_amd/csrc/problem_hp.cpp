@@ -130,8 +130,8 @@ void Problem::build_hp() {
 }
 
 // Work items of the cell pass (a project-side autotuner): the cell pass is
-// timed, as an FP32 G apply on zero data, with items of at most 256, 512 and
-// 1024 local functions (more cells per item amortise its barriers, fewer
+// timed, as an FP32 G apply on zero data, with items of at most 256, 384, 512,
+// 768 and 1024 local functions (more cells per item amortise its barriers, fewer
 // give more blocks), and the fastest is kept.  HPG_HP_ITEM_ELEMS fixes it.
 void Problem::set_hp_items(int item_elems) {
     const int lds = std::max(item_elems, hp_smax);
@@ -153,7 +153,7 @@ void Problem::tune_hp_items() {
     if (const char* e = std::getenv("HPG_HP_ITEM_ELEMS")) {
         cands.push_back(std::max(1, std::atoi(e)));
     } else {
-        for (int c : {256, 512, 1024})
+        for (int c : {256, 384, 512, 768, 1024})
             if (dev::hp_cell_lds(M.d, std::max(c, hp_smax), M.p + 1, sizeof(double),
                                  dev::MODE_RES) <= lds_max)
                 cands.push_back(c);
