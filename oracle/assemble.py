@@ -228,6 +228,18 @@ class System:
     def l2_norm_u(self, u):
         return float(np.sqrt(max(u @ (self.Mu @ u), 0.0)))
 
+    def grad_u_at_points(self, u):
+        """Physical gradient of u_h at every quadrature point, shape (n_qp, d)."""
+        mesh = self.mesh
+        out = np.zeros((mesh.n_qp, mesh.d))
+        for cno, cidx in mesh.cells():
+            W, Vu, Gu, Vpsi, hs = _cell_tables(mesh, self.ref_for(cno), cidx)
+            ug = mesh.u_dofs(cidx)
+            loc = np.where(ug >= 0, u[np.maximum(ug, 0)], 0.0)
+            for k in range(mesh.d):
+                out[mesh.qp_slice(cno), k] = Gu[k] @ loc
+        return out
+
     def u_at_points(self, u):
         mesh = self.mesh
         out = np.zeros(mesh.n_qp)

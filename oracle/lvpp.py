@@ -165,3 +165,10 @@ def max_violation(system, u):
     """max over quadrature points of u_h - phi (pointwise feasibility at the
     Gauss points, a reading of the constraint u <= phi on the discrete level)."""
     return float(np.max(system.u_at_points(u) - system.phi_qp))
+
+
+def max_violation_gradient(system, u):
+    """max over quadrature points of |grad u_h| - phi (the gradient constraint
+    |grad u| <= phi at the Gauss points)."""
+    g = system.grad_u_at_points(u)
+    return float(np.max(np.sqrt(np.sum(g * g, axis=1)) - system.phi_qp))
