@@ -63,6 +63,8 @@ typedef int hpg_status;
 #define HPG_FP64 0               /* every GPU operation in FP64 */
 #define HPG_MIXED 1              /* FP32 Krylov operator/preconditioner, FP64 Newton */
 
+#define HPG_KRYLOV_MINRES 0      /* preconditioned MINRES on G with the SPD form of P_D */
+
 typedef struct hpg_mesh hpg_mesh;
 typedef struct hpg_problem hpg_problem;
 
@@ -121,6 +123,15 @@ void hpg_destroy_problem(hpg_problem* prob);
 hpg_status hpg_set_forcing(hpg_problem* prob, const double* f_qp, size_t n_qp);
 hpg_status hpg_set_obstacle(hpg_problem* prob, const double* phi_qp, size_t n_qp);
 
+/* Convenience forms: fn(x, ctx) is called on the calling thread once per
+ * quadrature point, x = the point's dim coordinates (the order of
+ * hpg_quadrature_points), and the values are then set as by hpg_set_forcing /
+ * hpg_set_obstacle (same validation).  fn must not call into the library for
+ * the same problem.  NULL fn: HPG_ERR_INVALID_ARG. */
+typedef double (*hpg_point_fn)(const double* x, void* ctx);
+hpg_status hpg_set_forcing_fn(hpg_problem* prob, hpg_point_fn fn, void* ctx);
+hpg_status hpg_set_obstacle_fn(hpg_problem* prob, hpg_point_fn fn, void* ctx);
+
 /* ---- solve options and statistics ---------------------------------------- */
 typedef struct hpg_solve_opts {
     int32_t size;           /* sizeof(hpg_solve_opts), for ABI evolution */
@@ -144,6 +155,26 @@ typedef struct hpg_solve_opts {
                                2, 4 and 8 times the direction are tried in turn and the last
                                one that lowers the merit further is taken (default 0: the
                                backtracking search alone) */
+    int32_t q;              /* Gauss-Legendre points per direction: 0 (default) or p + 1, the
+                               only rule built; any other value is HPG_ERR_INVALID_ARG */
+    int32_t krylov;         /* HPG_KRYLOV_MINRES (default); any other value is
+                               HPG_ERR_INVALID_ARG */
+    /* Warm start / resume (Sec. 2.1: subproblem k depends only on psi_{k-1}):
+     * with k0 >= 0 and both vectors given, the solve starts from the state
+     * after k0 proximal steps, (u_{k0}, psi_{k0}) = (warm_u, warm_psi): step
+     * k0 + 1 uses alpha_{k0+1} = min(alpha0 factor^k0, alpha_max), psi_prev =
+     * warm_psi and the Newton initial guess (warm_u, warm_psi); the outer
+     * stop compares u_{k0+1} with warm_u; max_prox and fixed_prox_steps count
+     * from step 1, so a solve resumed at k0 runs steps k0 + 1 .. of the same
+     * sequence and, in FP64 mode, returns bit for bit what the uninterrupted
+     * solve returns (a mixed solve restarts its count of FP64 recomputations).
+     * Pointers: host memory for hpg_solve and hpg_server_submit (copied),
+     * device memory on the problem's device for hpg_solve_device; read only.
+     * Both NULL (default): u_0 = psi_0 = 0 and k0 must be 0.  Exactly one
+     * NULL, k0 < 0 or k0 >= the step cap: HPG_ERR_INVALID_ARG. */
+    const double* warm_u;
+    const double* warm_psi;
+    int32_t k0;
 } hpg_solve_opts;
 
 void hpg_default_opts(hpg_solve_opts* opts);
@@ -158,11 +189,27 @@ typedef struct hpg_solve_stats {
     double seconds;         /* wall time of the solve */
     double alpha_last;
     int32_t fp64_fallbacks; /* HPG_MIXED: Newton directions computed with the FP64 operator:
-                               those whose FP32 Krylov solve broke down, hit its cap or was
-                               rejected by the line search, and, after three of those within
-                               one proximal step, the rest of that step's directions (after
-                               twelve over the solve, every later direction) */
+                               the FP64 recomputations below, and, after three of those
+                               within one proximal step, the rest of that step's directions
+                               (after twelve over the solve, every later direction) */
     int32_t step_extensions; /* Newton steps lengthened beyond the full step (step_extension) */
+    int32_t fp64_recomputations; /* HPG_MIXED: FP32 directions that broke down, hit the Krylov
+                                    cap or were rejected by the line search, and were computed
+                                    again with the FP64 operator */
+    /* Diagnostics of the returned iterate, evaluated on the device at the
+     * n_qp Gauss points with lambda = (psi_{K-1} - psi_K) / alpha_K of the
+     * last proximal step K (Sec. 2.1):
+     * complementarity = sum_K sum_q w_q |J_K| |lambda_h(x_q)| exp(-psi_h(x_q))
+     *   (obstacle; the products of the multiplier and the latent gap
+     *   exp(-psi) = phi - u~ vanish at the limit), complementarity_rel = that
+     *   sum / (sum_K sum_q w_q |J_K| |lambda_h(x_q)| * max_q |phi_q|); both 0
+     *   for the gradient constraint, whose multiplier is a vector field;
+     * max_violation = max_q (u_h(x_q) - phi_q) (obstacle) or
+     *   max_q (|grad u_h(x_q)| - phi_q) (gradient): pointwise feasibility at
+     *   the Gauss points (<= 0 when feasible there). */
+    double complementarity;
+    double complementarity_rel;
+    double max_violation;
 } hpg_solve_stats;
 
 /* Solve; u_out[n_u], psi_out[n_psi] (psi may be NULL), lam_out[n_psi]
@@ -244,7 +291,13 @@ hpg_status hpg_kernel_time(hpg_problem* prob, const char* group, int64_t* launch
  * hpg_server_wait: as poll, blocking until the request is done.
  * hpg_server_stats: counts, latency percentiles (submission to completion)
  *   and throughput over the requests completed so far.
- * hpg_server_destroy: drops queued requests, waits for running ones. */
+ * hpg_server_destroy: queued requests complete at once with
+ *   HPG_ERR_INVALID_ARG ("server destroyed before the request ran"), which
+ *   wakes callers blocked in hpg_server_wait on them; running requests finish;
+ *   callers already inside hpg_server_poll / hpg_server_wait return before the
+ *   server is freed.  No call on the handle may start once destroy has begun.
+ * Warm starts (hpg_solve_opts.warm_u / warm_psi, host pointers) are copied by
+ * hpg_server_submit. */
 typedef struct hpg_server hpg_server;
 
 typedef struct hpg_request_info {

@@ -151,12 +151,14 @@ def solve(system, opts=None):
 def complementarity(system, psi, lam):
     """CR = sum_K sum_q w |J| |lambda_h(x_q)| exp(-psi_h(x_q)), and its relative
     form CR / (||lambda||_{L1,h} ||phi||_inf) (obstacle only)."""
-    lq = system.psi_at_points(lam)[:, 0, :]
-    pq = system.psi_at_points(psi)[:, 0, :]
-    W = np.array([c[2] for c in system.cells])
-    e = np.exp(np.minimum(-pq, EXP_CAP))
-    cr = float(np.sum(W * np.abs(lq) * e))
-    l1 = float(np.sum(W * np.abs(lq)))
+    cr, l1 = 0.0, 0.0
+    # cell by cell: the number of Gauss points may differ between cells
+    for cell, lq, pq in zip(system.cells, system.psi_at_points(lam),
+                            system.psi_at_points(psi)):
+        W = cell[2]
+        e = np.exp(np.minimum(-pq[0], EXP_CAP))
+        cr += float(np.sum(W * np.abs(lq[0]) * e))
+        l1 += float(np.sum(W * np.abs(lq[0])))
     rel = cr / max(l1 * np.max(np.abs(system.phi_qp)), 1e-300)
     return cr, rel
 

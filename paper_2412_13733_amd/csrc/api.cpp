@@ -38,6 +38,12 @@ hpg_solve_opts checked_opts(const hpg_solve_opts* in) {
     if (!(o.beta >= 0)) fail(HPG_ERR_INVALID_ARG, "beta must be >= 0");
     if (o.step_extension != 0 && o.step_extension != 1)
         fail(HPG_ERR_INVALID_ARG, "step_extension must be 0 or 1");
+    if (o.krylov != HPG_KRYLOV_MINRES) fail(HPG_ERR_INVALID_ARG, "krylov must be HPG_KRYLOV_MINRES");
+    if (o.q < 0) fail(HPG_ERR_INVALID_ARG, "q must be 0 (p + 1) or p + 1");
+    if ((o.warm_u == nullptr) != (o.warm_psi == nullptr))
+        fail(HPG_ERR_INVALID_ARG, "warm start needs both warm_u and warm_psi");
+    if (o.k0 < 0 || (o.k0 > 0 && !o.warm_u))
+        fail(HPG_ERR_INVALID_ARG, "k0 must be >= 0, and 0 without a warm start");
     return o;
 }
 
@@ -274,6 +280,35 @@ hpg_status hpg_set_obstacle(hpg_problem* prob, const double* phi_qp, size_t n_qp
     });
 }
 
+// values of fn at the problem's quadrature points (host)
+static std::vector<double> eval_at_points(hpg_problem* prob, hpg_point_fn fn, void* ctx) {
+    if (!fn) fail(HPG_ERR_INVALID_ARG, "fn is NULL");
+    const Mesh& M = prob->P.M;
+    hpg_mesh tmp;
+    tmp.M = M;
+    std::vector<double> x((size_t)M.n_qp * M.d), v((size_t)M.n_qp);
+    const hpg_status st = hpg_quadrature_points(&tmp, x.data());
+    if (st != HPG_OK) fail(st, "quadrature points");
+    for (int64_t i = 0; i < M.n_qp; ++i) v[i] = fn(x.data() + i * M.d, ctx);
+    return v;
+}
+
+hpg_status hpg_set_forcing_fn(hpg_problem* prob, hpg_point_fn fn, void* ctx) {
+    return guarded([&]() -> hpg_status {
+        check_problem(prob);
+        const std::vector<double> v = eval_at_points(prob, fn, ctx);
+        return hpg_set_forcing(prob, v.data(), v.size());
+    });
+}
+
+hpg_status hpg_set_obstacle_fn(hpg_problem* prob, hpg_point_fn fn, void* ctx) {
+    return guarded([&]() -> hpg_status {
+        check_problem(prob);
+        const std::vector<double> v = eval_at_points(prob, fn, ctx);
+        return hpg_set_obstacle(prob, v.data(), v.size());
+    });
+}
+
 void hpg_default_opts(hpg_solve_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -294,6 +329,11 @@ void hpg_default_opts(hpg_solve_opts* o) {
     o->krylov_chunk = 16;
     o->inexact_newton = 0;
     o->step_extension = 0;
+    o->q = 0;
+    o->krylov = HPG_KRYLOV_MINRES;
+    o->warm_u = nullptr;
+    o->warm_psi = nullptr;
+    o->k0 = 0;
 }
 
 

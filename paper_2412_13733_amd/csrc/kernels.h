@@ -163,6 +163,15 @@ void launch_lambda(int64_t n, const double* psi_prev, const double* psi, double 
                    double* lam, hipStream_t s);
 void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u, const double* v,
                double* partial, hipStream_t s);
+// Diagnostics of an iterate (diag.hip): per block b, partial[3 b] = sum w |J|
+// |lambda_h| exp(-psi_h), partial[3 b + 1] = sum w |J| |lambda_h| (obstacle;
+// 0 for the gradient constraint), partial[3 b + 2] = max over the block's
+// Gauss points of u_h - phi (obstacle) or |grad u_h| - phi (gradient).  Du:
+// q x (p+1) reference derivative table; phiq: phi at the Gauss points.
+// At most nblocks blocks (one cell at a time each).
+void launch_diag(const Geo& g, const PsiTabs<double>& tb, const double* Du, const double* u,
+                 const double* psi, const double* lam, const double* phiq, double* partial,
+                 int nblocks, hipStream_t s);
 
 // ---- gradient constraint |grad u| <= phi (gradient.hip) ---------------------
 // omega layout: [cell][pair (c <= l, row-major upper triangle)][q^d] of the
@@ -241,6 +250,10 @@ template <typename T>
 void launch_hp_gather(int64_t n_u, const int32_t* inc_ptr, const int32_t* inc_idx, const T* yloc,
                       const double* F, double alpha, const T* xu, T* yu, double* partial,
                       int nblocks, const int* done, int mode, hipStream_t s);
+// launch_diag on a mesh with one degree per cell (obstacle constraint)
+void launch_hp_diag(const HpGeo& g, const HpTabs<double>& tb, const double* u, const double* psi,
+                    const double* lam, const double* phiq, double* partial, int nblocks,
+                    hipStream_t s);
 // ||a - b||_{L2}^2 and ||a||_{L2}^2 per block (partial[2 i], partial[2 i + 1])
 void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, const double* b,
                   double* partial, int nblocks, hipStream_t s);

@@ -153,7 +153,10 @@ struct Problem {
     std::vector<double> f_qp, phi_qp;
     bool have_f = false, have_phi = false;
     DBuf F, Phi;
-    DBuf PhiQ;                             // gradient: phi at the Gauss points (FP64)
+    DBuf PhiQ;                             // phi at the Gauss points (FP64)
+    double phi_absmax = 0.0;               // max |phi| over the Gauss points
+    DBuf Du64;                             // q x (p+1) reference derivatives of the u basis
+    DBuf diag_part;                        // per-block sums of the solve diagnostics
     bool gradient = false;                 // constraint |grad u| <= phi
     bool prec_big = false;                 // psi blocks streamed from HBM (too large for LDS)
     int setup_mode = 0;                    // obstacle Schur blocks: dev::SETUP_LDS / _HBM_T2 / _HBM
@@ -206,6 +209,8 @@ struct Problem {
     void residual(const double* u, const double* psi, const double* psi_prev, double alpha,
                   double* R, hipStream_t s, double* nu2, double* np2);
     double l2_diff(const double* a, const double* b, double* norm_a, hipStream_t s);
+    void diagnostics(const double* u, const double* psi, const double* lam, hipStream_t s,
+                     double* cr, double* cr_rel, double* mv);
     hpg_status solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stats* st, double* d_u_out,
                      double* d_psi_out, double* d_lam_out);
     int newton_direction64(const double* dR, double* dd, double eta, const hpg_solve_opts& o,

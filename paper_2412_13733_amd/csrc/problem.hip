@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -126,7 +127,7 @@ size_t footprint_bytes(const Mesh& M, int precision) {
     b += 8.0 * 2 * 4096 * 2;              // partial sums, parameters, Krylov scalars
     const double npair = M.ncomp * (M.ncomp + 1) / 2.0;
     const double blk = (double)M.psi_per_cell * (double)M.psi_per_cell;
-    if (M.kind == HPG_GRADIENT) b += 8.0 * nc * (double)M.Qd;        // phi at the Gauss points
+    b += 8.0 * nc * (double)M.Qd;                                   // phi at the Gauss points
     if (precision == HPG_FP64) {
         b += 8.0 * n;                                                  // Krylov solution
         b += 8.0 * (7 * n + 2 * nu);                                   // Krylov work vectors
@@ -505,6 +506,7 @@ void Problem::build(const Mesh& mesh, int dev_) {
     upload(tab64.B1, T.B1);
     upload(tab64.Vpsi, T.Vpsi);
     upload(tab64.Vu, T.Vu);
+    upload(Du64, T.Du);
     upload(tab64.w, T.w);
     upload(tab64.Mdiag, T.MpsiDiag);
     upload(tab32.B1, cast<float>(T.B1));
@@ -655,6 +657,13 @@ void Problem::ensure_fdm() {
 
 // F_i = (f, v_i), Phi_i = (phi, zeta_i) by the Gauss-Legendre rule (sum-factorised)
 void Problem::set_data(const double* f, const double* phi) {
+    // phi at the Gauss points: the gradient constraint's weights and every
+    // solve's feasibility diagnostic read it
+    if (phi) {
+        upload(PhiQ, std::vector<double>(phi, phi + M.n_qp));
+        phi_absmax = 0.0;
+        for (int64_t i = 0; i < M.n_qp; ++i) phi_absmax = std::max(phi_absmax, std::fabs(phi[i]));
+    }
     if (M.hp) return set_data_hp(f, phi);
     const int d = M.d, q = M.q, L = M.p + 1, P = M.P;
     const RefTables& T = M.ref;
@@ -725,7 +734,6 @@ void Problem::set_data(const double* f, const double* phi) {
             for (int comp = 0; comp < M.ncomp; ++comp)
                 for (int64_t a = 0; a < M.Pd; ++a) Ph[(c * M.ncomp + comp) * M.Pd + a] = cur[a];
         }
-        if (gradient) upload(PhiQ, std::vector<double>(phi, phi + M.n_cells * M.Qd));
         double s = 0.0;
         for (double v : Ph) s += v * v;
         normPhi = std::max(std::sqrt(s), 1e-300);
@@ -1221,6 +1229,34 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
     *np2 = b;
 }
 
+// complementarity sums and pointwise violation of an iterate at the Gauss
+// points (launch_diag), reduced on the host in block order (synchronises)
+void Problem::diagnostics(const double* du, const double* dp, const double* dlam, hipStream_t s,
+                          double* cr, double* cr_rel, double* mv) {
+    constexpr int kDiagBlocks = 1024;
+    const int nb = (int)std::min<int64_t>(M.n_cells, kDiagBlocks);
+    if (!diag_part.p) diag_part.alloc((size_t)3 * kDiagBlocks * sizeof(double));
+    double* part = diag_part.as<double>();
+    if (M.hp)
+        dev::launch_hp_diag(hgeo, hp_tabs<double>(), du, dp, dlam, PhiQ.as<double>(), part, nb, s);
+    else
+        dev::launch_diag(geo, tab64.view(), Du64.as<double>(), du, dp, dlam, PhiQ.as<double>(),
+                         part, nb, s);
+    HPG_HIP(hipGetLastError());
+    std::vector<double> h((size_t)3 * nb);
+    HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HPG_HIP(hipStreamSynchronize(s));
+    double c = 0.0, l1 = 0.0, m = -std::numeric_limits<double>::infinity();
+    for (int i = 0; i < nb; ++i) {
+        c += h[3 * i];
+        l1 += h[3 * i + 1];
+        m = std::max(m, h[3 * i + 2]);
+    }
+    *cr = c;
+    *cr_rel = c / std::max(l1 * phi_absmax, 1e-300);
+    *mv = m;
+}
+
 double Problem::l2_diff(const double* a, const double* b, double* norm_a, hipStream_t s) {
     double* part = partial.as<double>();
     int nb;
@@ -1296,15 +1332,35 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
     double* dpt = pt.as<double>();
     double* dR = R.as<double>();
     double* dd = delta64.as<double>();
-    HPG_HIP(hipMemsetAsync(du, 0, M.n_u * sizeof(double), s));
-    HPG_HIP(hipMemsetAsync(dp, 0, M.n_psi * sizeof(double), s));
-    HPG_HIP(hipMemsetAsync(dpp, 0, M.n_psi * sizeof(double), s));
+    const int kmax = o.fixed_prox_steps > 0 ? o.fixed_prox_steps : o.max_prox;
+    if (o.q != 0 && o.q != M.q)
+        fail(HPG_ERR_INVALID_ARG, "only the Gauss rule with q = p + 1 points per direction is built");
+    if ((o.warm_u == nullptr) != (o.warm_psi == nullptr))
+        fail(HPG_ERR_INVALID_ARG, "warm start needs both warm_u and warm_psi");
+    if (o.k0 < 0 || o.k0 >= kmax || (o.k0 > 0 && !o.warm_u))
+        fail(HPG_ERR_INVALID_ARG, "k0 must be 0 without a warm start and below the step cap");
+    // u_0 = psi_0 = 0 (Sec. 2.1), or the state after k0 steps (warm start;
+    // host or device pointers, the copy direction is inferred)
+    if (o.warm_u) {
+        HPG_HIP(hipMemcpyAsync(du, o.warm_u, M.n_u * sizeof(double), hipMemcpyDefault, s));
+        HPG_HIP(hipMemcpyAsync(dp, o.warm_psi, M.n_psi * sizeof(double), hipMemcpyDefault, s));
+        HPG_HIP(hipMemcpyAsync(dpp, o.warm_psi, M.n_psi * sizeof(double), hipMemcpyDefault, s));
+    } else {
+        HPG_HIP(hipMemsetAsync(du, 0, M.n_u * sizeof(double), s));
+        HPG_HIP(hipMemsetAsync(dp, 0, M.n_psi * sizeof(double), s));
+        HPG_HIP(hipMemsetAsync(dpp, 0, M.n_psi * sizeof(double), s));
+    }
     hpg_solve_stats S{};
     S.status = HPG_OK;
+    // alpha_{k0+1}: the schedule's own recurrence, so a resumed solve takes the
+    // same step sizes as the uninterrupted one
     double alpha_k = o.alpha0;
-    int k = 0;
-    const int kmax = o.fixed_prox_steps > 0 ? o.fixed_prox_steps : o.max_prox;
+    for (int i = 0; i < o.k0; ++i) alpha_k = std::min(alpha_k * o.alpha_factor, o.alpha_max);
+    int k = o.k0;
     bool ok = true;
+    int recomputed = 0;   // FP32 directions computed again in FP64 over the solve (mixed)
+    bool have_lam = false;
+    double* dlam = dR;    // lambda of the last step: the residual buffer is free after the loop
     double last_err = 0.0;
     double alpha_used = alpha_k;
     // HPG_TRACE=1: one line per Newton step on stderr (proximal step, Newton
@@ -1328,7 +1384,7 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
             }
             if (it == o.max_newton) break;
             const bool use32 = mixed && fb_step < kMaxFallbacksPerStep &&
-                               S.fp64_fallbacks < kMaxFallbacksPerSolve;
+                               recomputed < kMaxFallbacksPerSolve;
             setup(dp, alpha_k, o.beta, use32 ? HPG_MIXED : HPG_FP64, s);
             // inexact Newton (optional): a linear-solve tolerance proportional
             // to the current error.  MINRES measures the residual in the
@@ -1371,6 +1427,7 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                     S.krylov_iters += its;
                     S.fp64_fallbacks += 1;   // the next Newton step sets up FP32 again
                     ++fb_step;
+                    ++recomputed;
                 }
                 t = 1.0;
                 for (int hv = 0; hv <= 30; ++hv) {
@@ -1424,6 +1481,9 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
                          conv ? "converged" : "NOT converged", last_err);
         if (!conv) {
             ok = false;
+            // the multiplier of the unfinished step, for the diagnostics
+            dev::launch_lambda(M.n_psi, dpp, dp, alpha_k, dlam, s);
+            have_lam = true;
             break;
         }
         // lambda_k and psi_prev <- psi
@@ -1432,17 +1492,24 @@ hpg_status Problem::solve(const hpg_solve_opts& o, hipStream_t s, hpg_solve_stat
         const double diff = l2_diff(du, u_old.as<double>(), &nrm_u, s);
         const bool stop = o.fixed_prox_steps > 0 ? last_possible
                                                  : (diff <= o.prox_tol * nrm_u || last_possible);
-        if (stop && d_lam_out)
-            dev::launch_lambda(M.n_psi, dpp, dp, alpha_k, d_lam_out, s);
+        if (stop) {
+            dev::launch_lambda(M.n_psi, dpp, dp, alpha_k, dlam, s);
+            have_lam = true;
+        }
         HPG_HIP(hipMemcpyAsync(dpp, dp, M.n_psi * sizeof(double), hipMemcpyDeviceToDevice, s));
         if (stop) break;
         alpha_k = std::min(alpha_k * o.alpha_factor, o.alpha_max);
     }
     // outputs
+    if (!have_lam) HPG_HIP(hipMemsetAsync(dlam, 0, M.n_psi * sizeof(double), s));
+    if (d_lam_out)
+        HPG_HIP(hipMemcpyAsync(d_lam_out, dlam, M.n_psi * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (d_u_out) HPG_HIP(hipMemcpyAsync(d_u_out, du, M.n_u * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (d_psi_out)
         HPG_HIP(hipMemcpyAsync(d_psi_out, dp, M.n_psi * sizeof(double), hipMemcpyDeviceToDevice, s));
+    diagnostics(du, dp, dlam, s, &S.complementarity, &S.complementarity_rel, &S.max_violation);
     HPG_HIP(hipStreamSynchronize(s));
+    S.fp64_recomputations = recomputed;
     // keep the internal buffers pointing at the final iterate
     if (du != u.as<double>()) u.swap(ut);
     if (dp != psi.as<double>()) psi.swap(pt);

@@ -437,6 +437,7 @@ size_t footprint_bytes_hp(const Mesh& M, int precision) {
     b += 2.0 * blk * 8.0;                                     // C_K classes and entity inverses (bound)
     b += 16.0 * n + 40.0 * n + 8.0 * 2 * 4096 * 2;
     b += 8.0 * blk;                                           // -S_hat blocks (formed in FP64)
+    b += 8.0 * nq;                                            // phi at the Gauss points
     if (precision == HPG_FP64) {
         b += 8.0 * n + 8.0 * (7 * n + 2 * nu) + 8.0 * nq + 8.0 * loc;
     } else {

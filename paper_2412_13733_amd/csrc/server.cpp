@@ -37,6 +37,7 @@ struct Request {
     uint64_t ticket = 0;
     Mesh mesh;
     std::vector<double> f, phi;
+    std::vector<double> warm_u, warm_psi;   // copies of a warm start's vectors
     hpg_solve_opts opts{};
     size_t footprint = 0;
     Clock::time_point t_submit, t_start, t_done;
@@ -63,6 +64,7 @@ struct Server {
     size_t reserved = 0, peak_reserved = 0;
     int running = 0, max_running = 0;
     bool stop = false;
+    int waiters = 0;   // calls inside hpg_server_poll / hpg_server_wait
 
     int64_t submitted = 0, completed = 0, failed = 0;
     std::vector<double> latencies;
@@ -201,6 +203,16 @@ hpg_status poll_or_wait(hpg_server* srv, uint64_t ticket, double* u_out, double*
         if (!srv) fail(HPG_ERR_INVALID_ARG, "server handle is NULL");
         Server& S = srv->S;
         std::unique_lock<std::mutex> lk(S.mu);
+        // counted while inside, so that hpg_server_destroy frees the server
+        // only after the last caller has left (destructor runs with lk held)
+        struct Inside {
+            Server& S;
+            explicit Inside(Server& s) : S(s) { ++S.waiters; }
+            ~Inside() {
+                --S.waiters;
+                S.cv_done.notify_all();
+            }
+        } inside(S);
         auto it = S.live.find(ticket);
         if (it == S.live.end()) fail(HPG_ERR_INVALID_ARG, "unknown or already retrieved ticket");
         if (block) {
@@ -277,6 +289,12 @@ hpg_status hpg_server_submit(hpg_server* srv, const hpg_mesh* mesh, const double
         auto r = std::make_shared<Request>();
         r->mesh = mesh->M;
         r->opts = checked_opts(opts);
+        if (r->opts.warm_u) {
+            r->warm_u.assign(r->opts.warm_u, r->opts.warm_u + r->mesh.n_u);
+            r->warm_psi.assign(r->opts.warm_psi, r->opts.warm_psi + r->mesh.n_psi);
+            r->opts.warm_u = r->warm_u.data();
+            r->opts.warm_psi = r->warm_psi.data();
+        }
         const size_t nq = (size_t)r->mesh.n_qp;
         r->f.assign(f_qp, f_qp + nq);
         r->phi.assign(phi_qp, phi_qp + nq);
@@ -359,12 +377,28 @@ void hpg_server_destroy(hpg_server* srv) {
     if (!srv) return;
     Server& S = srv->S;
     {
+        // queued requests never run: they complete with an error, which wakes
+        // any caller blocked in hpg_server_wait on them
         std::lock_guard<std::mutex> lk(S.mu);
         S.stop = true;
+        const auto now = Clock::now();
+        for (auto& r : S.queue) {
+            r->state = Request::DONE;
+            r->status = HPG_ERR_INVALID_ARG;
+            r->error = "server destroyed before the request ran";
+            r->t_start = r->t_done = now;
+            ++S.failed;
+        }
         S.queue.clear();
     }
+    S.cv_done.notify_all();
     S.cv_work.notify_all();
     for (auto& t : S.workers) t.join();
+    {
+        // callers already inside poll / wait leave before the server is freed
+        std::unique_lock<std::mutex> lk(S.mu);
+        S.cv_done.wait(lk, [&] { return S.waiters == 0; });
+    }
     delete srv;
 }
 

@@ -16,6 +16,7 @@ OK, NOT_CONVERGED, PENDING = 0, 1, 2
 ERR_INVALID_ARG, ERR_NOMEM, ERR_DEVICE, ERR_NUMERIC, ERR_BUDGET = -1, -2, -3, -4, -5
 OBSTACLE, GRADIENT = 0, 1
 FP64, MIXED = 0, 1
+KRYLOV_MINRES = 0
 
 
 class HpgError(RuntimeError):
@@ -40,7 +41,9 @@ class SolveOpts(ctypes.Structure):
                 ("krylov_rtol", ctypes.c_double), ("max_krylov", ctypes.c_int32),
                 ("beta", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("krylov_chunk", ctypes.c_int32), ("inexact_newton", ctypes.c_int32),
-                ("step_extension", ctypes.c_int32)]
+                ("step_extension", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("krylov", ctypes.c_int32), ("warm_u", ctypes.c_void_p),
+                ("warm_psi", ctypes.c_void_p), ("k0", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -48,7 +51,9 @@ class SolveStats(ctypes.Structure):
                 ("newton_iters", ctypes.c_int32), ("line_search_halvings", ctypes.c_int32),
                 ("krylov_iters", ctypes.c_int64), ("newton_error", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("alpha_last", ctypes.c_double),
-                ("fp64_fallbacks", ctypes.c_int32), ("step_extensions", ctypes.c_int32)]
+                ("fp64_fallbacks", ctypes.c_int32), ("step_extensions", ctypes.c_int32),
+                ("fp64_recomputations", ctypes.c_int32), ("complementarity", ctypes.c_double),
+                ("complementarity_rel", ctypes.c_double), ("max_violation", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -57,7 +62,8 @@ class SolveStats(ctypes.Structure):
 # every symbol include/hpg.h declares (checked by the CPU test-suite)
 EXPORTS = ["hpg_last_error", "hpg_create_mesh", "hpg_destroy_mesh", "hpg_get_mesh_info",
            "hpg_quadrature_points", "hpg_create_problem", "hpg_destroy_problem",
-           "hpg_set_forcing", "hpg_set_obstacle", "hpg_default_opts", "hpg_solve",
+           "hpg_set_forcing", "hpg_set_obstacle", "hpg_set_forcing_fn", "hpg_set_obstacle_fn",
+           "hpg_default_opts", "hpg_solve",
            "hpg_solve_device", "hpg_op_setup", "hpg_op_apply_G", "hpg_op_apply_prec",
            "hpg_op_minres", "hpg_op_residual", "hpg_l2_diff", "hpg_set_kernel_timing",
            "hpg_kernel_time", "hpg_problem_footprint", "hpg_server_create", "hpg_server_submit",
@@ -88,6 +94,9 @@ class ServingStats(ctypes.Structure):
 
 _lib = None
 
+# double (*)(const double* x, void* ctx)
+POINT_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
 
 def load():
     global _lib
@@ -108,6 +117,8 @@ def load():
         "hpg_destroy_problem": ([P], None),
         "hpg_set_forcing": ([P, P, SZ], ctypes.c_int),
         "hpg_set_obstacle": ([P, P, SZ], ctypes.c_int),
+        "hpg_set_forcing_fn": ([P, POINT_FN, P], ctypes.c_int),
+        "hpg_set_obstacle_fn": ([P, POINT_FN, P], ctypes.c_int),
         "hpg_default_opts": ([P], None),
         "hpg_solve": ([P, P, P, P, P, P], ctypes.c_int),
         "hpg_solve_device": ([P, P, P, P, P, P], ctypes.c_int),
@@ -227,15 +238,41 @@ class Problem:
         f = np.ascontiguousarray(phi_qp, dtype=np.float64).reshape(-1)
         _check(load().hpg_set_obstacle(self.h, _dptr(f), f.size))
 
-    def solve(self, opts=None, want_lambda=False):
+    def _point_fn(self, setter, fn):
+        dim = self.mesh.dim
+
+        def cb(x, ctx):
+            return float(fn(np.ctypeslib.as_array(x, shape=(dim,)).copy()))
+
+        c = POINT_FN(cb)
+        _check(setter(self.h, c, None))
+
+    def set_forcing_fn(self, fn):
+        """f from a Python callable of one point (array of dim coordinates),
+        evaluated by the library at every quadrature point."""
+        self._point_fn(load().hpg_set_forcing_fn, fn)
+
+    def set_obstacle_fn(self, fn):
+        self._point_fn(load().hpg_set_obstacle_fn, fn)
+
+    def solve(self, opts=None, want_lambda=False, warm=None):
+        """warm = (u_k0, psi_k0, k0): resume after k0 proximal steps."""
         m = self.mesh
         u = np.zeros(m.n_u)
         psi = np.zeros(m.n_psi)
         lam = np.zeros(m.n_psi) if want_lambda else None
         st = SolveStats()
         o = opts if opts is not None else default_opts()
+        keep = None
+        if warm is not None:
+            wu = np.ascontiguousarray(warm[0], dtype=np.float64)
+            wp = np.ascontiguousarray(warm[1], dtype=np.float64)
+            keep = (wu, wp)
+            o = SolveOpts.from_buffer_copy(o)
+            o.warm_u, o.warm_psi, o.k0 = wu.ctypes.data, wp.ctypes.data, int(warm[2])
         rc = load().hpg_solve(self.h, ctypes.byref(o), _dptr(u), _dptr(psi),
                               _dptr(lam) if lam is not None else None, ctypes.byref(st))
+        del keep
         _check(rc, allow=(OK, NOT_CONVERGED))
         return u, psi, lam, st
 
