@@ -243,6 +243,20 @@ hpg_status hpg_op_minres(hpg_problem* prob, const void* d_b, void* d_x, double r
  * latent iterate psi_prev and step alpha: R (n_u + n_psi, FP64, u first). */
 hpg_status hpg_op_residual(hpg_problem* prob, const double* d_u, const double* d_psi,
                            const double* d_psi_prev, double alpha, double* d_R, void* stream);
+/* hpg_op_residual for callers that cannot allocate memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * kernels and the same R, with their scratch (per-block partial sums and, on
+ * meshes with one degree per cell, the per-local-function values of the cell
+ * pass) in a fixed device array of the library, 8 MiB per device, held until
+ * the process ends; the call allocates no device or host memory.  norms2
+ * (host, may be NULL) receives ||R_u||_2^2 and ||R_psi||_2^2.  Meshes needing
+ * more than 8192 partial sums or 1040384 local values: HPG_ERR_INVALID_ARG.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (several host threads or streams) race and must be serialised
+ * by the caller.  Returns after `stream` has finished the call's work. */
+hpg_status hpg_op_residual_noalloc(hpg_problem* prob, const double* d_u, const double* d_psi,
+                                   const double* d_psi_prev, double alpha, double* d_R,
+                                   double* norms2, void* stream);
 
 /* L2 norms in function space (Gauss-Legendre, exact for degree 2p):
  * *diff = ||a_h - b_h||_{L2(Omega)}, *norm_b = ||b_h||_{L2(Omega)} for u

@@ -15,8 +15,8 @@ LIB = os.path.join(HERE, "libhpg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["tables.cpp", "kernels.hip", "tile.hip", "tile_d1.hip", "tile_d2.hip", "tile_d3.hip",
-           "gradient.hip", "hp.hip", "diag.hip", "problem.hip", "problem_hp.cpp", "hp_host.cpp", "api.cpp",
-           "server.cpp"]
+           "gradient.hip", "hp.hip", "diag.hip", "problem.hip", "problem_hp.cpp", "hp_host.cpp",
+           "api.cpp", "noalloc.hip", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # the compiler's packed two-wide FP32 arithmetic is disabled for all device

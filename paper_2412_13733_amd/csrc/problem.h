@@ -205,9 +205,20 @@ struct Problem {
                            T* Gq, T* z, T* x, hipStream_t s);
     void fork(hipStream_t s);
     void join(hipStream_t s);
-    // residual into R; returns (||R_u||^2, ||R_psi||^2) (synchronises)
+    // residual into R; returns (||R_u||^2, ||R_psi||^2) (synchronises).  With sc
+    // the partial sums (residual_partials() values), the per-local-function
+    // values of a per-cell-degree mesh (residual_local_values()) and the host
+    // copy of the partials use the caller's memory and nothing is allocated.
+    struct ResScratch {
+        double* part;   // device
+        double* yloc;   // device (per-cell degrees only)
+        double* host;   // host
+    };
     void residual(const double* u, const double* psi, const double* psi_prev, double alpha,
-                  double* R, hipStream_t s, double* nu2, double* np2);
+                  double* R, hipStream_t s, double* nu2, double* np2,
+                  const ResScratch* sc = nullptr);
+    int residual_partials() const;
+    int64_t residual_local_values() const;
     double l2_diff(const double* a, const double* b, double* norm_a, hipStream_t s);
     void diagnostics(const double* u, const double* psi, const double* lam, hipStream_t s,
                      double* cr, double* cr_rel, double* mv);

@@ -1172,11 +1172,28 @@ int Problem::minres_on(const T* b, T* x, double rtol, int maxit, int chunk, hipS
     return hs.iters;
 }
 
+int Problem::residual_partials() const {
+    if (use_tile) return 2 * dev::tile_grid(geo);
+    return np_u + np_psi;
+}
+
+int64_t Problem::residual_local_values() const {
+    return M.hp ? (int64_t)hph.loc_off.back() : 0;
+}
+
 void Problem::residual(const double* uu, const double* pp, const double* pprev, double alpha_,
-                       double* RR, hipStream_t s, double* nu2, double* np2) {
+                       double* RR, hipStream_t s, double* nu2, double* np2, const ResScratch* sc) {
     if (!have_f || !have_phi) fail(HPG_ERR_INVALID_ARG, "forcing and obstacle must be set");
     dev::URows<double> r[3] = {rows64[0].view(), rows64[1].view(), rows64[2].view()};
-    double* part = partial.as<double>();
+    double* part = sc ? sc->part : partial.as<double>();
+    // host copy of the partial sums: the caller's buffer, else a vector
+    const int npart = residual_partials();
+    std::vector<double> hv;
+    double* h = sc ? sc->host : nullptr;
+    if (!h) {
+        hv.resize(npart);
+        h = hv.data();
+    }
     tstart("residual", s);
     double a = 0.0, b = 0.0;
     if (use_tile) {
@@ -1185,9 +1202,8 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
                                  dev::MODE_RES, s);
         tstop("residual", s);
         HPG_HIP(hipGetLastError());
-        const int nb = dev::tile_grid(geo);
-        std::vector<double> h(2 * nb);
-        HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        const int nb = npart / 2;
+        HPG_HIP(hipMemcpyAsync(h, part, npart * sizeof(double), hipMemcpyDeviceToHost, s));
         HPG_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < nb; ++i) {
             a += h[2 * i];
@@ -1195,15 +1211,17 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
         }
     } else {
         if (M.hp) {
-            if (!hpd.yloc64.p) hpd.yloc64.alloc((size_t)hph.loc_off.back() * sizeof(double));
+            double* yloc = sc ? sc->yloc : nullptr;
+            if (!yloc) {
+                if (!hpd.yloc64.p) hpd.yloc64.alloc((size_t)hph.loc_off.back() * sizeof(double));
+                yloc = hpd.yloc64.as<double>();
+            }
             dev::launch_hp_cell<double>(hgeo, hp_tabs<double>(), alpha_, 0.0, nullptr, uu, pp,
-                                        pprev, nullptr, Phi.as<double>(), hpd.yloc64.as<double>(),
-                                        RR + M.n_u, part + np_u, np_cell, nullptr, dev::MODE_RES,
-                                        s);
+                                        pprev, nullptr, Phi.as<double>(), yloc, RR + M.n_u,
+                                        part + np_u, np_cell, nullptr, dev::MODE_RES, s);
             dev::launch_hp_gather<double>(M.n_u, hpd.inc_ptr.as<int32_t>(),
-                                          hpd.inc_idx.as<int32_t>(), hpd.yloc64.as<double>(),
-                                          F.as<double>(), alpha_, uu, RR, part, np_gath, nullptr,
-                                          dev::MODE_RES, s);
+                                          hpd.inc_idx.as<int32_t>(), yloc, F.as<double>(), alpha_,
+                                          uu, RR, part, np_gath, nullptr, dev::MODE_RES, s);
         } else if (gradient) {
             dev::launch_u_side_grad<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR,
                                             part, nullptr, dev::MODE_RES, s, nullptr);
@@ -1219,8 +1237,7 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
         }
         tstop("residual", s);
         HPG_HIP(hipGetLastError());
-        std::vector<double> h(np_u + np_psi);
-        HPG_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HPG_HIP(hipMemcpyAsync(h, part, npart * sizeof(double), hipMemcpyDeviceToHost, s));
         HPG_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < np_u; ++i) a += h[i];
         for (int i = 0; i < np_psi; ++i) b += h[np_u + i];

@@ -65,7 +65,7 @@ EXPORTS = ["hpg_last_error", "hpg_create_mesh", "hpg_destroy_mesh", "hpg_get_mes
            "hpg_set_forcing", "hpg_set_obstacle", "hpg_set_forcing_fn", "hpg_set_obstacle_fn",
            "hpg_default_opts", "hpg_solve",
            "hpg_solve_device", "hpg_op_setup", "hpg_op_apply_G", "hpg_op_apply_prec",
-           "hpg_op_minres", "hpg_op_residual", "hpg_l2_diff", "hpg_set_kernel_timing",
+           "hpg_op_minres", "hpg_op_residual", "hpg_op_residual_noalloc", "hpg_l2_diff", "hpg_set_kernel_timing",
            "hpg_kernel_time", "hpg_problem_footprint", "hpg_server_create", "hpg_server_submit",
            "hpg_server_poll", "hpg_server_wait", "hpg_server_stats", "hpg_server_destroy"]
 
@@ -127,6 +127,7 @@ def load():
         "hpg_op_apply_prec": ([P, P, P, P], ctypes.c_int),
         "hpg_op_minres": ([P, P, P, D, I32, P, P], ctypes.c_int),
         "hpg_op_residual": ([P, P, P, P, D, P, P], ctypes.c_int),
+        "hpg_op_residual_noalloc": ([P, P, P, P, D, P, P, P], ctypes.c_int),
         "hpg_l2_diff": ([P, P, P, P, P, P], ctypes.c_int),
         "hpg_set_kernel_timing": ([P, ctypes.c_char_p], ctypes.c_int),
         "hpg_kernel_time": ([P, ctypes.c_char_p, P, P], ctypes.c_int),
@@ -306,6 +307,14 @@ class Problem:
     def op_residual(self, u, psi, psi_prev, alpha, R, stream=None):
         _check(load().hpg_op_residual(self.h, _tptr(u), _tptr(psi), _tptr(psi_prev), alpha,
                                       _tptr(R), ctypes.c_void_p(stream) if stream else None))
+
+    def op_residual_noalloc(self, u, psi, psi_prev, alpha, R, stream=None):
+        """hpg_op_residual without allocation; returns (||R_u||^2, ||R_psi||^2)."""
+        n2 = np.zeros(2)
+        _check(load().hpg_op_residual_noalloc(self.h, _tptr(u), _tptr(psi), _tptr(psi_prev),
+                                              alpha, _tptr(R), _dptr(n2),
+                                              ctypes.c_void_p(stream) if stream else None))
+        return float(n2[0]), float(n2[1])
 
     def l2_diff(self, a, b, stream=None):
         """(||a_h - b_h||_L2, ||b_h||_L2) for device u vectors a, b."""
