@@ -278,6 +278,44 @@ hpg_status hpg_set_kernel_timing(hpg_problem* prob, const char* group);
 hpg_status hpg_kernel_time(hpg_problem* prob, const char* group, int64_t* launches,
                            double* total_ms);
 
+/* ---- batched solves: many problems of one mesh shape in each launch -------
+ * nbatch independent problems on the same mesh (the same breakpoints, degree
+ * p and obstacle constraint; the Sec. 2 problem with its own f and phi each)
+ * solved together: each step of the inner Newton solve (Sec. 4: the G apply
+ * of eq. (pG-matrix), the preconditioner P_D of eq. (schur4), the Lanczos
+ * updates, the Newton residual, the linearisation) is one launch over all
+ * requests, with per-request reductions in the order of a solve of that
+ * request alone, and per-request Newton and proximal decisions, so a request's
+ * result does not depend on the rest of the batch.  Supported: obstacle
+ * constraint, one degree on every cell, p <= 12 in 1-D/2-D and p <= 7 in 3-D
+ * (the fused tiled apply) with Schur blocks of at most 48 KB
+ * (HPG_ERR_INVALID_ARG otherwise).  Arrays are request-major: request b's f
+ * and phi are values [b n_qp, (b+1) n_qp), its u [b n_u, (b+1) n_u), its psi and
+ * lambda [b n_psi, (b+1) n_psi).
+ * hpg_batch_solve: options as for hpg_solve (step_extension, inexact_newton
+ *   and warm starts: HPG_ERR_INVALID_ARG); stats[nbatch] per request; returns
+ *   HPG_OK if every request converged, else HPG_NOT_CONVERGED (outputs
+ *   written for all).  Every request's outer loop stops by its own test.
+ * hpg_batch_op_setup / hpg_batch_op_apply_G: the linearisation and G of all
+ *   requests at once (device psi[nbatch n_psi], x and y [nbatch (n_u + n_psi)],
+ *   request b's vector at offset b (n_u + n_psi), u first; float vectors for
+ *   HPG_MIXED).
+ * hpg_batch_set_kernel_timing / hpg_batch_kernel_time: as the hpg_problem
+ *   forms, for the batch's launches. */
+typedef struct hpg_batch hpg_batch;
+hpg_status hpg_create_batch(const hpg_mesh* mesh, int32_t nbatch, int device, hpg_batch** out);
+void hpg_destroy_batch(hpg_batch* batch);
+hpg_status hpg_batch_set_data(hpg_batch* batch, const double* f_qp, const double* phi_qp,
+                              size_t n_values);
+hpg_status hpg_batch_solve(hpg_batch* batch, const hpg_solve_opts* opts, double* u_out,
+                           double* psi_out, double* lam_out, hpg_solve_stats* stats);
+hpg_status hpg_batch_op_setup(hpg_batch* batch, const double* d_psi, double alpha, double beta,
+                              int32_t precision, void* stream);
+hpg_status hpg_batch_op_apply_G(hpg_batch* batch, const void* d_x, void* d_y, void* stream);
+hpg_status hpg_batch_set_kernel_timing(hpg_batch* batch, const char* group);
+hpg_status hpg_batch_kernel_time(hpg_batch* batch, const char* group, int64_t* launches,
+                                 double* total_ms);
+
 /* ---- serving: continuous batching of independent solves on one GPU --------
  * A request is one whole LVPP solve (the problem statement of Sec. 2 on its
  * own mesh, degree and constraint).  The server admits requests in arrival

@@ -16,7 +16,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["tables.cpp", "kernels.hip", "tile.hip", "tile_d1.hip", "tile_d2.hip", "tile_d3.hip",
            "gradient.hip", "hp.hip", "diag.hip", "problem.hip", "problem_hp.cpp", "hp_host.cpp",
-           "api.cpp", "noalloc.hip", "server.cpp"]
+           "api.cpp", "noalloc.hip", "server.cpp", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # the compiler's packed two-wide FP32 arithmetic is disabled for all device

@@ -107,9 +107,17 @@ __global__ __launch_bounds__(256) void k_diag(Geo g, PsiTabs<double> tb,
                                               const double* __restrict__ psi,
                                               const double* __restrict__ lam,
                                               const double* __restrict__ phiq,
-                                              double* __restrict__ partial) {
+                                              double* __restrict__ partial, DiagBatch bt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
+    {
+        const int64_t rb = blockIdx.y;
+        u += rb * bt.u;
+        psi += rb * bt.psi;
+        lam += rb * bt.psi;
+        phiq += rb * bt.qp;
+        partial += rb * 3 * (int64_t)gridDim.x;
+    }
     double* su = reinterpret_cast<double*>(smem_raw);   // Ld
     double* sp = su + g.Ld;                             // Pd (obstacle)
     double* sl = sp + g.Pd;                             // Pd
@@ -181,12 +189,13 @@ size_t diag_lds(const Geo& g) { return (size_t)(g.Ld + 2 * g.Pd) * sizeof(double
 
 void launch_diag(const Geo& g, const PsiTabs<double>& tb, const double* Du, const double* u,
                  const double* psi, const double* lam, const double* phiq, double* partial,
-                 int nblocks, hipStream_t s) {
+                 int nblocks, hipStream_t s, const DiagBatch& bt) {
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g.n_cells, nblocks));
     const size_t shm = diag_lds(g);
     const bool grad = g.nc > 1 || g.P == g.p;   // gradient constraint: P = p modes
-#define HPG_DIAG(DD, GG) \
-    hipLaunchKernelGGL((k_diag<DD, GG>), dim3(grid), dim3(256), shm, s, g, tb, Du, u, psi, lam, phiq, partial)
+#define HPG_DIAG(DD, GG)                                                                      \
+    hipLaunchKernelGGL((k_diag<DD, GG>), dim3(grid, (unsigned)bt.nb), dim3(256), shm, s, g, tb, \
+                       Du, u, psi, lam, phiq, partial, bt)
     if (grad) {
         if (g.d == 1) HPG_DIAG(1, true);
         else if (g.d == 2) HPG_DIAG(2, true);

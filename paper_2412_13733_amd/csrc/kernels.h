@@ -66,6 +66,24 @@ struct KernelEvents {
     hipEvent_t stop = nullptr;
 };
 
+// Batches of independent problems on one mesh: a launch covers nb requests,
+// request b = blockIdx.y (blockIdx.z for the GEMM passes), and every pointer a
+// kernel takes is offset by b times its stride below (0: shared).  Partial
+// sums and done flags are per request, so each request's reductions run in
+// the same fixed order as when it is solved alone.
+struct TileBatch {
+    int nb = 1;
+    int64_t xu = 0, xp = 0, pprev = 0, om = 0, F = 0, Phi = 0, yu = 0, yp = 0, part = 0, done = 0;
+};
+struct PsiBatch {
+    int nb = 1;
+    int64_t sinv = 0, r = 0, z = 0, part = 0, done = 0;
+};
+struct VecBatch {
+    int nb = 1;
+    int64_t v = 0, part = 0;   // vector stride, partial-sum stride (the state: st + b)
+};
+
 // MINRES scalar state (device)
 struct KState {
     double gamma1, gamma, delta;
@@ -94,7 +112,8 @@ template <typename T>
 bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                  const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
                  const double* F, const double* Phi, T* yu, T* ypsi, double* partial,
-                 const int* done, int mode, hipStream_t s, const KernelEvents* ev = nullptr);
+                 const int* done, int mode, hipStream_t s, const KernelEvents* ev = nullptr,
+                 const TileBatch& bt = TileBatch());
 // Obstacle setup: LDS bytes per cell with the block in LDS; and of the
 // variants that form and invert the block in s64 (global memory), with or
 // without (d = 3) the q P^4 contraction intermediate in LDS.
@@ -106,7 +125,8 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, con
                   float* om32, double* s64, float* s32, hipStream_t s);
 template <typename T>
 void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
-                     double* partial, const int* done, hipStream_t s);
+                     double* partial, const int* done, hipStream_t s,
+                     const PsiBatch& bt = PsiBatch());
 // C_b = A_b B_b (row-major, M x K times K x N), batch strides sA, sB, sC,
 // with the optional epilogues of GemmEpi
 template <typename T>
@@ -119,6 +139,11 @@ struct GemmEpi {
     const double* prm;
     const T* dotv;
     double* partial;
+    // batches of requests: the GEMM batch bz belongs to request bz / bdiv, whose
+    // done flag is done[request * dstride] and whose partial sums start at
+    // partial[request * pstride] (pstride 0: one index over all batches)
+    int bdiv;
+    int64_t pstride, dstride;
 };
 template <typename T>
 void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,
@@ -130,21 +155,23 @@ void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const
 template <typename T>
 void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
                       int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
-                      int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s);
+                      int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s,
+                      int64_t sA = 0, int64_t sC = 0, const PsiBatch& bt = PsiBatch());
 template <typename T>
 void launch_dot(int64_t n, const T* a, const T* b, double* partial, int nblocks, const int* done,
                 hipStream_t s);
 template <typename T>
 void launch_kr_start(int64_t n, KState* st0, const double* partial, int np, double rtol,
                      int maxit, const T* b, const T* z, T* vcur, T* vprev, T* q, T* wprev,
-                     T* wcur, T* x, hipStream_t s);
+                     T* wcur, T* x, hipStream_t s, const VecBatch& bt = VecBatch());
 template <typename T>
 void launch_kr_vhat(int64_t n, KState* st, const double* partial, int np, const T* Gq,
-                    const T* vcur, const T* vprev, T* vhat, hipStream_t s);
+                    const T* vcur, const T* vprev, T* vhat, hipStream_t s,
+                    const VecBatch& bt = VecBatch());
 template <typename T>
 void launch_kr_update(int64_t n, const KState* st_in, KState* st_out, const double* partial,
                       int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* vhat,
-                      const T* z, hipStream_t s);
+                      const T* z, hipStream_t s, const VecBatch& bt = VecBatch());
 // launch_gemm_prec with the Lanczos step folded in: every block reduces the
 // G-apply partials gpart (npg) to delta = <q, Gq> (stored in st), and the
 // first pass (A = vhat, R x N with lda N, B = V, C) and the psi-block read
@@ -162,16 +189,22 @@ void launch_axpy_to(int64_t n, const double* x, double t, const T* d, double* y,
 void launch_lambda(int64_t n, const double* psi_prev, const double* psi, double alpha,
                    double* lam, hipStream_t s);
 void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u, const double* v,
-               double* partial, hipStream_t s);
+               double* partial, hipStream_t s, const VecBatch& bt = VecBatch());
 // Diagnostics of an iterate (diag.hip): per block b, partial[3 b] = sum w |J|
 // |lambda_h| exp(-psi_h), partial[3 b + 1] = sum w |J| |lambda_h| (obstacle;
 // 0 for the gradient constraint), partial[3 b + 2] = max over the block's
 // Gauss points of u_h - phi (obstacle) or |grad u_h| - phi (gradient).  Du:
 // q x (p+1) reference derivative table; phiq: phi at the Gauss points.
 // At most nblocks blocks (one cell at a time each).
+// Batched: request b = blockIdx.y reads u + b u_stride, psi and lam + b
+// psi_stride, phiq + b qp_stride and writes partial + 3 nblocks b.
+struct DiagBatch {
+    int nb = 1;
+    int64_t u = 0, psi = 0, qp = 0;
+};
 void launch_diag(const Geo& g, const PsiTabs<double>& tb, const double* Du, const double* u,
                  const double* psi, const double* lam, const double* phiq, double* partial,
-                 int nblocks, hipStream_t s);
+                 int nblocks, hipStream_t s, const DiagBatch& bt = DiagBatch());
 
 // ---- gradient constraint |grad u| <= phi (gradient.hip) ---------------------
 // omega layout: [cell][pair (c <= l, row-major upper triangle)][q^d] of the

@@ -571,11 +571,13 @@ __global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cp
                                                   const T* __restrict__ sinv,
                                                   const T* __restrict__ r, T* __restrict__ z,
                                                   double* __restrict__ partial,
-                                                  const int* __restrict__ done) {
+                                                  const int* __restrict__ done, PsiBatch bt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
-    prec_psi_body<T>(blockIdx.x, gridDim.x, n_cells, n, cpb, sinv, r, z, partial, done,
-                     reinterpret_cast<T*>(smem_raw), red);
+    const int64_t rb = blockIdx.y;
+    prec_psi_body<T>(blockIdx.x, gridDim.x, n_cells, n, cpb, sinv + rb * bt.sinv, r + rb * bt.r,
+                     z + rb * bt.z, partial ? partial + rb * bt.part : nullptr,
+                     done ? done + rb * bt.done : nullptr, reinterpret_cast<T*>(smem_raw), red);
 }
 
 // ---------------------------------------------------------------------------
@@ -620,6 +622,10 @@ __device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int 
                                       const int* __restrict__ done, const GemmEpi<T>& ep,
                                       T (*red)[256], double* rsum,
                                       const VhatSrc<T>* vs = nullptr) {
+    // batched requests: batch bz belongs to request bz / bdiv
+    const int64_t rq = ep.bdiv > 0 ? bz / ep.bdiv : 0;
+    if (done) done += rq * ep.dstride;
+    if (ep.pstride) pidx = rq * ep.pstride + (pidx - (int64_t)bz * ((M + 15) / 16) * ((N + 15) / 16));
     if (done && *done) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t b = bz;
@@ -757,18 +763,23 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
                                                    int gx, int gy, int64_t n_cells, int n, int cpb,
                                                    const T* __restrict__ sinv,
                                                    const T* __restrict__ r, T* __restrict__ z,
-                                                   double* __restrict__ ppart) {
+                                                   double* __restrict__ ppart, int64_t sA,
+                                                   int64_t sC, PsiBatch bt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ T red[4][256];
     __shared__ double rsum[4];
     const int ng = gx * gy;
+    const int64_t rb = blockIdx.y;   // request of a batched launch
     if ((int)blockIdx.x < ng) {
         const int bx = blockIdx.x % gx, by = blockIdx.x / gx;
-        gemm_tile_body<T>(bx, by, 0, bx + (int64_t)gx * by, M, N, K, A, lda, 0, B, ldb, 0, C, ldc,
-                          0, done, ep, red, rsum);
+        gemm_tile_body<T>(bx, by, 0, bx + (int64_t)gx * by, M, N, K, A + rb * sA, lda, 0, B, ldb,
+                          0, C + rb * sC, ldc, 0, done ? done + rb * bt.done : nullptr, ep, red,
+                          rsum);
     } else {
-        prec_psi_body<T>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv, r, z, ppart,
-                         done, reinterpret_cast<T*>(smem_raw), rsum);
+        prec_psi_body<T>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv + rb * bt.sinv,
+                         r + rb * bt.r, z + rb * bt.z, ppart ? ppart + rb * bt.part : nullptr,
+                         done ? done + rb * bt.done : nullptr, reinterpret_cast<T*>(smem_raw),
+                         rsum);
     }
 }
 
@@ -789,9 +800,22 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_kr_start(int64_t n, KState* st0, const double* partial,
                                                   int np, double rtol, int maxit, const T* b,
                                                   const T* z, T* vcur, T* vprev, T* q, T* wprev,
-                                                  T* wcur, T* x) {
+                                                  T* wcur, T* x, VecBatch bt) {
     __shared__ double red[4];
     __shared__ double bc;
+    {
+        const int64_t rb = blockIdx.y, o = rb * bt.v;
+        st0 += rb;
+        partial += rb * bt.part;
+        b += o;
+        z += o;
+        vcur += o;
+        vprev += o;
+        q += o;
+        wprev += o;
+        wcur += o;
+        x += o;
+    }
     const double g2 = reduce_partials(partial, np, red, &bc);
     const double g1 = sqrt(g2 > 0.0 ? g2 : 0.0);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -825,9 +849,18 @@ __global__ __launch_bounds__(256) void k_kr_start(int64_t n, KState* st0, const 
 template <typename T>
 __global__ __launch_bounds__(256) void k_kr_vhat(int64_t n, KState* st, const double* partial,
                                                  int np, const T* Gq, const T* vcur,
-                                                 const T* vprev, T* vhat) {
+                                                 const T* vprev, T* vhat, VecBatch bt) {
     __shared__ double red[4];
     __shared__ double bc;
+    {
+        const int64_t rb = blockIdx.y, o = rb * bt.v;
+        st += rb;
+        partial += rb * bt.part;
+        Gq += o;
+        vcur += o;
+        vprev += o;
+        vhat += o;
+    }
     if (st->done) return;
     const double delta = reduce_partials(partial, np, red, &bc);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->delta = delta;
@@ -844,10 +877,23 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_kr_update(int64_t n, const KState* st_in, KState* st_out,
                                                    const double* partial, int np, T* q, T* wprev,
                                                    const T* wcur, T* x, T* vprev, const T* vhat,
-                                                   const T* z) {
+                                                   const T* z, VecBatch bt) {
     __shared__ double red[4];
     __shared__ double bc;
     __shared__ double sc[6];   // a1, a2, a3, step, 1/gamma_new, skip
+    {
+        const int64_t rb = blockIdx.y, o = rb * bt.v;
+        st_in += rb;
+        st_out += rb;
+        partial += rb * bt.part;
+        q += o;
+        wprev += o;
+        wcur += o;
+        x += o;
+        vprev += o;
+        vhat += o;
+        z += o;
+    }
     if (st_in->done) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *st_out = *st_in;
         return;
@@ -949,9 +995,12 @@ template <int D>
 __global__ __launch_bounds__(256) void k_l2(Geo g, PsiTabs<double> tb, int cpb,
                                             const double* __restrict__ u,
                                             const double* __restrict__ v,
-                                            double* __restrict__ partial) {
+                                            double* __restrict__ partial, VecBatch bt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
+    u += (int64_t)blockIdx.y * bt.v;
+    v += (int64_t)blockIdx.y * bt.v;
+    partial += (int64_t)blockIdx.y * bt.part;
     double* sm = reinterpret_cast<double*>(smem_raw);
     const int S = g.S;
     double* a = sm;
@@ -1075,11 +1124,11 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, con
 
 template <typename T>
 void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
-                     double* partial, const int* done, hipStream_t s) {
+                     double* partial, const int* done, hipStream_t s, const PsiBatch& bt) {
     const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
     const unsigned grid = (unsigned)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
-    hipLaunchKernelGGL((k_prec_psi<T>), dim3(grid), dim3(256), shm, s, n_cells, n,
-                       cpb, sinv, r, z, partial, done);
+    hipLaunchKernelGGL((k_prec_psi<T>), dim3(grid, (unsigned)bt.nb), dim3(256), shm, s, n_cells,
+                       n, cpb, sinv, r, z, partial, done, bt);
 }
 
 template <typename T>
@@ -1098,12 +1147,14 @@ void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const
 template <typename T>
 void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
                       int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
-                      int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s) {
+                      int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s,
+                      int64_t sA, int64_t sC, const PsiBatch& bt) {
     const int gx = (N + 15) / 16, gy = (M + 15) / 16;
     const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
     const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
-    hipLaunchKernelGGL((k_gemm_prec<T>), dim3(gx * gy + np), dim3(256), shm, s, M, N, K, A, lda, B,
-                       ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb, sinv, r, z, ppart);
+    hipLaunchKernelGGL((k_gemm_prec<T>), dim3(gx * gy + np, (unsigned)bt.nb), dim3(256), shm, s,
+                       M, N, K, A, lda, B, ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb, sinv, r,
+                       z, ppart, sA, sC, bt);
 }
 
 template <typename T>
@@ -1131,22 +1182,22 @@ static inline unsigned vec_grid(int64_t n) {
 template <typename T>
 void launch_kr_start(int64_t n, KState* st0, const double* partial, int np, double rtol,
                      int maxit, const T* b, const T* z, T* vcur, T* vprev, T* q, T* wprev,
-                     T* wcur, T* x, hipStream_t s) {
-    hipLaunchKernelGGL((k_kr_start<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st0, partial, np,
-                       rtol, maxit, b, z, vcur, vprev, q, wprev, wcur, x);
+                     T* wcur, T* x, hipStream_t s, const VecBatch& bt) {
+    hipLaunchKernelGGL((k_kr_start<T>), dim3(vec_grid(n), (unsigned)bt.nb), dim3(256), 0, s, n,
+                       st0, partial, np, rtol, maxit, b, z, vcur, vprev, q, wprev, wcur, x, bt);
 }
 template <typename T>
 void launch_kr_vhat(int64_t n, KState* st, const double* partial, int np, const T* Gq,
-                    const T* vcur, const T* vprev, T* vhat, hipStream_t s) {
-    hipLaunchKernelGGL((k_kr_vhat<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st, partial, np, Gq,
-                       vcur, vprev, vhat);
+                    const T* vcur, const T* vprev, T* vhat, hipStream_t s, const VecBatch& bt) {
+    hipLaunchKernelGGL((k_kr_vhat<T>), dim3(vec_grid(n), (unsigned)bt.nb), dim3(256), 0, s, n, st,
+                       partial, np, Gq, vcur, vprev, vhat, bt);
 }
 template <typename T>
 void launch_kr_update(int64_t n, const KState* st_in, KState* st_out, const double* partial,
                       int np, T* q, T* wprev, const T* wcur, T* x, T* vprev, const T* vhat,
-                      const T* z, hipStream_t s) {
-    hipLaunchKernelGGL((k_kr_update<T>), dim3(vec_grid(n)), dim3(256), 0, s, n, st_in, st_out,
-                       partial, np, q, wprev, wcur, x, vprev, vhat, z);
+                      const T* z, hipStream_t s, const VecBatch& bt) {
+    hipLaunchKernelGGL((k_kr_update<T>), dim3(vec_grid(n), (unsigned)bt.nb), dim3(256), 0, s, n,
+                       st_in, st_out, partial, np, q, wprev, wcur, x, vprev, vhat, z, bt);
 }
 template <typename TI, typename TO>
 void launch_convert(int64_t n, const TI* a, TO* b, double scale, hipStream_t s) {
@@ -1161,15 +1212,15 @@ void launch_lambda(int64_t n, const double* psi_prev, const double* psi, double 
     hipLaunchKernelGGL(k_lambda, dim3(nblk(n)), dim3(256), 0, s, n, psi_prev, psi, alpha, lam);
 }
 void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u, const double* v,
-               double* partial, hipStream_t s) {
-    dim3 grid(nblk(g.n_cells, cpb));
+               double* partial, hipStream_t s, const VecBatch& bt) {
+    dim3 grid(nblk(g.n_cells, cpb), (unsigned)bt.nb);
     size_t shm = (size_t)4 * cpb * g.S * sizeof(double);
     if (g.d == 1)
-        hipLaunchKernelGGL((k_l2<1>), grid, dim3(256), shm, s, g, tb, cpb, u, v, partial);
+        hipLaunchKernelGGL((k_l2<1>), grid, dim3(256), shm, s, g, tb, cpb, u, v, partial, bt);
     else if (g.d == 2)
-        hipLaunchKernelGGL((k_l2<2>), grid, dim3(256), shm, s, g, tb, cpb, u, v, partial);
+        hipLaunchKernelGGL((k_l2<2>), grid, dim3(256), shm, s, g, tb, cpb, u, v, partial, bt);
     else
-        hipLaunchKernelGGL((k_l2<3>), grid, dim3(256), shm, s, g, tb, cpb, u, v, partial);
+        hipLaunchKernelGGL((k_l2<3>), grid, dim3(256), shm, s, g, tb, cpb, u, v, partial, bt);
 }
 
 #define HPG_INST(T)                                                                              \
@@ -1180,19 +1231,22 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
                                      const T*, const double*, T*, double*, const int*, int,     \
                                      hipStream_t, const double*);                                \
     template void launch_prec_psi<T>(int64_t, int, int, const T*, const T*, T*, double*,         \
-                                     const int*, hipStream_t);                                   \
+                                     const int*, hipStream_t, const PsiBatch&);                  \
     template void launch_gemm<T>(int, int, int, const T*, int64_t, int64_t, const T*, int64_t,    \
                                  int64_t, T*, int64_t, int64_t, int, const int*,                 \
                                  const GemmEpi<T>&, hipStream_t, const KernelEvents*);           \
     template void launch_gemm_prec<T>(int, int, int, const T*, int64_t, const T*, int64_t, T*,   \
                                       int64_t, const int*, const GemmEpi<T>&, int64_t, int, int,  \
-                                      const T*, const T*, T*, double*, hipStream_t);             \
+                                      const T*, const T*, T*, double*, hipStream_t, int64_t,     \
+                                      int64_t, const PsiBatch&);                                 \
     template void launch_kr_start<T>(int64_t, KState*, const double*, int, double, int, const T*, \
-                                     const T*, T*, T*, T*, T*, T*, T*, hipStream_t);             \
+                                     const T*, T*, T*, T*, T*, T*, T*, hipStream_t,              \
+                                     const VecBatch&);                                           \
     template void launch_kr_vhat<T>(int64_t, KState*, const double*, int, const T*, const T*,   \
-                                    const T*, T*, hipStream_t);                                  \
+                                    const T*, T*, hipStream_t, const VecBatch&);                 \
     template void launch_kr_update<T>(int64_t, const KState*, KState*, const double*, int, T*, T*, \
-                                      const T*, T*, T*, const T*, const T*, hipStream_t);        \
+                                      const T*, T*, T*, const T*, const T*, hipStream_t,         \
+                                      const VecBatch&);                                          \
     template void launch_vhat_gemm_prec<T>(int, int, const T*, T*, const GemmEpi<T>&, int64_t,   \
                                            int, int, const T*, T*, double*, KState*,             \
                                            const double*, int, const T*, const T*, const T*, T*, \

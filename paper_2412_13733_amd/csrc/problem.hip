@@ -204,6 +204,11 @@ dev::PsiTabs<T> DevTabs<T>::view() const {
     return t;
 }
 
+template struct DevRows<double>;
+template struct DevRows<float>;
+template struct DevTabs<double>;
+template struct DevTabs<float>;
+
 template <typename T>
 void KrylovWork<T>::ensure(int64_t n_, int64_t n_u) {
     if (n >= n_) return;

@@ -42,17 +42,19 @@ template <typename T, int D, int MODE>
 bool launch_tile_d(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                    const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev,
                    const T* omega, const double* F, const double* Phi, T* yu, T* ypsi,
-                   double* partial, const int* done, hipStream_t s, const KernelEvents* ev);
+                   double* partial, const int* done, hipStream_t s, const KernelEvents* ev,
+                   const TileBatch& bt);
 
 template <typename T>
 bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                  const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
                  const double* F, const double* Phi, T* yu, T* ypsi, double* partial,
-                 const int* done, int mode, hipStream_t s, const KernelEvents* ev) {
+                 const int* done, int mode, hipStream_t s, const KernelEvents* ev,
+                 const TileBatch& bt) {
     if (!tile_supported(g)) return false;
 #define HPG_TD(DD, MM)                                                                        \
     return launch_tile_d<T, DD, MM>(g, r, tb, alpha, beta, prm, xu, xpsi, xpsi_prev, omega, F, \
-                                    Phi, yu, ypsi, partial, done, s, ev)
+                                    Phi, yu, ypsi, partial, done, s, ev, bt)
     if (mode == MODE_APPLY) {
         if (g.d == 1) HPG_TD(1, MODE_APPLY);
         if (g.d == 2) HPG_TD(2, MODE_APPLY);
@@ -68,11 +70,12 @@ template bool launch_tile<double>(const Geo&, const URows<double>*, const PsiTab
                                   double, const double*, const double*, const double*,
                                   const double*, const double*, const double*, const double*,
                                   double*, double*, double*, const int*, int, hipStream_t,
-                                  const KernelEvents*);
+                                  const KernelEvents*, const TileBatch&);
 template bool launch_tile<float>(const Geo&, const URows<float>*, const PsiTabs<float>&, float,
                                  float, const double*, const float*, const float*, const float*,
                                  const float*, const double*, const double*, float*, float*,
-                                 double*, const int*, int, hipStream_t, const KernelEvents*);
+                                 double*, const int*, int, hipStream_t, const KernelEvents*,
+                                 const TileBatch&);
 
 }  // namespace dev
 }  // namespace hpg

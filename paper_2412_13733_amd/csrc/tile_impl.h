@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_apply_tile(Geo g, URows<T> r0, URows<T>
                                                     const double* __restrict__ Phi,
                                                     T* __restrict__ yu, T* __restrict__ ypsi,
                                                     double* __restrict__ partial,
-                                                    const int* __restrict__ done) {
+                                                    const int* __restrict__ done, TileBatch bt) {
     using C = TileCfg<D, PP, TC>;
     constexpr int L = C::L, P = C::P, Q = C::Q, OW = C::OW, XW = C::XW, CW = C::CW;
     constexpr int W = URows<T>::WM, WB = URows<T>::WB;
@@ -169,6 +169,20 @@ __global__ __launch_bounds__(256) void k_apply_tile(Geo g, URows<T> r0, URows<T>
     __shared__ T bv[D][WB][C::OWS];
     __shared__ T WIN[C::NWIN];   // dense windows: [dir][owned row][A | M | B]
     __shared__ double red[4];
+    {
+        // request of a batched launch (blockIdx.y = 0 otherwise)
+        const int64_t rb = blockIdx.y;
+        xu += rb * bt.xu;
+        xpsi += rb * bt.xp;
+        if (xpsi_prev) xpsi_prev += rb * bt.pprev;
+        if (omega) omega += rb * bt.om;
+        if (F) F += rb * bt.F;
+        if (Phi) Phi += rb * bt.Phi;
+        yu += rb * bt.yu;
+        ypsi += rb * bt.yp;
+        if (partial) partial += rb * bt.part;
+        if (done) done += rb * bt.done;
+    }
     if (done && *done) return;
     if (prm) {
         alpha = (T)prm[0];
@@ -844,32 +858,34 @@ void launch_tile_impl(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T a
                              T beta, const double* prm, const T* xu, const T* xpsi,
                              const T* xpsi_prev, const T* omega, const double* F,
                              const double* Phi, T* yu, T* ypsi, double* partial, const int* done,
-                             hipStream_t s, const KernelEvents* ev) {
+                             hipStream_t s, const KernelEvents* ev, const TileBatch& bt) {
     constexpr int TC = tile_cells(D, PP);
     // the prefetching path runs persistent blocks over contiguous runs of tiles;
     // otherwise one block per tile, unless per-block partial sums are written
     // (their count must fit the reduction buffer)
     const unsigned grid = (TileCfg<D, PP, TC>::DENSE || partial) ? (unsigned)tile_grid(g)
                                                                  : (unsigned)tile_count(g);
+    const dim3 gd(grid, (unsigned)bt.nb);
     if (ev && ev->start)
-        hipExtLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), dim3(grid), dim3(256), 0, s,
+        hipExtLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), gd, dim3(256), 0, s,
                               ev->start, ev->stop, 0, g, r[0], r[1], r[2], tb, alpha, beta, prm, xu,
-                              xpsi, xpsi_prev, omega, F, Phi, yu, ypsi, partial, done);
+                              xpsi, xpsi_prev, omega, F, Phi, yu, ypsi, partial, done, bt);
     else
-        hipLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), dim3(grid), dim3(256), 0, s, g,
+        hipLaunchKernelGGL((k_apply_tile<T, D, PP, TC, MODE>), gd, dim3(256), 0, s, g,
                            r[0], r[1], r[2], tb, alpha, beta, prm, xu, xpsi, xpsi_prev, omega, F,
-                           Phi, yu, ypsi, partial, done);
+                           Phi, yu, ypsi, partial, done, bt);
 }
 
 template <typename T, int D, int MODE>
 bool launch_tile_d(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha, T beta,
                    const double* prm, const T* xu, const T* xpsi, const T* xpsi_prev,
                    const T* omega, const double* F, const double* Phi, T* yu, T* ypsi,
-                   double* partial, const int* done, hipStream_t s, const KernelEvents* ev) {
+                   double* partial, const int* done, hipStream_t s, const KernelEvents* ev,
+                   const TileBatch& bt) {
 #define HPG_TC(PV)                                                                            \
     case PV:                                                                                  \
         launch_tile_impl<T, D, PV, MODE>(g, r, tb, alpha, beta, prm, xu, xpsi, xpsi_prev,    \
-                                         omega, F, Phi, yu, ypsi, partial, done, s, ev);      \
+                                         omega, F, Phi, yu, ypsi, partial, done, s, ev, bt);  \
         return true;
     if constexpr (D == 3) {
         switch (g.p) {
@@ -890,7 +906,8 @@ bool launch_tile_d(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alph
     template bool launch_tile_d<T, DD, MM>(const Geo&, const URows<T>*, const PsiTabs<T>&, T, T, \
                                            const double*, const T*, const T*, const T*,          \
                                            const T*, const double*, const double*, T*, T*,       \
-                                           double*, const int*, hipStream_t, const KernelEvents*);
+                                           double*, const int*, hipStream_t, const KernelEvents*, \
+                                           const TileBatch&);
 
 }  // namespace dev
 }  // namespace hpg

@@ -67,7 +67,10 @@ EXPORTS = ["hpg_last_error", "hpg_create_mesh", "hpg_destroy_mesh", "hpg_get_mes
            "hpg_solve_device", "hpg_op_setup", "hpg_op_apply_G", "hpg_op_apply_prec",
            "hpg_op_minres", "hpg_op_residual", "hpg_op_residual_noalloc", "hpg_l2_diff", "hpg_set_kernel_timing",
            "hpg_kernel_time", "hpg_problem_footprint", "hpg_server_create", "hpg_server_submit",
-           "hpg_server_poll", "hpg_server_wait", "hpg_server_stats", "hpg_server_destroy"]
+           "hpg_server_poll", "hpg_server_wait", "hpg_server_stats", "hpg_server_destroy",
+           "hpg_create_batch", "hpg_destroy_batch", "hpg_batch_set_data", "hpg_batch_solve",
+           "hpg_batch_op_setup", "hpg_batch_op_apply_G", "hpg_batch_set_kernel_timing",
+           "hpg_batch_kernel_time"]
 
 
 class RequestInfo(ctypes.Structure):
@@ -138,6 +141,14 @@ def load():
         "hpg_server_wait": ([P, ctypes.c_uint64, P, P, P, P], ctypes.c_int),
         "hpg_server_stats": ([P, P], ctypes.c_int),
         "hpg_server_destroy": ([P], None),
+        "hpg_create_batch": ([P, I32, ctypes.c_int, P], ctypes.c_int),
+        "hpg_destroy_batch": ([P], None),
+        "hpg_batch_set_data": ([P, P, P, SZ], ctypes.c_int),
+        "hpg_batch_solve": ([P, P, P, P, P, P], ctypes.c_int),
+        "hpg_batch_op_setup": ([P, P, D, D, I32, P], ctypes.c_int),
+        "hpg_batch_op_apply_G": ([P, P, P, P], ctypes.c_int),
+        "hpg_batch_set_kernel_timing": ([P, ctypes.c_char_p], ctypes.c_int),
+        "hpg_batch_kernel_time": ([P, ctypes.c_char_p, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -337,6 +348,61 @@ class Problem:
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.hpg_destroy_problem(self.h)
+            self.h = None
+
+
+class Batch:
+    """nbatch independent obstacle problems on one mesh, solved together
+    (hpg_batch_*): every Krylov/Newton step of all of them is one launch."""
+
+    def __init__(self, mesh, nbatch, device=0):
+        self.mesh = mesh
+        self.nb = int(nbatch)
+        h = ctypes.c_void_p()
+        _check(load().hpg_create_batch(mesh.h, self.nb, device, ctypes.byref(h)))
+        self.h = h
+
+    def set_data(self, f_qp, phi_qp):
+        """f and phi of every request at the mesh's quadrature points,
+        shape (nbatch, n_qp) (request-major)."""
+        f = np.ascontiguousarray(f_qp, dtype=np.float64).reshape(-1)
+        ph = np.ascontiguousarray(phi_qp, dtype=np.float64).reshape(-1)
+        _check(load().hpg_batch_set_data(self.h, _dptr(f), _dptr(ph), f.size))
+
+    def solve(self, opts=None, want_lambda=False):
+        m, nb = self.mesh, self.nb
+        u = np.zeros((nb, m.n_u))
+        psi = np.zeros((nb, m.n_psi))
+        lam = np.zeros((nb, m.n_psi)) if want_lambda else None
+        st = (SolveStats * nb)()
+        o = opts if opts is not None else default_opts()
+        rc = load().hpg_batch_solve(self.h, ctypes.byref(o), _dptr(u), _dptr(psi),
+                                    _dptr(lam) if lam is not None else None,
+                                    ctypes.cast(st, ctypes.c_void_p))
+        _check(rc, allow=(OK, NOT_CONVERGED))
+        return u, psi, lam, list(st)
+
+    def op_setup(self, d_psi, alpha, beta=0.0, precision=FP64, stream=None):
+        _check(load().hpg_batch_op_setup(self.h, _tptr(d_psi), alpha, beta, precision,
+                                         ctypes.c_void_p(stream) if stream else None))
+
+    def op_apply_G(self, x, y, stream=None):
+        _check(load().hpg_batch_op_apply_G(self.h, _tptr(x), _tptr(y),
+                                           ctypes.c_void_p(stream) if stream else None))
+
+    def set_kernel_timing(self, group):
+        _check(load().hpg_batch_set_kernel_timing(self.h, group.encode() if group else None))
+
+    def kernel_time(self, group):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(load().hpg_batch_kernel_time(self.h, group.encode(), ctypes.byref(n),
+                                            ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpg_destroy_batch(self.h)
             self.h = None
 
 

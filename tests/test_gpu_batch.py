@@ -1,0 +1,162 @@
+"""Batched solves (hpg_batch_*): several obstacle problems on one mesh, each
+with its own seeded data, solved together with every Krylov/Newton step one
+launch over all of them.
+
+* each request's result is the same bit for bit as when it is solved in a
+  batch of its own (per-request reductions in a fixed order, per-request
+  Newton and proximal decisions), whatever else is in the batch;
+* each matches the oracle's solve of that request (FP64 1e-10, mixed 1e-8
+  relative L2) and the single-problem path;
+* the batched G apply equals the single-problem apply request by request;
+* requests whose solves take different Newton and proximal counts (an
+  unconstrained one beside constrained ones) still agree with their solves
+  alone;
+* unsupported meshes are rejected."""
+import numpy as np
+import pytest
+
+from oracle import assemble, lvpp, mesh as OM
+import workloads as W
+
+from gpu_common import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _hpg():
+    from paper_2412_13733_amd import hpg
+    return hpg
+
+
+def _data(dim, seed):
+    """Request seed s: the sine forcing of seed s (2-D/3-D: a 3-D extension
+    in x, y times 1), paraboloid obstacle; 1-D: f = 10 + s, paraboloid."""
+    if dim == 1:
+        return W.const(10.0 + seed), W.w1d()[1]
+    f2, _ = W.sine_forcing(seed)
+    if dim == 2:
+        return f2, W.paraboloid_phi
+    return (lambda x: f2(np.atleast_2d(x)[:, :2]) + 20.0), W.w3d()[1]
+
+
+def _batch(dim, m, p, seeds):
+    hpg = _hpg()
+    mesh = hpg.Mesh(dim, [m] * dim, p)
+    x = mesh.quadrature_points()
+    fs = np.stack([_data(dim, s)[0](x) for s in seeds])
+    ps = np.stack([_data(dim, s)[1](x) for s in seeds])
+    b = hpg.Batch(mesh, len(seeds))
+    b.set_data(fs, ps)
+    return mesh, b, x
+
+
+def _opts(precision, **kw):
+    hpg = _hpg()
+    base = dict(precision=precision)
+    if precision == hpg.MIXED:
+        base.update(newton_tol=1e-10, krylov_rtol=1e-6)
+    base.update(kw)
+    return hpg.default_opts(**base)
+
+
+CASES = [(1, 16, 4, [0, 1, 2]), (2, 6, 4, [0, 1, 2, 3]), (2, 9, 2, [4, 5]), (3, 3, 3, [0, 1])]
+
+
+@pytest.mark.parametrize("dim,m,p,seeds", CASES)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_requests_alone_and_the_oracle(dim, m, p, seeds, precision):
+    hpg = _hpg()
+    log("batch", dim, m, p, seeds, "precision", precision)
+    mesh, b, x = _batch(dim, m, p, seeds)
+    o = _opts(precision)
+    u, psi, lam, st = b.solve(o, want_lambda=True)
+    for i, sd in enumerate(seeds):
+        log("  request", sd, st[i].as_dict())
+        assert st[i].status == 0
+        # alone: a batch of one
+        _, b1, _ = _batch(dim, m, p, [sd])
+        u1, psi1, lam1, st1 = b1.solve(o, want_lambda=True)
+        assert np.array_equal(u1[0], u[i]) and np.array_equal(psi1[0], psi[i])
+        assert np.array_equal(lam1[0], lam[i])
+        assert st1[0].krylov_iters == st[i].krylov_iters
+        assert st1[0].newton_iters == st[i].newton_iters
+        # the single-problem path
+        prob = hpg.Problem(mesh)
+        f, phi = _data(dim, sd)
+        prob.set_forcing(f(x))
+        prob.set_obstacle(phi(x))
+        us, _, _, sts = prob.solve(o)
+        assert sts.prox_steps == st[i].prox_steps
+        # the oracle
+        om = OM.uniform_mesh(dim, m, p)
+        xo = om.quadrature_points()
+        sysm = assemble.System(om, f(xo), phi(xo))
+        ro = lvpp.solve(sysm, lvpp.Options())
+        eu = sysm.l2_norm_u(u[i] - ro.u) / sysm.l2_norm_u(ro.u)
+        es = sysm.l2_norm_u(u[i] - us) / sysm.l2_norm_u(us)
+        log("  rel L2 vs oracle", eu, "vs single path", es)
+        assert ro.prox_steps == st[i].prox_steps
+        assert eu < (1e-8 if precision else 1e-10)
+        assert es < (1e-8 if precision else 1e-12)
+
+
+def test_batch_with_uneven_requests():
+    # an obstacle that is never reached (phi = 10) beside two constrained
+    # requests: the free one converges in far fewer Newton steps
+    hpg = _hpg()
+    mesh = hpg.Mesh(2, [5, 5], 3)
+    x = mesh.quadrature_points()
+    f0, _ = W.sine_forcing(0)
+    f1, _ = W.sine_forcing(1)
+    fs = np.stack([f0(x), f1(x), f0(x)])
+    ps = np.stack([W.paraboloid_phi(x), np.full(mesh.n_qp, 10.0), W.w2d_dip(2)[1](x)])
+    b = hpg.Batch(mesh, 3)
+    b.set_data(fs, ps)
+    o = _opts(0)
+    u, psi, _, st = b.solve(o)
+    log("  newton", [s.newton_iters for s in st], "prox", [s.prox_steps for s in st])
+    assert len({s.newton_iters for s in st}) > 1
+    for i in range(3):
+        b1 = hpg.Batch(mesh, 1)
+        b1.set_data(fs[i:i + 1], ps[i:i + 1])
+        u1, psi1, _, st1 = b1.solve(o)
+        assert np.array_equal(u1[0], u[i]) and np.array_equal(psi1[0], psi[i])
+        assert st1[0].status == st[i].status == 0
+
+
+@pytest.mark.parametrize("dim,m,p", [(2, 7, 2), (2, 5, 6), (3, 3, 4)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_apply_equals_single_applies(dim, m, p, precision):
+    hpg = _hpg()
+    seeds = [0, 1, 2]
+    mesh, b, x = _batch(dim, m, p, seeds)
+    rng = np.random.default_rng(3)
+    nb, n = len(seeds), mesh.n_u + mesh.n_psi
+    dt = torch.float64 if precision == 0 else torch.float32
+    psi = torch.tensor(0.5 * rng.standard_normal((nb, mesh.n_psi)), dtype=torch.float64,
+                       device="cuda").contiguous()
+    xv = torch.tensor(rng.standard_normal((nb, n)), dtype=dt, device="cuda").contiguous()
+    y = torch.zeros_like(xv)
+    b.op_setup(psi, 3.0, 0.0, precision=precision)
+    b.op_apply_G(xv, y)
+    for i, sd in enumerate(seeds):
+        prob = hpg.Problem(mesh)
+        f, phi = _data(dim, sd)
+        prob.set_forcing(f(x))
+        prob.set_obstacle(phi(x))
+        prob.op_setup(psi[i].contiguous(), 3.0, 0.0, precision=precision)
+        yi = torch.zeros(n, dtype=dt, device="cuda")
+        prob.op_apply_G(xv[i].contiguous(), yi)
+        assert torch.equal(yi, y[i])
+
+
+def test_batch_rejects_unsupported_meshes():
+    hpg = _hpg()
+    for mesh in (hpg.Mesh(2, [3, 3], 3, constraint=hpg.GRADIENT),
+                 hpg.Mesh(2, [2, 2], 0, degree=[2, 3, 4, 5]),
+                 hpg.Mesh(2, [2, 2], 14)):
+        with pytest.raises(hpg.HpgError) as e:
+            hpg.Batch(mesh, 2)
+        assert e.value.status == hpg.ERR_INVALID_ARG
