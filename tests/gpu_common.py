@@ -1,6 +1,7 @@
 """Shared set-up for the GPU parity tests: builds the same discrete problem on
 the HIP side (through the C ABI) and on the oracle side (its own quadrature
 points, assembly and DOF map); only the input generators are shared."""
+import os
 import sys
 
 import numpy as np
@@ -33,5 +34,27 @@ def build_pair(dim, m, p, data, breaks=None, kind=OM.OBSTACLE):
     return mesh, prob, sysm
 
 
+# Parity bars of the operator tests (max-norm relative error against the
+# oracle's assembled operators), each at most ten times the worst error the
+# suite observes, or the target (1e-13 FP64, 1e-6 FP32) where that already
+# holds.  Worst observed on the MI355X: FP64 G 2.0e-15, FP64 Newton residual
+# 1.7e-15, FP64 preconditioner 4.7e-13 (inverses of conditioned Schur blocks
+# and the fast-diagonalisation passes), FP32 G 4.7e-7, FP32 preconditioner
+# 5.2e-7.
+FP64_G = 1e-13
+FP64_RES = 1e-13
+FP64_P = 5e-12
+FP32_G = 1e-6
+FP32_P = 1e-6
+
+
 def rel(a, b):
-    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+    """max |a - b| / max |b|; printed with the calling test and line when
+    HPG_LOG_REL is set (to record the observed errors behind the bars)."""
+    v = float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+    if os.environ.get("HPG_LOG_REL"):
+        fr = sys._getframe(1)
+        print("[rel] %s %s:%d %.3e" % (os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0],
+                                       os.path.basename(fr.f_code.co_filename), fr.f_lineno, v),
+              flush=True)
+    return v

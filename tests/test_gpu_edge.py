@@ -11,7 +11,7 @@ import pytest
 from oracle import lvpp, precond, mesh as OM
 import workloads as W
 
-from gpu_common import build_pair, log, rel
+from gpu_common import FP32_G, FP32_P, FP64_G, FP64_P, FP64_RES, build_pair, log, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_edge_operators(dim, m, p, breaks, kind):
     x = rng.standard_normal(mesh.n_u + mesh.n_psi)
     yu, yp = precond.apply_G(sysm, psi, alpha, beta, x[:mesh.n_u], x[mesh.n_u:])
     zu, zp = precond.apply_prec(sysm, psi, alpha, beta, x[:mesh.n_u], x[mesh.n_u:])
-    for prec, dt, tol_g, tol_p in ((1, torch.float32, 2e-5, 1e-4), (0, torch.float64, 1e-12, 1e-10)):
+    for prec, dt, tol_g, tol_p in ((1, torch.float32, FP32_G, FP32_P), (0, torch.float64, FP64_G, FP64_P)):
         prob.op_setup(_dev(psi), alpha, beta, precision=prec)
         y = torch.zeros(mesh.n_u + mesh.n_psi, dtype=dt, device="cuda")
         prob.op_apply_G(_dev(x, dt), y)
@@ -79,7 +79,7 @@ def test_edge_operators(dim, m, p, breaks, kind):
     prob.op_residual(_dev(u), _dev(psi), _dev(pp), alpha, R)
     Ru, Rp = sysm.residual(u, psi, pp, alpha)
     Rg = R.cpu().numpy()
-    assert rel(Rg[:mesh.n_u], Ru) < 1e-12 and rel(Rg[mesh.n_u:], Rp) < 1e-12
+    assert rel(Rg[:mesh.n_u], Ru) < FP64_RES and rel(Rg[mesh.n_u:], Rp) < FP64_RES
 
 
 def test_edge_inactive_constraint_solve():

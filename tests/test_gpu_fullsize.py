@@ -12,14 +12,14 @@ the solves use.
   widths (every cell touching the support lies in that box); psi-block outputs
   are compared on the cells of a 2^3 box against the oracle's, and the A-block
   through alpha A z_u = r_u.
-Tolerances as for the small parity cases (FP64 1e-12 / 1e-10, FP32 2e-5)."""
+Tolerances as for the small parity cases (the bars in gpu_common)."""
 import numpy as np
 import pytest
 
 from oracle import assemble, precond, mesh as OM
 import workloads as W
 
-from gpu_common import log, rel
+from gpu_common import FP32_G, FP64_G, FP64_P, FP64_RES, log, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +96,7 @@ def test_fullsize_2d_32x32_p6_operators():
     x = rng.standard_normal(mesh.n_u + mesh.n_psi)
     alpha, beta = 16.0, 1e-4
     yu, yp = precond.apply_G(sysm, psi, alpha, beta, x[:mesh.n_u], x[mesh.n_u:])
-    for prec, dt, tol in ((0, torch.float64, 1e-12), (1, torch.float32, 2e-5)):
+    for prec, dt, tol in ((0, torch.float64, FP64_G), (1, torch.float32, FP32_G)):
         prob.op_setup(_dev(psi), alpha, beta, precision=prec)
         y = torch.zeros(mesh.n_u + mesh.n_psi, dtype=dt, device="cuda")
         prob.op_apply_G(_dev(x, dt), y)
@@ -110,7 +110,7 @@ def test_fullsize_2d_32x32_p6_operators():
     prob.op_residual(_dev(u), _dev(psi), _dev(psi_prev), alpha, R)
     Ru, Rp = sysm.residual(u, psi, psi_prev, alpha)
     Rg = R.cpu().numpy()
-    assert rel(Rg[:mesh.n_u], Ru) < 1e-12 and rel(Rg[mesh.n_u:], Rp) < 1e-12
+    assert rel(Rg[:mesh.n_u], Ru) < FP64_RES and rel(Rg[mesh.n_u:], Rp) < FP64_RES
     # preconditioner: A-block by alpha A z_u = r_u, psi-block on sampled cells
     prob.op_setup(_dev(psi), alpha, beta, precision=0)
     r = rng.standard_normal(mesh.n_u + mesh.n_psi)
@@ -120,7 +120,7 @@ def test_fullsize_2d_32x32_p6_operators():
     zz[mesh.n_u:] = 0
     y = torch.zeros_like(z)
     prob.op_apply_G(zz, y)
-    assert rel(y[:mesh.n_u].cpu().numpy(), r[:mesh.n_u]) < 1e-10
+    assert rel(y[:mesh.n_u].cpu().numpy(), r[:mesh.n_u]) < FP64_P
     _check_psi_block_cells(sysm, psi, alpha, beta, r, z.cpu().numpy(), mesh.n_u,
                            cells=rng.choice(mesh.n_cells, 12, replace=False), npc=mesh.P ** 2)
 
@@ -133,7 +133,7 @@ def _check_psi_block_cells(sysm, psi, alpha, beta, r, zg, n_u, cells, npc, cell_
         rb = r[n_u + cg * npc: n_u + (cg + 1) * npc]
         zo = np.linalg.solve(-S[k], rb)
         zb = zg[n_u + cg * npc: n_u + (cg + 1) * npc]
-        assert rel(zb, zo) < 1e-10, (c, rel(zb, zo))
+        assert rel(zb, zo) < FP64_P, (c, rel(zb, zo))
 
 
 # ---------------------------------------------------------------------------
@@ -161,7 +161,7 @@ def test_fullsize_3d_16cubed_windowed(kind, p, data):
     pidx = (cmap[:, None] * npc + np.arange(npc)[None, :]).reshape(-1)
     psi_s = psi[pidx]
     yu_o, yp_o = precond.apply_G(sysm, psi_s, alpha, beta, x[umap], x[mesh.n_u + pidx])
-    for prec, dt, tol in ((0, torch.float64, 1e-12), (1, torch.float32, 2e-5)):
+    for prec, dt, tol in ((0, torch.float64, FP64_G), (1, torch.float32, FP32_G)):
         prob.op_setup(_dev(psi), alpha, beta, precision=prec)
         y = torch.zeros(mesh.n_u + mesh.n_psi, dtype=dt, device="cuda")
         prob.op_apply_G(_dev(x, dt), y)
@@ -183,7 +183,7 @@ def test_fullsize_3d_16cubed_windowed(kind, p, data):
     zz[mesh.n_u:] = 0
     y = torch.zeros_like(z)
     prob.op_apply_G(zz, y)
-    assert rel(y[:mesh.n_u].cpu().numpy(), r[:mesh.n_u]) < 1e-10
+    assert rel(y[:mesh.n_u].cpu().numpy(), r[:mesh.n_u]) < FP64_P
     om2, sys2 = _oracle(d, m, 2, p, kind, data)
     cm2 = _cell_map(d, m, 2)
     p2 = (cm2[:, None] * npc + np.arange(npc)[None, :]).reshape(-1)
