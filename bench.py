@@ -48,9 +48,20 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-newton-sample", type=int, default=2)
     ap.add_argument("--no-probe", action="store_true")
-    ap.add_argument("--probe-m", type=int, default=4096)
-    ap.add_argument("--probe-p", type=int, default=2)
+    ap.add_argument("--probes", default="R1,R2,R3",
+                    help="roofline probes of the G apply: R1 = 2-D 4096^2 p=2, R2 = 2-D 2048^2 "
+                         "p=3, R3 = 3-D 160^3 p=2 (FP64)")
     ap.add_argument("--probe-launches", type=int, default=20)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched solves and the batched apply probe B1")
+    ap.add_argument("--batch-n", type=int, default=64,
+                    help="requests of the headline mesh (seeds 0..n-1) in the batched solve")
+    ap.add_argument("--b1-n", type=int, default=4096,
+                    help="requests of 32x32 cells at p=2 in the batched apply probe B1")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the 3-D 16^3 p=5 obstacle solves")
+    ap.add_argument("--3d-gradient", dest="gradient3d", action="store_true",
+                    help="also solve the 3-D 16^3 p=4 gradient-constraint problem (minutes)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="prefix of the 512-request serving stream to run")
@@ -64,8 +75,8 @@ def parse():
                     help="run only the per-cell-degree workload (for profiling)")
     ap.add_argument("--counters", action="store_true",
                     help="only a few operator launches for rocprofv3 --pmc passes: the "
-                         "workload's G apply and preconditioner (FP32 and FP64), the 4096^2 "
-                         "p=2 G apply, and a 1 GiB device copy to calibrate the counters")
+                         "workload's G apply and preconditioner (FP32 and FP64), the G apply of "
+                         "each roofline probe, and a 1 GiB device copy to calibrate the counters")
     return ap.parse_args()
 
 
@@ -95,7 +106,11 @@ def counters_run(args, torch, hpg, W):
     prob.set_kernel_timing(None)
     del prob
     args.probe_launches = 5
-    apply_probe(args, torch, hpg)
+    for name in [s_.strip() for s_ in args.probes.split(",") if s_.strip()]:
+        dim, m, p = PROBES[name]
+        apply_probe(args, torch, hpg, dim, m, p, None)
+    if not args.no_batch:
+        batch_probe(args, torch, hpg)
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
     b = torch.empty_like(a)
     for _ in range(3):
@@ -145,9 +160,10 @@ def measured_traffic(group, m, p, path):
     return ent["traffic_bytes"] if ent else None
 
 
-def run_solves(prob, d_u, d_psi, opts, steps, torch, group=None):
+def run_solves(prob, d_u, d_psi, opts, steps, torch, group=None, check=True):
     lat = []
     kry = newton = prox = 0
+    st = None
     if group:
         prob.set_kernel_timing(group)
     torch.cuda.synchronize()
@@ -159,7 +175,7 @@ def run_solves(prob, d_u, d_psi, opts, steps, torch, group=None):
         kry += st.krylov_iters
         newton += st.newton_iters
         prox += st.prox_steps
-        assert st.status == 0, st.as_dict()
+        assert st.status == 0 or not check, st.as_dict()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = {}
@@ -167,7 +183,7 @@ def run_solves(prob, d_u, d_psi, opts, steps, torch, group=None):
         for g in GROUPS:
             kt[g] = prob.kernel_time(g)
         prob.set_kernel_timing(None)
-    return dict(seconds=t1 - t0, lat=lat, krylov=kry, newton=newton, prox=prox, ktime=kt)
+    return dict(seconds=t1 - t0, lat=lat, krylov=kry, newton=newton, prox=prox, ktime=kt, last=st)
 
 
 def cpu_baseline(args, newton_per_solve):
@@ -195,18 +211,73 @@ def cpu_baseline(args, newton_per_solve):
         dt = time.perf_counter() - t1
     per_newton = dt / max(res.newton, 1)
     solve_s = t_asm + per_newton * newton_per_solve
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d Newton steps (sparse LU of the full saddle matrix, %d DOF) of the "
-                      "first proximal subproblem, %.1f s, plus assembly %.1f s; extrapolated "
-                      "with %d Newton steps per solve; 1 thread"
-                      % (res.newton, om.n_u + om.n_psi, dt, t_asm, newton_per_solve),
-            "seconds_per_newton_step": per_newton}
+    out = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": "%d Newton steps (sparse LU of the full saddle matrix, %d DOF) of the "
+                     "first proximal subproblem, %.1f s, plus assembly %.1f s; extrapolated "
+                     "with %d Newton steps per solve; 1 thread"
+                     % (res.newton, om.n_u + om.n_psi, dt, t_asm, newton_per_solve),
+           "seconds_per_newton_step": per_newton,
+           "lu_share": res.lu_seconds / max(dt, 1e-300),
+           "host": host_info()}
+    # the whole oracle solve of this workload, timed where the stored oracle
+    # solution was written (tests/golden), for comparison with the extrapolation
+    fn = os.path.join(ROOT, "tests", "golden", "solve_2d_%dx%d_p%d.npz" % (args.m, args.m, args.p))
+    if args.seed == 0 and os.path.exists(fn):
+        z = np.load(fn)
+        out["full_solve_reference"] = {
+            "seconds": float(z["solve_seconds"]), "lu_seconds": float(z["lu_seconds"]),
+            "newton": int(z["newton"]), "prox_steps": int(z["prox_steps"]),
+            "nproc": int(z["nproc"]), "cpu_model": str(z["cpu_model"]),
+            "where": "the machine that wrote the stored oracle solution, 1 thread"}
+    return out
 
 
-def apply_probe(args, torch, hpg):
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem = 0
+    try:
+        with open("/proc/meminfo") as fh:
+            mem = int(fh.readline().split()[1]) * 1024
+    except (OSError, ValueError, IndexError):
+        pass
+    return {"nproc": os.cpu_count() or 0, "cpu_model": model, "mem_GB": mem / 1e9}
+
+
+PROBES = {"R1": (2, 4096, 2), "R2": (2, 2048, 3), "R3": (3, 160, 2)}
+
+
+def copy_bandwidth(torch):
+    """Device-to-device copy of a 1 GiB FP64 buffer (HIP events): bytes read
+    plus bytes written per second, the bandwidth a streaming kernel can reach."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    out = {"bytes": 2 * a.numel() * 8, "us": sec * 1e6, "GBs": 2 * a.numel() * 8 / sec / 1e9}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def apply_probe(args, torch, hpg, dim, m, p, copy_gbs):
     """HBM roofline of the operator apply on a large low-p mesh (FP64)."""
-    m, p = args.probe_m, args.probe_p
-    mesh = hpg.Mesh(2, [m, m], p)
+    mesh = hpg.Mesh(dim, [m] * dim, p)
     prob = hpg.Problem(mesh, device=0)
     n = mesh.n_u + mesh.n_psi
     gen = torch.Generator(device="cuda")
@@ -228,7 +299,7 @@ def apply_probe(args, torch, hpg):
     nu, msu = prob.kernel_time("apply_G_u")
     npx, msp = prob.kernel_time("apply_G_psi")
     prob.set_kernel_timing(None)
-    Qd = mesh.q ** 2
+    Qd = mesh.q ** dim
     alg = 8 * (2 * mesh.n_u + 2 * mesh.n_psi + mesh.n_cells * Qd)
     if nf:
         t_apply = msf / nf * 1e-3
@@ -240,12 +311,14 @@ def apply_probe(args, torch, hpg):
     fn = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "pmc_traffic.json")
     ent = None
     if os.path.exists(fn):
-        ent = json.load(open(fn))["kernels"].get("G apply, 2-D %dx%d p=%d, FP64" % (m, m, p))
-    out = {"workload": "apply_G, 2-D %dx%d cells, p=%d, FP64" % (m, m, p),
+        ent = json.load(open(fn))["kernels"].get("G apply, %d-D %s p=%d, FP64"
+                                                 % (dim, "x".join([str(m)] * dim), p))
+    out = {"workload": "apply_G, %d-D %s cells, p=%d, FP64" % (dim, "x".join([str(m)] * dim), p),
            "traffic": ent["traffic_bytes"] if ent else None,
            "kernel": "fused tiled apply" if nf else "u-side + psi-side kernels",
            "algorithmic_bytes": alg, "apply_us": t_apply * 1e6,
            "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
+           "frac_of_copy": ach / copy_gbs if copy_gbs else None,
            "wall_us_per_call": wall * 1e6, "launches": launches}
     del prob, mesh, x, y, psi
     torch.cuda.empty_cache()
@@ -327,6 +400,8 @@ def serving_bench(args, hpg, W):
                 "fp64_fallbacks": int(sum(st.fp64_fallbacks for _, st, _ in res))}
 
     seq, s_seq = serve(hpg, built, None, 1, hpg.FP64, "fp64 x1")
+    b64, s_b64 = serve(hpg, built, None, args.serve_slots, hpg.FP64,
+                       "fp64 x%d" % args.serve_slots)
     bat, s_bat = serve(hpg, built, None, args.serve_slots, hpg.MIXED,
                        "mixed x%d" % args.serve_slots)
     live, s_live = serve(hpg, built, arrivals, args.serve_slots, hpg.MIXED, "mixed poisson")
@@ -343,9 +418,14 @@ def serving_bench(args, hpg, W):
         "gradient_requests": kinds.count("gradient"),
         "slots": args.serve_slots,
         "fp64_sequential": summary(seq, s_seq),
+        "fp64_batched": summary(b64, s_b64),
         "mixed_batched": summary(bat, s_bat),
         "mixed_poisson": summary(live, s_live),
+        # mixed x slots over FP64 x1 mixes precision and concurrency; the two
+        # ratios after it separate them
         "speedup_batched_mixed_vs_fp64": s_bat["solves_per_s"] / max(s_seq["solves_per_s"], 1e-300),
+        "speedup_mixed_vs_fp64_same_slots": s_bat["solves_per_s"] / max(s_b64["solves_per_s"], 1e-300),
+        "speedup_fp64_slots_vs_one": s_b64["solves_per_s"] / max(s_seq["solves_per_s"], 1e-300),
         "accuracy_note": "relative l2 distance of the mixed-path u to the FP64-path u, over the "
                          "requests both paths converged on",
         "max_rel_l2_mixed_vs_fp64": max(errs) if errs else None,
@@ -402,6 +482,139 @@ def hp_bench(args, torch, hpg, W):
         print("[bench] hp %s: %.3f s per solve, krylov %d, newton %d"
               % (prec, 1e-3 * ent["ms_per_solve"], ent["krylov_per_solve"],
                  ent["newton_per_solve"]), file=sys.stderr, flush=True)
+    return out
+
+
+def batch_probe(args, torch, hpg):
+    """B1: the G apply of args.b1_n requests of 32 x 32 cells at p = 2 (FP64)
+    in one launch (hpg_batch_op_apply_G), HIP events per launch."""
+    nb = args.b1_n
+    mesh = hpg.Mesh(2, [32, 32], 2)
+    bt = hpg.Batch(mesh, nb)
+    n = mesh.n_u + mesh.n_psi
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2)
+    psi = 0.5 * torch.randn(nb * mesh.n_psi, dtype=torch.float64, device="cuda", generator=gen)
+    x = torch.randn(nb * n, dtype=torch.float64, device="cuda", generator=gen)
+    y = torch.empty_like(x)
+    bt.op_setup(psi, 4.0, 0.0, precision=hpg.FP64)
+    for _ in range(3):
+        bt.op_apply_G(x, y)
+    bt.set_kernel_timing("apply_G")
+    for _ in range(args.probe_launches):
+        bt.op_apply_G(x, y)
+    nl, ms = bt.kernel_time("apply_G")
+    bt.set_kernel_timing(None)
+    alg = nb * 8 * (2 * mesh.n_u + 2 * mesh.n_psi + mesh.n_cells * mesh.q ** 2)
+    t = ms / nl * 1e-3
+    out = {"workload": "apply_G of %d requests of 2-D 32x32 cells, p=2, FP64, one launch" % nb,
+           "algorithmic_bytes": alg, "apply_us": t * 1e6, "achieved_GBs": alg / t / 1e9,
+           "frac": alg / t / 1e9 / HBM_PEAK_GBS, "launches": nl}
+    del bt, x, y, psi
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_bench(args, torch, hpg, W):
+    """Batched solves: args.batch_n requests of the headline mesh (32 x 32
+    cells, p = 6, paraboloid obstacle), request i with the sine forcing of
+    seed i, solved together (hpg_batch_solve), FP64 and mixed; request 0's
+    result against the single-problem path."""
+    nb = args.batch_n
+    mesh = hpg.Mesh(2, [args.m, args.m], args.p)
+    x = mesh.quadrature_points()
+    fs = np.stack([W.sine_forcing(i)[0](x) for i in range(nb)])
+    ps = np.stack([W.paraboloid_phi(x)] * nb)
+    n_dof = mesh.n_u + mesh.n_psi
+    bt = hpg.Batch(mesh, nb)
+    bt.set_data(fs, ps)
+    out = {"workload": "%d requests of the 2-D %dx%d p=%d obstacle problem (sine forcing seeds "
+                       "0..%d), solved together" % (nb, args.m, args.m, args.p, nb - 1),
+           "requests": nb}
+    ref = {}
+    for prec in ("fp64", "mixed"):
+        kw = dict(precision=hpg.FP64 if prec == "fp64" else hpg.MIXED)
+        if prec == "mixed":
+            kw.update(newton_tol=1e-10, krylov_rtol=1e-6)
+        opts = hpg.default_opts(**kw)
+        t0 = time.perf_counter()
+        u, psi, _, st = bt.solve(opts)
+        sec = time.perf_counter() - t0
+        kry = sum(s_.krylov_iters for s_ in st)
+        ent = {"seconds": sec, "solves_per_s": nb / sec, "dof_krylov_per_s": n_dof * kry / sec,
+               "converged": int(sum(s_.status == 0 for s_ in st)),
+               "krylov_per_request": kry / nb,
+               "newton_per_request": sum(s_.newton_iters for s_ in st) / nb}
+        ref[prec] = u
+        out["path_" + prec] = ent
+        print("[bench] batch of %d, %s: %.2f s, %.1f solves/s" % (nb, prec, sec, nb / sec),
+              file=sys.stderr, flush=True)
+    # request 0 through the single-problem path, and mixed against FP64
+    prob = hpg.Problem(mesh, device=0)
+    prob.set_forcing(fs[0])
+    prob.set_obstacle(ps[0])
+    u0, _, _, _ = prob.solve(hpg.default_opts())
+    du = ref["fp64"][0] - u0
+    out["request0_max_rel_vs_single_fp64"] = float(np.max(np.abs(du)) / np.max(np.abs(u0)))
+    dm = ref["mixed"] - ref["fp64"]
+    out["mixed_max_rel_vs_fp64"] = float(np.max(np.abs(dm)) / np.max(np.abs(ref["fp64"])))
+    del bt, prob
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_3d(args, torch, hpg, W):
+    """3-D unit cube, 16^3 cells: the p = 5 obstacle problem (f = 50,
+    phi = 0.05 + 0.2 |x - c|^2, alpha_k = 2^k) in FP64 and mixed, and with
+    --3d-gradient the p = 4 gradient-constraint problem (|grad u| <= 0.3,
+    the paper's gradient step sizes) in mixed precision.  One solve each,
+    after an untimed warm-up; feasibility and complementarity diagnostics of
+    each result."""
+    out = {}
+    cases = [("obstacle_p5", hpg.OBSTACLE, 5, W.w3d(), {})]
+    if args.gradient3d:
+        cases.append(("gradient_p4", hpg.GRADIENT, 4, W.w3d_gradient(),
+                      dict(alpha0=2.0 ** -7, alpha_factor=2.0 ** 0.5, alpha_max=4.0,
+                           fixed_prox_steps=20, max_newton=200, stall_tol=1e-8)))
+    for name, kind, p, (f, phi), extra in cases:
+        mesh = hpg.Mesh(3, [16, 16, 16], p, constraint=kind)
+        x = mesh.quadrature_points()
+        prob = hpg.Problem(mesh, device=0)
+        prob.set_forcing(f(x))
+        prob.set_obstacle(phi(x))
+        n_dof = mesh.n_u + mesh.n_psi
+        d_u = torch.zeros(mesh.n_u, dtype=torch.float64, device="cuda")
+        d_psi = torch.zeros(mesh.n_psi, dtype=torch.float64, device="cuda")
+        d_u64 = torch.zeros_like(d_u)
+        ent = {"n_u": mesh.n_u, "n_psi": mesh.n_psi}
+        precs = ("fp64", "mixed") if kind == hpg.OBSTACLE else ("mixed",)
+        for prec in precs:
+            kw = dict(extra)
+            kw["precision"] = hpg.FP64 if prec == "fp64" else hpg.MIXED
+            if prec == "mixed":
+                kw.update(newton_tol=1e-10, krylov_rtol=1e-6)
+            opts = hpg.default_opts(**kw)
+            if kind == hpg.OBSTACLE:
+                prob.solve_device(d_u, d_psi, opts)   # warm-up (tables, graphs)
+            r = run_solves(prob, d_u, d_psi, opts, 1, torch, check=False)
+            st = r["last"]
+            e = {"seconds": r["seconds"], "status": st.status,
+                 "dof_krylov_per_s": n_dof * r["krylov"] / r["seconds"],
+                 "krylov": r["krylov"], "newton": r["newton"], "prox": r["prox"],
+                 "complementarity_rel": st.complementarity_rel,
+                 "max_violation": st.max_violation, "fp64_fallbacks": st.fp64_fallbacks}
+            if prec == "fp64":
+                d_u64.copy_(d_u)
+            elif "fp64" in precs:
+                diff, nrm = prob.l2_diff(d_u, d_u64)
+                e["rel_l2_vs_fp64"] = diff / nrm
+            ent["path_" + prec] = e
+            print("[bench] 3-D 16^3 %s %s: %.2f s, status %d, krylov %d, newton %d"
+                  % (name, prec, r["seconds"], st.status, r["krylov"], r["newton"]),
+                  file=sys.stderr, flush=True)
+        out[name] = ent
+        del prob
+        torch.cuda.empty_cache()
     return out
 
 
@@ -558,10 +771,24 @@ def main():
     if not args.no_probe:
         del prob
         torch.cuda.empty_cache()
-        out["apply_G_probe"] = apply_probe(args, torch, hpg)
-        print("[bench] apply_G probe: %.1f us, %.0f GB/s" % (out["apply_G_probe"]["apply_us"],
-                                                            out["apply_G_probe"]["achieved_GBs"]),
+        cp = copy_bandwidth(torch)
+        out["copy_bandwidth"] = cp
+        print("[bench] 1 GiB device copy: %.0f GB/s" % cp["GBs"], file=sys.stderr, flush=True)
+        for name in [s_.strip() for s_ in args.probes.split(",") if s_.strip()]:
+            dim, m, p = PROBES[name]
+            ent = apply_probe(args, torch, hpg, dim, m, p, cp["GBs"])
+            out["apply_G_probe" if name == "R1" else "apply_G_probe_" + name] = ent
+            print("[bench] apply_G probe %s: %.1f us, %.0f GB/s (%.1f %% of 8 TB/s, %.1f %% of "
+                  "the copy)" % (name, ent["apply_us"], ent["achieved_GBs"], 100 * ent["frac"],
+                                 100 * ent["frac_of_copy"]), file=sys.stderr, flush=True)
+    if not args.no_batch:
+        out["apply_G_probe_B1"] = batch_probe(args, torch, hpg)
+        print("[bench] apply_G probe B1: %.1f us, %.0f GB/s" % (out["apply_G_probe_B1"]["apply_us"],
+                                                               out["apply_G_probe_B1"]["achieved_GBs"]),
               file=sys.stderr, flush=True)
+        out["batch"] = batch_bench(args, torch, hpg, W)
+    if not args.no_3d:
+        out["solve_3d"] = bench_3d(args, torch, hpg, W)
     if not args.no_hp:
         out["hp_dip_64x64"] = hp_bench(args, torch, hpg, W)
     if not args.no_serving:
