@@ -279,23 +279,27 @@ hpg_status hpg_kernel_time(hpg_problem* prob, const char* group, int64_t* launch
                            double* total_ms);
 
 /* ---- batched solves: many problems of one mesh shape in each launch -------
- * nbatch independent problems on the same mesh (the same breakpoints, degree
- * p and obstacle constraint; the Sec. 2 problem with its own f and phi each)
- * solved together: each step of the inner Newton solve (Sec. 4: the G apply
- * of eq. (pG-matrix), the preconditioner P_D of eq. (schur4), the Lanczos
- * updates, the Newton residual, the linearisation) is one launch over all
- * requests, with per-request reductions in the order of a solve of that
- * request alone, and per-request Newton and proximal decisions, so a request's
- * result does not depend on the rest of the batch.  Supported: obstacle
- * constraint, one degree on every cell, p <= 12 in 1-D/2-D and p <= 7 in 3-D
- * (the fused tiled apply) with Schur blocks of at most 48 KB
- * (HPG_ERR_INVALID_ARG otherwise).  Arrays are request-major: request b's f
- * and phi are values [b n_qp, (b+1) n_qp), its u [b n_u, (b+1) n_u), its psi and
- * lambda [b n_psi, (b+1) n_psi).
+ * Independent problems on the same mesh (the same breakpoints, degree p and
+ * obstacle constraint; the Sec. 2 problem with its own f and phi each) solved
+ * together in nbatch slots: each step of the inner Newton solve (Sec. 4: the
+ * G apply of eq. (pG-matrix), the preconditioner P_D of eq. (schur4), the
+ * Lanczos updates, the Newton residual, the linearisation) of the requests in
+ * the slots is one launch, with per-request reductions in the order of a
+ * solve of that request alone.  Each request runs its own proximal, Newton
+ * and line-search sequence at its own pace (a request whose Krylov solve
+ * ends goes on while the others' continue), and a slot whose request
+ * finishes takes the next one, so its result does not depend on the others.
+ * Supported: obstacle constraint, one degree on every cell, p <= 12 in
+ * 1-D/2-D and p <= 7 in 3-D (the fused tiled apply) with Schur blocks of at
+ * most 48 KB (HPG_ERR_INVALID_ARG otherwise).
+ * hpg_batch_set_data: f and phi of nreq requests (n_values = nreq n_qp, any
+ *   nreq >= 1), request-major: request r's values are [r n_qp, (r+1) n_qp).
  * hpg_batch_solve: options as for hpg_solve (step_extension, inexact_newton
- *   and warm starts: HPG_ERR_INVALID_ARG); stats[nbatch] per request; returns
- *   HPG_OK if every request converged, else HPG_NOT_CONVERGED (outputs
- *   written for all).  Every request's outer loop stops by its own test.
+ *   and warm starts: HPG_ERR_INVALID_ARG); outputs per request, request-major
+ *   (u_out[nreq n_u], psi_out and lam_out [nreq n_psi], stats[nreq], where
+ *   seconds is the time from the request's start in a slot to its end);
+ *   returns HPG_OK if every request converged, else HPG_NOT_CONVERGED
+ *   (outputs written for all).
  * hpg_batch_op_setup / hpg_batch_op_apply_G: the linearisation and G of all
  *   requests at once (device psi[nbatch n_psi], x and y [nbatch (n_u + n_psi)],
  *   request b's vector at offset b (n_u + n_psi), u first; float vectors for

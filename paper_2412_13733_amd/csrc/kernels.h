@@ -74,6 +74,7 @@ struct KernelEvents {
 struct TileBatch {
     int nb = 1;
     int64_t xu = 0, xp = 0, pprev = 0, om = 0, F = 0, Phi = 0, yu = 0, yp = 0, part = 0, done = 0;
+    int64_t prm = 0;   // per-request (alpha, beta, 1/alpha) at prm + b * this
 };
 struct PsiBatch {
     int nb = 1;
@@ -82,6 +83,7 @@ struct PsiBatch {
 struct VecBatch {
     int nb = 1;
     int64_t v = 0, part = 0;   // vector stride, partial-sum stride (the state: st + b)
+    const int* mask = nullptr; // MINRES start: only the requests with mask[b] != 0
 };
 
 // MINRES scalar state (device)
@@ -120,9 +122,13 @@ bool launch_tile(const Geo& g, const URows<T>* r, const PsiTabs<T>& tb, T alpha,
 enum { SETUP_LDS = 0, SETUP_HBM_T2 = 1, SETUP_HBM = 2 };
 size_t setup_smem_per_cell(const Geo& g);
 size_t setup_big_smem(const Geo& g, bool t2);
+// batches (g.n_cells = all requests' cells): prm_req (4 per request: alpha,
+// beta, ..) overrides alpha and beta per request, and with mask only the
+// cells of requests with mask[req] != 0 are written (req = cell / cpr)
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
-                  float* om32, double* s64, float* s32, hipStream_t s);
+                  float* om32, double* s64, float* s32, hipStream_t s,
+                  const double* prm_req = nullptr, const int* mask = nullptr, int64_t cpr = 1);
 template <typename T>
 void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
                      double* partial, const int* done, hipStream_t s,
@@ -144,6 +150,7 @@ struct GemmEpi {
     // partial[request * pstride] (pstride 0: one index over all batches)
     int bdiv;
     int64_t pstride, dstride;
+    int64_t prmstride;   // per-request prm at prm + request * prmstride
 };
 template <typename T>
 void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,

@@ -235,10 +235,16 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
                                                double* __restrict__ omega64,
                                                float* __restrict__ omega32,
                                                double* __restrict__ sinv64,
-                                               float* __restrict__ sinv32) {
+                                               float* __restrict__ sinv32,
+                                               const double* __restrict__ prm_req,
+                                               const int* __restrict__ mask, int64_t cpr) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     const int n = g.Pd, q = g.q, P = g.P, Qd = g.Qd;
+    // batches: the request of a cell, whether it is set up now, its alpha and beta
+    auto live = [&](int64_t cell) { return !mask || mask[cell / cpr] != 0; };
+    auto a_of = [&](int64_t cell) { return prm_req ? prm_req[4 * (cell / cpr)] : alpha; };
+    auto b_of = [&](int64_t cell) { return prm_req ? prm_req[4 * (cell / cpr) + 1] : beta; };
     const int S = g.S;
     // per cell: A, B (S each), T1 (q^(D-1) P^2), T2 (q P^4, D = 3), Dm (n^2), col/row (2n)
     const int sT1 = (D == 1) ? 1 : ((D == 2) ? q * P * P : q * q * P * P);
@@ -246,6 +252,12 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
     const int per = 2 * S + sT1 + sT2 + n * n + 2 * n;
     const int64_t cell0 = (int64_t)blockIdx.x * cpb;
     const int ncell = (int)min((int64_t)cpb, g.n_cells - cell0);
+    if (mask) {
+        // a block none of whose cells is set up now has nothing to do
+        bool any = false;
+        for (int ci = 0; ci < ncell; ++ci) any = any || live(cell0 + ci);
+        if (!any) return;
+    }
     double* bA = sm;
     double* bB = sm + cpb * S;
     double* T1 = sm + 2 * cpb * S;
@@ -270,6 +282,7 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
         const double arg = -vq[ci * S + j];
         const double om = wq * exp(arg < 700.0 ? arg : 700.0);
         vq[ci * S + j] = om;
+        if (!live(cell)) continue;
         if (omega64) omega64[cell * Qd + j] = om;
         if (omega32) omega32[cell * Qd + j] = (float)om;
     }
@@ -341,11 +354,11 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
         __syncthreads();
     }
     // -S_hat = D + beta M + C / alpha
-    const double ia = 1.0 / alpha;
     for (int e = threadIdx.x; e < ncell * n * n; e += blockDim.x) {
         const int ci = e / (n * n), r = e - ci * n * n;
         const int i = r / n, j = r % n;
         const int64_t cell = cell0 + ci;
+        const double ia = 1.0 / a_of(cell);
         const double* C = Cmat + (int64_t)cclass[cell] * n * n;
         double v = Dm[ci * n * n + r] + ia * C[r];
         if (i == j) {
@@ -354,7 +367,7 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
             int aa[3] = {i % P, (i / P) % P, i / (P * P)};
             double md = J;
             for (int k = 0; k < D; ++k) md *= tb.Mdiag[aa[k]];
-            v += beta * md;
+            v += b_of(cell) * md;
         }
         Dm[ci * n * n + r] = v;
     }
@@ -387,6 +400,7 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
         const int i = r / n, j = r % n;
         const double v = 0.5 * (Dm[ci * n * n + i * n + j] + Dm[ci * n * n + j * n + i]);
         const int64_t off = (cell0 + ci) * (int64_t)n * n + r;
+        if (!live(cell0 + ci)) continue;
         if (sinv64) sinv64[off] = v;
         if (sinv32) sinv32[off] = (float)v;
     }
@@ -626,6 +640,7 @@ __device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int 
     const int64_t rq = ep.bdiv > 0 ? bz / ep.bdiv : 0;
     if (done) done += rq * ep.dstride;
     if (ep.pstride) pidx = rq * ep.pstride + (pidx - (int64_t)bz * ((M + 15) / 16) * ((N + 15) / 16));
+    const double* eprm = ep.prm ? ep.prm + rq * ep.prmstride : nullptr;
     if (done && *done) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t b = bz;
@@ -691,7 +706,7 @@ __device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int 
                 lam = ep.l1[row] + ep.l0[col];
             else
                 lam = ep.l2[row] + ep.l0[col % ep.n0] + ep.l1[col / ep.n0];
-            s = s * (T)ep.prm[2] / lam;
+            s = s * (T)eprm[2] / lam;
         }
         C[(int64_t)row * ldc + col] = s;
         if (ep.dotv) part = (double)s * (double)ep.dotv[b * sC + (int64_t)row * ldc + col];
@@ -772,8 +787,10 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
     const int64_t rb = blockIdx.y;   // request of a batched launch
     if ((int)blockIdx.x < ng) {
         const int bx = blockIdx.x % gx, by = blockIdx.x / gx;
+        GemmEpi<T> e2 = ep;
+        if (e2.prm) e2.prm += rb * e2.prmstride;
         gemm_tile_body<T>(bx, by, 0, bx + (int64_t)gx * by, M, N, K, A + rb * sA, lda, 0, B, ldb,
-                          0, C + rb * sC, ldc, 0, done ? done + rb * bt.done : nullptr, ep, red,
+                          0, C + rb * sC, ldc, 0, done ? done + rb * bt.done : nullptr, e2, red,
                           rsum);
     } else {
         prec_psi_body<T>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv + rb * bt.sinv,
@@ -803,6 +820,7 @@ __global__ __launch_bounds__(256) void k_kr_start(int64_t n, KState* st0, const 
                                                   T* wcur, T* x, VecBatch bt) {
     __shared__ double red[4];
     __shared__ double bc;
+    if (bt.mask && !bt.mask[blockIdx.y]) return;   // a request not starting now
     {
         const int64_t rb = blockIdx.y, o = rb * bt.v;
         st0 += rb;
@@ -1097,7 +1115,8 @@ size_t setup_big_smem(const Geo& g, bool t2) {
 
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
-                  float* om32, double* s64, float* s32, hipStream_t s) {
+                  float* om32, double* s64, float* s32, hipStream_t s, const double* prm_req,
+                  const int* mask, int64_t cpr) {
     if (big) {
         const bool t2 = big == SETUP_HBM_T2;
         const size_t shm = setup_big_smem(g, t2);
@@ -1115,7 +1134,7 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, con
     size_t shm = setup_smem_per_cell(g) * cpb;
 #define HPG_S(DD)                                                                        \
     hipLaunchKernelGGL((k_setup<DD>), grid, blk, shm, s, g, tb, cpb, psi, alpha, beta, C, \
-                       cclass, om64, om32, s64, s32)
+                       cclass, om64, om32, s64, s32, prm_req, mask, cpr)
     if (g.d == 1) HPG_S(1);
     else if (g.d == 2) HPG_S(2);
     else HPG_S(3);

@@ -182,6 +182,7 @@ __global__ __launch_bounds__(256) void k_apply_tile(Geo g, URows<T> r0, URows<T>
         ypsi += rb * bt.yp;
         if (partial) partial += rb * bt.part;
         if (done) done += rb * bt.done;
+        if (prm) prm += rb * bt.prm;
     }
     if (done && *done) return;
     if (prm) {

@@ -352,25 +352,28 @@ class Problem:
 
 
 class Batch:
-    """nbatch independent obstacle problems on one mesh, solved together
-    (hpg_batch_*): every Krylov/Newton step of all of them is one launch."""
+    """Obstacle problems on one mesh solved together in nbatch slots
+    (hpg_batch_*): every Krylov/Newton step of the requests in the slots is
+    one launch, and a slot whose request finishes takes the next one."""
 
     def __init__(self, mesh, nbatch, device=0):
         self.mesh = mesh
         self.nb = int(nbatch)
+        self.nreq = self.nb
         h = ctypes.c_void_p()
         _check(load().hpg_create_batch(mesh.h, self.nb, device, ctypes.byref(h)))
         self.h = h
 
     def set_data(self, f_qp, phi_qp):
         """f and phi of every request at the mesh's quadrature points,
-        shape (nbatch, n_qp) (request-major)."""
+        shape (nrequests, n_qp) (request-major; any number of requests)."""
         f = np.ascontiguousarray(f_qp, dtype=np.float64).reshape(-1)
         ph = np.ascontiguousarray(phi_qp, dtype=np.float64).reshape(-1)
         _check(load().hpg_batch_set_data(self.h, _dptr(f), _dptr(ph), f.size))
+        self.nreq = f.size // self.mesh.n_qp
 
     def solve(self, opts=None, want_lambda=False):
-        m, nb = self.mesh, self.nb
+        m, nb = self.mesh, self.nreq
         u = np.zeros((nb, m.n_u))
         psi = np.zeros((nb, m.n_psi))
         lam = np.zeros((nb, m.n_psi)) if want_lambda else None

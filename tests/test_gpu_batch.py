@@ -160,3 +160,29 @@ def test_batch_rejects_unsupported_meshes():
         with pytest.raises(hpg.HpgError) as e:
             hpg.Batch(mesh, 2)
         assert e.value.status == hpg.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_requests_through_fewer_slots(precision):
+    # five requests through two slots: a slot whose request finishes takes the
+    # next one; every result equals its request solved alone
+    hpg = _hpg()
+    seeds = [3, 4, 5, 6, 7]
+    mesh = hpg.Mesh(2, [6, 6], 4)
+    x = mesh.quadrature_points()
+    fs = np.stack([_data(2, s)[0](x) for s in seeds])
+    ps = np.stack([_data(2, s)[1](x) for s in seeds])
+    b = hpg.Batch(mesh, 2)
+    b.set_data(fs, ps)
+    o = _opts(precision)
+    u, psi, lam, st = b.solve(o, want_lambda=True)
+    assert u.shape == (5, mesh.n_u) and len(st) == 5
+    for i in range(5):
+        b1 = hpg.Batch(mesh, 1)
+        b1.set_data(fs[i:i + 1], ps[i:i + 1])
+        u1, psi1, lam1, st1 = b1.solve(o, want_lambda=True)
+        log("  request", seeds[i], st[i].as_dict())
+        assert st[i].status == 0
+        assert np.array_equal(u1[0], u[i]) and np.array_equal(psi1[0], psi[i])
+        assert np.array_equal(lam1[0], lam[i])
+        assert st1[0].krylov_iters == st[i].krylov_iters
