@@ -327,6 +327,7 @@ void Batch::apply_prec(const T* r, T* z, double* pr, const int* done, int dstrid
             ++pass;
             T* dst = (pass == npass) ? z : ((src == t1) ? t2 : t1);
             dev::GemmEpi<T> ep{};
+            ep.ts = P.fdm_tile<T>();
             if (ph == 0 && k == d - 1) {
                 ep.scale_mode = d;
                 ep.n0 = M.n1[0];
@@ -434,6 +435,24 @@ template <typename T>
 void Batch::start(const std::vector<int>& entrants, double rtol, int maxit, hipStream_t s) {
     ensure_engine<T>();
     BKrylov<T>& K = kw<T>();
+    int& ts = P.fdm_ts<T>();
+    if (!ts) {
+        // the GEMM tile of this batch size, timed on zero vectors before the
+        // first Krylov graph is captured
+        const int* ign = mask2.as<int>();
+        HPG_HIP(hipMemsetAsync(mask2.p, 0, nb * sizeof(int), s));
+        HPG_HIP(hipMemsetAsync(K.vhat.p, 0, (size_t)nb * n * sizeof(T), s));
+        const bool tm = P.timing;
+        P.timing = false;
+        ts = pick_gemm_tile(
+            s,
+            [&](int c) {
+                ts = c;
+                apply_prec<T>(K.vhat.template as<T>(), K.Gq.template as<T>(), nullptr, ign, 1, s);
+            },
+            sizeof(T) == 4 ? "batched FP32 preconditioner" : "batched FP64 preconditioner");
+        P.timing = tm;
+    }
     T* b = rhs<T>();
     int* dm = mask.as<int>();
     int* skip = mask2.as<int>();

@@ -151,7 +151,14 @@ struct GemmEpi {
     int bdiv;
     int64_t pstride, dstride;
     int64_t prmstride;   // per-request prm at prm + request * prmstride
+    // block tile (16 ts) x (16 ts), ts = 1 or 2 (0: 1).  Every tile shape sums
+    // in the same order, so the choice changes the time and never the result
+    int ts;
 };
+template <typename T>
+inline int gemm_ts(const GemmEpi<T>& ep) {
+    return ep.ts == 2 ? 2 : 1;
+}
 template <typename T>
 void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,
                  int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, int batch,

@@ -597,11 +597,12 @@ __global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cp
 // ---------------------------------------------------------------------------
 // Tensor-axis GEMMs of the fast-diagonalisation A-block inverse on the matrix
 // cores: C_b = A_b (M x K) B_b (K x N), row-major, batch b = blockIdx.z.
-// One block of 4 waves owns a 16x16 tile of C; the waves split K in slabs of
-// 4 (v_mfma_*_16x16x4 operands: lane l supplies A[l%16][k+l/16] and
-// B[k+l/16][l%16]; the 16x16 result sits 4 values per lane at positions the
-// kernel reads off two index-valued MFMAs) and the four partial tiles are
-// summed in LDS in a fixed order.
+// A block of 4 waves owns a (16 TS) x (16 TS) tile of C (TS = 1 or 2); the
+// waves split K, each wave computes all TS x TS 16x16 sub-tiles over its part
+// of K (v_mfma_*_16x16x4 operands: lane l supplies A[l%16][k] and B[k][l%16]
+// for the k of its lane group; the 16x16 result sits 4 values per lane at
+// positions the kernel reads off two index-valued MFMAs) and the four partial
+// tiles are summed in LDS in a fixed order.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -626,20 +627,29 @@ struct Mfma<float> {
 // eigenvalues) (the eigen-space division of the fast diagonalisation) and/or
 // accumulate <C, dotv> per block into partial[block]
 
-// one 16x16 tile (bx, by) of batch bz; the partial of the fused dot goes to
-// partial[pidx]
-template <typename T, bool VH = false>
-__device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int M, int N, int K,
+// Summation order, the same for every tile shape: wave w takes the K slabs of
+// four k0 = 4 w + 16 u (u = 0, 1, ..; the four lanes of a row read four
+// consecutive k, so a row's loads share a cache line), MFMA k row kk adding
+// k0 + kk (zero beyond K), even steps into one accumulator and odd steps into
+// another;
+// a 16x16 output element is (w0 + w1) + (w2 + w3) of the four waves' sums, and
+// the fused dot's partials are one block_sum per 16x16 sub-tile.  So the tile
+// shape never changes a bit of the result: it is a free (tuned) choice.
+//
+// One (16 TS)^2 tile (bx, by) of batch bz; the partial of the fused dot of
+// 16x16 sub-tile (x, y) of the 16-grid goes to partial[(bz * gy + y) gx + x]
+// (pstride 0) or partial[request * pstride + y gx + x].
+template <typename T, int TS, bool VH = false>
+__device__ inline void gemm_tile_body(int bx, int by, int bz, int M, int N, int K,
                                       const T* __restrict__ A, int64_t lda, int64_t sA,
                                       const T* __restrict__ B, int64_t ldb, int64_t sB,
                                       T* __restrict__ C, int64_t ldc, int64_t sC,
                                       const int* __restrict__ done, const GemmEpi<T>& ep,
-                                      T (*red)[256], double* rsum,
-                                      const VhatSrc<T>* vs = nullptr) {
+                                      T* red, double* rsum, const VhatSrc<T>* vs = nullptr) {
+    using V = typename Mfma<T>::V;
     // batched requests: batch bz belongs to request bz / bdiv
     const int64_t rq = ep.bdiv > 0 ? bz / ep.bdiv : 0;
     if (done) done += rq * ep.dstride;
-    if (ep.pstride) pidx = rq * ep.pstride + (pidx - (int64_t)bz * ((M + 15) / 16) * ((N + 15) / 16));
     const double* eprm = ep.prm ? ep.prm + rq * ep.prmstride : nullptr;
     if (done && *done) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -647,88 +657,125 @@ __device__ inline void gemm_tile_body(int bx, int by, int bz, int64_t pidx, int 
     A += b * sA;
     B += b * sB;
     C += b * sC;
-    const int i0 = by * 16, j0 = bx * 16;
-    const int ar = i0 + (lane & 15), kk = lane >> 4, bc = j0 + (lane & 15);
-    const bool rok = ar < M, cok = bc < N;
-    typename Mfma<T>::V acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    // wave w takes the K slabs k0 = 4 w + 16 i; the operands of twelve slabs
-    // are loaded before their MFMAs, so K <= 192 costs one round trip
+    const int i0 = by * 16 * TS, j0 = bx * 16 * TS;
+    const int l16 = lane & 15, kk = lane >> 4;
+    V acc[2][TS][TS];
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int ta = 0; ta < TS; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < TS; ++tb) acc[e][ta][tb] = V{0, 0, 0, 0};
+    // the operands of twelve steps are loaded before their MFMAs, so K <= 192
+    // costs one round trip (the row offsets of a lane are fixed, so every load
+    // is the lane's base address plus a constant)
+    int ar[TS], bc[TS];
+    bool aok[TS], bok[TS];
+#pragma unroll
+    for (int t = 0; t < TS; ++t) {
+        ar[t] = i0 + 16 * t + l16;
+        bc[t] = j0 + 16 * t + l16;
+        aok[t] = ar[t] < M;
+        bok[t] = bc[t] < N;
+    }
     for (int k0 = 4 * w; k0 < K; k0 += 16 * 12) {
-        T a[12], bb[12];
+        T a[12][TS], bb[12][TS];
 #pragma unroll
         for (int u = 0; u < 12; ++u) {
-            const int ka = k0 + 16 * u + kk;
-            if (VH) {
-                // A = vhat (batch 0, no stride): formed here; the blocks of the
-                // first tile column store it (each element once)
-                T v = (T)0;
-                if (rok && ka < K) {
-                    const int64_t gi = (int64_t)ar * lda + ka;
-                    v = vs->at(gi);
-                    if (bx == 0) vs->out[gi] = v;
+            const int k = k0 + 16 * u + kk;
+            const bool kok = k < K;
+#pragma unroll
+            for (int t = 0; t < TS; ++t) {
+                const int64_t gi = (int64_t)ar[t] * lda + k;
+                if (VH) {
+                    // A = vhat (batch 0, no stride): formed here; the blocks of
+                    // the first tile column store it (each element once)
+                    T v = (T)0;
+                    if (kok && aok[t]) {
+                        v = vs->at(gi);
+                        if (bx == 0) vs->out[gi] = v;
+                    }
+                    a[u][t] = v;
+                } else {
+                    a[u][t] = (kok && aok[t]) ? A[gi] : (T)0;
                 }
-                a[u] = v;
-            } else {
-                a[u] = (rok && ka < K) ? A[(int64_t)ar * lda + ka] : (T)0;
+                bb[u][t] = (kok && bok[t]) ? B[(int64_t)k * ldb + bc[t]] : (T)0;
             }
-            bb[u] = (cok && ka < K) ? B[(int64_t)ka * ldb + bc] : (T)0;
         }
 #pragma unroll
-        for (int u = 0; u < 12; u += 2) {
-            acc0 = Mfma<T>::op(a[u], bb[u], acc0);
-            acc1 = Mfma<T>::op(a[u + 1], bb[u + 1], acc1);
-        }
+        for (int u = 0; u < 12; ++u)
+#pragma unroll
+            for (int ta = 0; ta < TS; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < TS; ++tb)
+                    acc[u & 1][ta][tb] = Mfma<T>::op(a[u][ta], bb[u][tb], acc[u & 1][ta][tb]);
     }
-    // where each of the 4 result values of this lane sits in the 16x16 tile:
+    // where each of the 4 result values of this lane sits in a 16x16 tile:
     // one MFMA with A[i][0] = i, B[0][j] = 1 gives D[i][j] = i, one with
     // A[i][0] = 1, B[0][j] = j gives D[i][j] = j (exact small integers)
-    typename Mfma<T>::V zero = {0, 0, 0, 0};
-    const typename Mfma<T>::V rid =
-        Mfma<T>::op(kk == 0 ? (T)(lane & 15) : (T)0, kk == 0 ? (T)1 : (T)0, zero);
-    const typename Mfma<T>::V cid =
-        Mfma<T>::op(kk == 0 ? (T)1 : (T)0, kk == 0 ? (T)(lane & 15) : (T)0, zero);
-    for (int v = 0; v < 4; ++v) {
-        const int ri = (int)rid[v] & 15, ci = (int)cid[v] & 15;
-        red[w][ri * 16 + ci] = acc0[v] + acc1[v];
-    }
+    const V zero = {0, 0, 0, 0};
+    const V rid = Mfma<T>::op(kk == 0 ? (T)l16 : (T)0, kk == 0 ? (T)1 : (T)0, zero);
+    const V cid = Mfma<T>::op(kk == 0 ? (T)1 : (T)0, kk == 0 ? (T)l16 : (T)0, zero);
+#pragma unroll
+    for (int ta = 0; ta < TS; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < TS; ++tb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ri = (int)rid[v] & 15, ci = (int)cid[v] & 15;
+                red[((w * TS + ta) * TS + tb) * 256 + ri * 16 + ci] =
+                    acc[0][ta][tb][v] + acc[1][ta][tb][v];
+            }
     __syncthreads();
     const int t = threadIdx.x, r = t >> 4, c = t & 15;
-    T s = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-    const int row = i0 + r, col = j0 + c;
-    const bool in = row < M && col < N;
-    double part = 0.0;
-    if (in) {
-        if (ep.scale_mode) {
-            T lam;
-            if (ep.scale_mode == 1)
-                lam = ep.l0[col];
-            else if (ep.scale_mode == 2)
-                lam = ep.l1[row] + ep.l0[col];
-            else
-                lam = ep.l2[row] + ep.l0[col % ep.n0] + ep.l1[col / ep.n0];
-            s = s * (T)eprm[2] / lam;
+    const int gx16 = (N + 15) >> 4, gy16 = (M + 15) >> 4;
+    const int64_t pbase = ep.pstride ? rq * ep.pstride + (b - rq * ep.bdiv) * gx16 * gy16
+                                     : b * gx16 * gy16;
+#pragma unroll
+    for (int ta = 0; ta < TS; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < TS; ++tb) {
+            const int sub = ta * TS + tb, st = TS * TS * 256;
+            T s = (red[sub * 256 + t] + red[st + sub * 256 + t]) +
+                  (red[2 * st + sub * 256 + t] + red[3 * st + sub * 256 + t]);
+            const int row = i0 + 16 * ta + r, col = j0 + 16 * tb + c;
+            const bool in = row < M && col < N;
+            double part = 0.0;
+            if (in) {
+                if (ep.scale_mode) {
+                    T lam;
+                    if (ep.scale_mode == 1)
+                        lam = ep.l0[col];
+                    else if (ep.scale_mode == 2)
+                        lam = ep.l1[row] + ep.l0[col];
+                    else
+                        lam = ep.l2[row] + ep.l0[col % ep.n0] + ep.l1[col / ep.n0];
+                    s = s * (T)eprm[2] / lam;
+                }
+                C[(int64_t)row * ldc + col] = s;
+                if (ep.dotv)
+                    part = (double)s * (double)ep.dotv[b * sC + (int64_t)row * ldc + col];
+            }
+            // sub-tiles beyond the matrix are not part of the 16-grid
+            if (ep.partial && i0 + 16 * ta < M && j0 + 16 * tb < N) {
+                const double tot = block_sum(part, rsum);
+                if (t == 0)
+                    ep.partial[pbase + (int64_t)(by * TS + ta) * gx16 + bx * TS + tb] = tot;
+            }
         }
-        C[(int64_t)row * ldc + col] = s;
-        if (ep.dotv) part = (double)s * (double)ep.dotv[b * sC + (int64_t)row * ldc + col];
-    }
-    if (ep.partial) {
-        const double tot = block_sum(part, rsum);
-        if (threadIdx.x == 0) ep.partial[pidx] = tot;
-    }
 }
 
-template <typename T>
+template <typename T, int TS>
 __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T* __restrict__ A,
                                                    int64_t lda, int64_t sA,
                                                    const T* __restrict__ B, int64_t ldb,
                                                    int64_t sB, T* __restrict__ C, int64_t ldc,
                                                    int64_t sC, const int* __restrict__ done,
                                                    GemmEpi<T> ep) {
-    __shared__ T red[4][256];
+    __shared__ T red[4 * TS * TS * 256];
     __shared__ double rsum[4];
-    gemm_tile_body<T>(blockIdx.x, blockIdx.y, blockIdx.z,
-                      blockIdx.x + gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z), M, N,
-                      K, A, lda, sA, B, ldb, sB, C, ldc, sC, done, ep, red, rsum);
+    gemm_tile_body<T, TS>(blockIdx.x, blockIdx.y, blockIdx.z, M, N, K, A, lda, sA, B, ldb, sB, C,
+                          ldc, sC, done, ep, red, rsum);
 }
 
 // The first fast-diagonalisation pass (one GEMM, batch 1) and the psi-block
@@ -740,7 +787,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T*
 // fixed order (delta, stored by block 0), then the GEMM tiles and the
 // psi-block cells read vhat = Gq - delta v_cur - gamma v_prev where they load
 // the residual, and store it to vhat (each element by exactly one block).
-template <typename T>
+template <typename T, int TS>
 __global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, const T* __restrict__ B,
                                                         int64_t ldb, T* __restrict__ C,
                                                         int64_t ldc, GemmEpi<T> ep, int gx,
@@ -752,7 +799,7 @@ __global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, con
                                                         const T* Gq, const T* vcur,
                                                         const T* vprev, T* vhat, int64_t n_u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ T red[4][256];
+    __shared__ T red[4 * TS * TS * 256];
     __shared__ double rsum[4];
     __shared__ double bc;
     if (st->done) return;
@@ -762,15 +809,15 @@ __global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, con
     const int ng = gx * gy;
     if ((int)blockIdx.x < ng) {
         const int bx = blockIdx.x % gx, by = blockIdx.x / gx;
-        gemm_tile_body<T, true>(bx, by, 0, bx + (int64_t)gx * by, M, N, K, nullptr, N, 0, B, ldb,
-                                0, C, ldc, 0, nullptr, ep, red, rsum, &vs);
+        gemm_tile_body<T, TS, true>(bx, by, 0, M, N, K, nullptr, N, 0, B, ldb, 0, C, ldc, 0,
+                                    nullptr, ep, red, rsum, &vs);
     } else {
         prec_psi_body<T, true>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv, nullptr,
                                z, ppart, nullptr, reinterpret_cast<T*>(smem_raw), rsum, &vs, n_u);
     }
 }
 
-template <typename T>
+template <typename T, int TS>
 __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T* __restrict__ A,
                                                    int64_t lda, const T* __restrict__ B,
                                                    int64_t ldb, T* __restrict__ C, int64_t ldc,
@@ -781,7 +828,7 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
                                                    double* __restrict__ ppart, int64_t sA,
                                                    int64_t sC, PsiBatch bt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ T red[4][256];
+    __shared__ T red[4 * TS * TS * 256];
     __shared__ double rsum[4];
     const int ng = gx * gy;
     const int64_t rb = blockIdx.y;   // request of a batched launch
@@ -789,9 +836,8 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
         const int bx = blockIdx.x % gx, by = blockIdx.x / gx;
         GemmEpi<T> e2 = ep;
         if (e2.prm) e2.prm += rb * e2.prmstride;
-        gemm_tile_body<T>(bx, by, 0, bx + (int64_t)gx * by, M, N, K, A + rb * sA, lda, 0, B, ldb,
-                          0, C + rb * sC, ldc, 0, done ? done + rb * bt.done : nullptr, e2, red,
-                          rsum);
+        gemm_tile_body<T, TS>(bx, by, 0, M, N, K, A + rb * sA, lda, 0, B, ldb, 0, C + rb * sC,
+                              ldc, 0, done ? done + rb * bt.done : nullptr, e2, red, rsum);
     } else {
         prec_psi_body<T>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv + rb * bt.sinv,
                          r + rb * bt.r, z + rb * bt.z, ppart ? ppart + rb * bt.part : nullptr,
@@ -1154,13 +1200,21 @@ template <typename T>
 void launch_gemm(int M, int N, int K, const T* A, int64_t lda, int64_t sA, const T* B,
                  int64_t ldb, int64_t sB, T* C, int64_t ldc, int64_t sC, int batch,
                  const int* done, const GemmEpi<T>& ep, hipStream_t s, const KernelEvents* ev) {
-    dim3 grid((N + 15) / 16, (M + 15) / 16, batch);
-    if (ev && ev->start)
-        hipExtLaunchKernelGGL((k_gemm_mfma<T>), grid, dim3(256), 0, s, ev->start, ev->stop, 0, M,
-                              N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, done, ep);
-    else
-        hipLaunchKernelGGL((k_gemm_mfma<T>), grid, dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb,
-                           sB, C, ldc, sC, done, ep);
+    const int e = 16 * gemm_ts(ep);
+    dim3 grid((N + e - 1) / e, (M + e - 1) / e, batch);
+#define HPG_G(TS)                                                                               \
+    do {                                                                                        \
+        if (ev && ev->start)                                                                    \
+            hipExtLaunchKernelGGL((k_gemm_mfma<T, TS>), grid, dim3(256), 0, s, ev->start,        \
+                                  ev->stop, 0, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, done, \
+                                  ep);                                                          \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_gemm_mfma<T, TS>), grid, dim3(256), 0, s, M, N, K, A, lda, sA, \
+                               B, ldb, sB, C, ldc, sC, done, ep);                               \
+    } while (0)
+    if (e == 32) HPG_G(2);
+    else HPG_G(1);
+#undef HPG_G
 }
 
 template <typename T>
@@ -1168,12 +1222,17 @@ void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, 
                       int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
                       int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s,
                       int64_t sA, int64_t sC, const PsiBatch& bt) {
-    const int gx = (N + 15) / 16, gy = (M + 15) / 16;
+    const int e = 16 * gemm_ts(ep);
+    const int gx = (N + e - 1) / e, gy = (M + e - 1) / e;
     const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
     const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
-    hipLaunchKernelGGL((k_gemm_prec<T>), dim3(gx * gy + np, (unsigned)bt.nb), dim3(256), shm, s,
-                       M, N, K, A, lda, B, ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb, sinv, r,
-                       z, ppart, sA, sC, bt);
+#define HPG_G(TS)                                                                                \
+    hipLaunchKernelGGL((k_gemm_prec<T, TS>), dim3(gx * gy + np, (unsigned)bt.nb), dim3(256), shm, \
+                       s, M, N, K, A, lda, B, ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb, sinv, \
+                       r, z, ppart, sA, sC, bt)
+    if (e == 32) HPG_G(2);
+    else HPG_G(1);
+#undef HPG_G
 }
 
 template <typename T>
@@ -1181,12 +1240,17 @@ void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep,
                            int n, int cpb, const T* sinv, T* z, double* ppart, KState* st,
                            const double* gpart, int npg, const T* Gq, const T* vcur,
                            const T* vprev, T* vhat, int64_t n_u, hipStream_t s) {
-    const int gx = (N + 15) / 16, gy = (M + 15) / 16;
+    const int e = 16 * gemm_ts(ep);
+    const int gx = (N + e - 1) / e, gy = (M + e - 1) / e;
     const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
     const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
-    hipLaunchKernelGGL((k_vhat_gemm_prec<T>), dim3(gx * gy + np), dim3(256), shm, s, M, N, N, B, N,
-                       C, N, ep, gx, gy, n_cells, n, cpb, sinv, z, ppart, st, gpart, npg, Gq, vcur,
-                       vprev, vhat, n_u);
+#define HPG_G(TS)                                                                                \
+    hipLaunchKernelGGL((k_vhat_gemm_prec<T, TS>), dim3(gx * gy + np), dim3(256), shm, s, M, N, N, \
+                       B, N, C, N, ep, gx, gy, n_cells, n, cpb, sinv, z, ppart, st, gpart, npg, Gq, \
+                       vcur, vprev, vhat, n_u)
+    if (e == 32) HPG_G(2);
+    else HPG_G(1);
+#undef HPG_G
 }
 
 template <typename T>

@@ -1,6 +1,7 @@
 // Problem state of the hpG library: device tables, data and work buffers.
 #pragma once
 
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -91,6 +92,9 @@ struct GraphKey {
         return std::tie(prec, chunk, b, x) < std::tie(o.prec, o.chunk, o.b, o.x);
     }
 };
+
+// HPG_GEMM_TILE as a tile (1 or 2), else fallback
+int forced_gemm_tile(int fallback);
 
 struct Problem {
     Mesh M;
@@ -188,6 +192,21 @@ struct Problem {
     void ensure_linearisation_buffers();
     bool fdm_ready = false;
     void ensure_fdm();
+    // block tile of the fast-diagonalisation GEMMs per Krylov precision (0:
+    // FP64, 1: FP32): 1 (16x16) or 2 (32x32), 0 until tuned on this problem
+    int gemm_ts[2] = {0, 0};
+    template <typename T>
+    int& fdm_ts() {
+        return gemm_ts[sizeof(T) == 4 ? 1 : 0];
+    }
+    // the tile in use: the tuned one, else HPG_GEMM_TILE, else 16x16
+    template <typename T>
+    int fdm_tile() {
+        const int t = fdm_ts<T>();
+        return t ? t : forced_gemm_tile(1);
+    }
+    template <typename T>
+    void tune_fdm(hipStream_t s);
 
     // operations (all enqueue on stream s)
     void setup(const double* d_psi, double alpha, double beta, int precision, hipStream_t s);
@@ -261,6 +280,12 @@ void upload(DBuf& d, const std::vector<T>& h) {
 }
 // solve options with defaults filled in and validated (throws Error)
 hpg_solve_opts checked_opts(const hpg_solve_opts* in);
+// The faster GEMM block tile (1: 16x16, 2: 32x32) for run(ts), the work of
+// one preconditioner apply enqueued on s, timed after a warm-up.  The tiles
+// sum in the same order, so this picks a time and never a result.
+// HPG_GEMM_TILE=16 or 32 forces a tile.
+int pick_gemm_tile(hipStream_t s, const std::function<void(int)>& run, const char* what);
+
 }  // namespace hpg
 
 struct hpg_problem {

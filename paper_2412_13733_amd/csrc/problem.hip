@@ -998,6 +998,7 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
             ++pass;
             T* dst = (pass == npass) ? z : ((src == t1) ? t2 : t1);
             dev::GemmEpi<T> ep{};
+            ep.ts = fdm_tile<T>();
             if (ph == 0 && k == d - 1) {
                 ep.scale_mode = d;   // 1, 2, 3 as documented in the kernel
                 ep.n0 = M.n1[0];
@@ -1045,6 +1046,65 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
     }
     if (part && !fuse_dot) dev::launch_dot<T>(M.n_u, z, r, part, np_dot, dn, s);
     if (par) join(s);
+}
+
+int forced_gemm_tile(int fallback) {
+    const char* e = std::getenv("HPG_GEMM_TILE");
+    if (!e) return fallback;
+    return std::atoi(e) == 32 ? 2 : 1;
+}
+
+int pick_gemm_tile(hipStream_t s, const std::function<void(int)>& run, const char* what) {
+    if (std::getenv("HPG_GEMM_TILE")) return forced_gemm_tile(1);
+    hipEvent_t e0, e1;
+    HPG_HIP(hipEventCreate(&e0));
+    HPG_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int pick = 1;
+    for (int ts : {1, 2}) {
+        run(ts);
+        HPG_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) run(ts);
+        HPG_HIP(hipEventRecord(e1, s));
+        HPG_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HPG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (std::getenv("HPG_TRACE"))
+            std::fprintf(stderr, "[hpg] %s: GEMM tile %dx%d %.1f us per preconditioner apply\n",
+                         what, 16 * ts, 16 * ts, 1e3 * ms / 3);
+        if (ms < best) {
+            best = ms;
+            pick = ts;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return pick;
+}
+
+// times one preconditioner apply with each GEMM tile on zero vectors (the
+// linearisation in place) and keeps the faster; runs before the first Krylov
+// graph of this precision is captured
+template <typename T>
+void Problem::tune_fdm(hipStream_t s) {
+    int& ts = fdm_ts<T>();
+    if (ts) return;
+    const int64_t n = M.n_u + M.n_psi;
+    DBuf tmp;
+    tmp.alloc((size_t)2 * n * sizeof(T));
+    HPG_HIP(hipMemsetAsync(tmp.p, 0, tmp.bytes, s));
+    T* r = tmp.as<T>();
+    const bool tm = timing;
+    timing = false;
+    ts = pick_gemm_tile(
+        s,
+        [&](int c) {
+            ts = c;
+            apply_prec<T>(r, r + n, nullptr, nullptr, s);
+        },
+        sizeof(T) == 4 ? "FP32 preconditioner" : "FP64 preconditioner");
+    timing = tm;
+    HPG_HIP(hipStreamSynchronize(s));
 }
 
 static double host_sum(const double* d_part, int n, hipStream_t s) {
@@ -1123,6 +1183,7 @@ int Problem::minres_on(const T* b, T* x, double rtol, int maxit, int chunk, hipS
     double* part = partial.as<double>();
     auto* st = kstate.as<dev::KState>();   // st[0], st[1]: state by iteration parity
     const int npP = np_dot + np_prec;
+    tune_fdm<T>(s);
     // z1 = M^{-1} b, gamma1^2 = <z1, b>
     apply_prec<T>(b, z, part, nullptr, s);
     dev::launch_kr_start<T>(n, st, part, npP, rtol, maxit, b, z, vcur, vprev, q, wprev, wcur, x,
@@ -1559,5 +1620,7 @@ template void Problem::minres_iterations<double>(int, int, double*&, double*&, d
 template void Problem::minres_iterations<float>(int, int, float*&, float*&, float*&, float*&,
                                                 float*, float*, float*, float*, hipStream_t);
 template int Problem::minres<float>(const float*, float*, double, int, int, hipStream_t);
+template void Problem::tune_fdm<double>(hipStream_t);
+template void Problem::tune_fdm<float>(hipStream_t);
 
 }  // namespace hpg

@@ -380,6 +380,7 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
                 ++pass;
                 T* dst = (pass == npass) ? cv : ((src == t1) ? t2 : t1);
                 dev::GemmEpi<T> ep{};
+                ep.ts = fdm_tile<T>();
                 if (ph == 0 && k == d - 1) {
                     ep.scale_mode = d;
                     ep.n0 = n1[0];

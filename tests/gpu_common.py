@@ -46,6 +46,13 @@ FP64_RES = 1e-13
 FP64_P = 5e-12
 FP32_G = 1e-6
 FP32_P = 1e-6
+# The psi-block of the FP64 preconditioner on cells whose Schur blocks have 169
+# to 343 unknowns (2-D degree 14, 3-D degrees 7 and 8, inverted in HBM): an
+# inverse is good to about n eps cond, and these blocks have condition numbers
+# 2.6e5 (2-D p = 14) and 3.6e4 to 1.2e5 (3-D p = 7, 8) on cell 0 by the
+# oracle.  Observed 2.4e-11 (2-D p = 14) and 1.5e-11 (3-D p = 7); bar ten
+# times the worst.
+FP64_P_COND = 2.5e-10
 
 
 def rel(a, b):

@@ -11,7 +11,7 @@ import pytest
 from oracle import lvpp, precond, mesh as OM
 import workloads as W
 
-from gpu_common import FP32_G, FP32_P, FP64_G, FP64_P, FP64_RES, build_pair, log, rel
+from gpu_common import FP32_G, FP32_P, FP64_G, FP64_P, FP64_P_COND, FP64_RES, build_pair, log, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +68,9 @@ def test_edge_operators(dim, m, p, breaks, kind):
         log("  prec", prec, "G", rel(yg[:mesh.n_u], yu), rel(yg[mesh.n_u:], yp),
             "P", rel(zg[:mesh.n_u], zu), rel(zg[mesh.n_u:], zp))
         assert rel(yg[:mesh.n_u], yu) < tol_g and rel(yg[mesh.n_u:], yp) < tol_g
-        assert rel(zg[:mesh.n_u], zu) < tol_p and rel(zg[mesh.n_u:], zp) < tol_p
+        # FP64 psi-blocks of 3-D degree >= 7: the conditioning bar
+        tol_pp = FP64_P_COND if prec == 0 and dim == 3 and p >= 7 else tol_p
+        assert rel(zg[:mesh.n_u], zu) < tol_p and rel(zg[mesh.n_u:], zp) < tol_pp
     # zero in, zero out
     y.fill_(1.0)
     prob.op_apply_G(torch.zeros_like(y), y)
