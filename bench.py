@@ -54,8 +54,10 @@ def parse():
     ap.add_argument("--probe-launches", type=int, default=20)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched solves and the batched apply probe B1")
-    ap.add_argument("--batch-n", type=int, default=64,
-                    help="requests of the headline mesh (seeds 0..n-1) in the batched solve")
+    ap.add_argument("--batch-n", type=int, default=32,
+                    help="slots of the batched solve of the headline mesh")
+    ap.add_argument("--batch-requests", type=int, default=0,
+                    help="requests (seeds 0..n-1) streamed through the slots (0: 3 x slots)")
     ap.add_argument("--b1-n", type=int, default=4096,
                     help="requests of 32x32 cells at p=2 in the batched apply probe B1")
     ap.add_argument("--no-3d", action="store_true",
@@ -516,21 +518,25 @@ def batch_probe(args, torch, hpg):
 
 
 def batch_bench(args, torch, hpg, W):
-    """Batched solves: args.batch_n requests of the headline mesh (32 x 32
-    cells, p = 6, paraboloid obstacle), request i with the sine forcing of
-    seed i, solved together (hpg_batch_solve), FP64 and mixed; request 0's
-    result against the single-problem path."""
+    """Batched solves of a request stream: args.batch_requests requests of the
+    headline mesh (32 x 32 cells, p = 6, paraboloid obstacle), request i with
+    the sine forcing of seed i, through args.batch_n slots of one
+    hpg_batch_solve (a slot whose request finishes takes the next one), FP64
+    and mixed; request 0's result against the single-problem path."""
     nb = args.batch_n
+    nreq = args.batch_requests if args.batch_requests > 0 else 3 * nb
     mesh = hpg.Mesh(2, [args.m, args.m], args.p)
     x = mesh.quadrature_points()
-    fs = np.stack([W.sine_forcing(i)[0](x) for i in range(nb)])
-    ps = np.stack([W.paraboloid_phi(x)] * nb)
+    fs = np.stack([W.sine_forcing(i)[0](x) for i in range(nreq)])
+    ps = np.stack([W.paraboloid_phi(x)] * nreq)
     n_dof = mesh.n_u + mesh.n_psi
     bt = hpg.Batch(mesh, nb)
     bt.set_data(fs, ps)
-    out = {"workload": "%d requests of the 2-D %dx%d p=%d obstacle problem (sine forcing seeds "
-                       "0..%d), solved together" % (nb, args.m, args.m, args.p, nb - 1),
-           "requests": nb}
+    out = {"workload": "stream of %d requests of the 2-D %dx%d p=%d obstacle problem (sine forcing "
+                       "seeds 0..%d) through %d slots of one batched solve"
+                       % (nreq, args.m, args.m, args.p, nreq - 1, nb),
+           "requests": nreq, "slots": nb,
+           "latency_note": "per-request service time, from taking a slot to finishing"}
     ref = {}
     for prec in ("fp64", "mixed"):
         kw = dict(precision=hpg.FP64 if prec == "fp64" else hpg.MIXED)
@@ -541,14 +547,20 @@ def batch_bench(args, torch, hpg, W):
         u, psi, _, st = bt.solve(opts)
         sec = time.perf_counter() - t0
         kry = sum(s_.krylov_iters for s_ in st)
-        ent = {"seconds": sec, "solves_per_s": nb / sec, "dof_krylov_per_s": n_dof * kry / sec,
+        lat = [s_.seconds for s_ in st]
+        ent = {"seconds": sec, "solves_per_s": nreq / sec, "dof_krylov_per_s": n_dof * kry / sec,
                "converged": int(sum(s_.status == 0 for s_ in st)),
-               "krylov_per_request": kry / nb,
-               "newton_per_request": sum(s_.newton_iters for s_ in st) / nb}
+               "krylov_per_request": kry / nreq,
+               "krylov_per_request_min_max": [min(s_.krylov_iters for s_ in st),
+                                              max(s_.krylov_iters for s_ in st)],
+               "newton_per_request": sum(s_.newton_iters for s_ in st) / nreq,
+               "p50_service_s": float(np.percentile(lat, 50)),
+               "p99_service_s": float(np.percentile(lat, 99))}
         ref[prec] = u
         out["path_" + prec] = ent
-        print("[bench] batch of %d, %s: %.2f s, %.1f solves/s" % (nb, prec, sec, nb / sec),
-              file=sys.stderr, flush=True)
+        print("[bench] batch stream of %d through %d slots, %s: %.2f s, %.2f solves/s"
+              % (nreq, nb, prec, sec, nreq / sec), file=sys.stderr, flush=True)
+    out["speedup_mixed_vs_fp64"] = out["path_mixed"]["solves_per_s"] / out["path_fp64"]["solves_per_s"]
     # request 0 through the single-problem path, and mixed against FP64
     prob = hpg.Problem(mesh, device=0)
     prob.set_forcing(fs[0])

@@ -129,6 +129,7 @@ struct Batch {
     std::vector<double> hprm;
     // linearisation (FP64 always; FP32 as well for mixed solves)
     DBuf om64, om32, s64, s32;
+    DBuf sflag;   // mixed: cells whose FP32 psi-block apply uses s64 (kFp32CondLimit)
     // MINRES engines: FP64 and FP32 work vectors, right-hand sides, solutions
     // and per-request states (two parities each)
     BKrylov<double> k64;
@@ -272,6 +273,7 @@ void Batch::setup(const double* d_psi, const int* d_mask, bool want32, hipStream
     if (want32) {
         om32.alloc(B * nq * sizeof(float));
         s32.alloc(B * ns * sizeof(float));
+        sflag.alloc(B * (size_t)ncell * sizeof(int));
     }
     // the cells of all requests in one launch: psi, the weights and the blocks
     // are request-major, the cell geometry repeats per request
@@ -281,7 +283,8 @@ void Batch::setup(const double* d_psi, const int* d_mask, bool want32, hipStream
     dev::launch_setup(gb, P.tab64.view(), P.cpb_setup, dev::SETUP_LDS, d_psi, 1.0, 0.0,
                       P.C.as<double>(), cclass_rep.as<int>(), om64.as<double>(),
                       want32 ? om32.as<float>() : nullptr, s64.as<double>(),
-                      want32 ? s32.as<float>() : nullptr, s, prm.as<double>(), d_mask, ncell);
+                      want32 ? s32.as<float>() : nullptr, s, prm.as<double>(), d_mask, ncell,
+                      want32 ? sflag.as<int>() : nullptr);
     P.tstop("setup", s);
     HPG_HIP(hipGetLastError());
 }
@@ -320,6 +323,12 @@ void Batch::apply_prec(const T* r, T* z, double* pr, const int* done, int dstrid
     pb.r = pb.z = n;
     pb.part = PS;
     pb.done = dstride;
+    pb.flag = ncell;
+    dev::PsiHi hi;
+    if (BSel<T>::prec == HPG_MIXED) {
+        hi.s64 = s64.as<double>();
+        hi.flag = sflag.as<int>();
+    }
     const T* src = r;
     int pass = 0;
     for (int ph = 0; ph < 2; ++ph) {
@@ -352,7 +361,7 @@ void Batch::apply_prec(const T* r, T* z, double* pr, const int* done, int dstrid
                 if (pass == 1) {
                     dev::launch_gemm_prec<T>(R, N, N, src, N, Bm, N, dst, N, done, ep, ncell, Pd,
                                              P.cpb_prec, sinv, r + nu, z + nu,
-                                             pr ? pr + P.np_dot : nullptr, s, ss, ds, pb);
+                                             pr ? pr + P.np_dot : nullptr, s, ss, ds, pb, hi);
                 } else {
                     const dev::KernelEvents ke = P.kernel_events("fdm");   // one GEMM per event pair
                     dev::launch_gemm<T>(R, N, N, src, N, ss, Bm, N, 0, dst, N, ds, nb, done, ep, s,

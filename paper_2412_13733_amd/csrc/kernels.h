@@ -79,7 +79,20 @@ struct TileBatch {
 struct PsiBatch {
     int nb = 1;
     int64_t sinv = 0, r = 0, z = 0, part = 0, done = 0;
+    int64_t flag = 0;   // per-request stride of the cell flags of PsiHi (cells)
 };
+// FP32 psi-block apply: the cells with flag[cell] != 0 (a Schur block too
+// ill-conditioned for an FP32 product, see kFp32CondLimit) are applied with
+// their FP64 inverse s64 and FP64 accumulation instead of the FP32 blocks
+struct PsiHi {
+    const double* s64 = nullptr;
+    const int* flag = nullptr;
+};
+// 1-norm condition number of -S_hat_K above which the FP32 path applies the
+// cell's block in FP64: an FP32 product with a block of condition c carries a
+// relative error up to about n eps_32 c, which turns <S^{-1} v, v> negative
+// (a MINRES breakdown) once it passes 1
+constexpr double kFp32CondLimit = 1e6;
 struct VecBatch {
     int nb = 1;
     int64_t v = 0, part = 0;   // vector stride, partial-sum stride (the state: st + b)
@@ -128,11 +141,12 @@ size_t setup_big_smem(const Geo& g, bool t2);
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
                   float* om32, double* s64, float* s32, hipStream_t s,
-                  const double* prm_req = nullptr, const int* mask = nullptr, int64_t cpr = 1);
+                  const double* prm_req = nullptr, const int* mask = nullptr, int64_t cpr = 1,
+                  int* sflag = nullptr);
 template <typename T>
 void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
                      double* partial, const int* done, hipStream_t s,
-                     const PsiBatch& bt = PsiBatch());
+                     const PsiBatch& bt = PsiBatch(), const PsiHi& hi = PsiHi());
 // C_b = A_b B_b (row-major, M x K times K x N), batch strides sA, sB, sC,
 // with the optional epilogues of GemmEpi
 template <typename T>
@@ -170,7 +184,8 @@ template <typename T>
 void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
                       int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
                       int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s,
-                      int64_t sA = 0, int64_t sC = 0, const PsiBatch& bt = PsiBatch());
+                      int64_t sA = 0, int64_t sC = 0, const PsiBatch& bt = PsiBatch(),
+                      const PsiHi& hi = PsiHi());
 template <typename T>
 void launch_dot(int64_t n, const T* a, const T* b, double* partial, int nblocks, const int* done,
                 hipStream_t s);
@@ -195,7 +210,8 @@ template <typename T>
 void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep, int64_t n_cells,
                            int n, int cpb, const T* sinv, T* z, double* ppart, KState* st,
                            const double* gpart, int npg, const T* Gq, const T* vcur,
-                           const T* vprev, T* vhat, int64_t n_u, hipStream_t s);
+                           const T* vprev, T* vhat, int64_t n_u, hipStream_t s,
+                           const PsiHi& hi = PsiHi());
 template <typename TI, typename TO>
 void launch_convert(int64_t n, const TI* a, TO* b, double scale, hipStream_t s);
 template <typename T>

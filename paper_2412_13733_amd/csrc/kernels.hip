@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
                                                double* __restrict__ sinv64,
                                                float* __restrict__ sinv32,
                                                const double* __restrict__ prm_req,
-                                               const int* __restrict__ mask, int64_t cpr) {
+                                               const int* __restrict__ mask, int64_t cpr,
+                                               int* __restrict__ sflag) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     const int n = g.Pd, q = g.q, P = g.P, Qd = g.Qd;
@@ -246,10 +247,11 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
     auto a_of = [&](int64_t cell) { return prm_req ? prm_req[4 * (cell / cpr)] : alpha; };
     auto b_of = [&](int64_t cell) { return prm_req ? prm_req[4 * (cell / cpr) + 1] : beta; };
     const int S = g.S;
-    // per cell: A, B (S each), T1 (q^(D-1) P^2), T2 (q P^4, D = 3), Dm (n^2), col/row (2n)
+    // per cell: A, B (S each), T1 (q^(D-1) P^2), T2 (q P^4, D = 3), Dm (n^2), col/row (2n),
+    // the 1-norm of -S_hat (1)
     const int sT1 = (D == 1) ? 1 : ((D == 2) ? q * P * P : q * q * P * P);
     const int sT2 = (D == 3) ? q * P * P * P * P : 1;
-    const int per = 2 * S + sT1 + sT2 + n * n + 2 * n;
+    const int per = 2 * S + sT1 + sT2 + n * n + 2 * n + 1;
     const int64_t cell0 = (int64_t)blockIdx.x * cpb;
     const int ncell = (int)min((int64_t)cpb, g.n_cells - cell0);
     if (mask) {
@@ -264,6 +266,23 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
     double* T2 = T1 + cpb * sT1;
     double* Dm = T2 + cpb * sT2;
     double* cr = Dm + cpb * n * n;
+    double* nrm = cr + cpb * 2 * n;
+    // 1-norm of each block of Dm into nrm[ci] (column sums staged in cr)
+    auto block_norm1 = [&]() {
+        for (int e = threadIdx.x; e < ncell * n; e += blockDim.x) {
+            const int ci = e / n, j = e - ci * n;
+            double cs = 0.0;
+            for (int i = 0; i < n; ++i) cs += fabs(Dm[ci * n * n + i * n + j]);
+            cr[ci * 2 * n + j] = cs;
+        }
+        __syncthreads();
+        for (int ci = threadIdx.x; ci < ncell; ci += blockDim.x) {
+            double m = 0.0;
+            for (int j = 0; j < n; ++j) m = fmax(m, cr[ci * 2 * n + j]);
+            nrm[ci] = m;
+        }
+        __syncthreads();
+    };
     for (int e = threadIdx.x; e < ncell * n; e += blockDim.x) {
         const int ci = e / n, a = e - ci * n;
         bA[ci * S + a] = psi[(cell0 + ci) * n + a];
@@ -372,6 +391,12 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
         Dm[ci * n * n + r] = v;
     }
     __syncthreads();
+    double nrm_s = 0.0;   // ||-S_hat||_1 of this thread's cell (flagging threads)
+    if (sflag) {
+        block_norm1();
+        nrm_s = threadIdx.x < ncell ? nrm[threadIdx.x] : 0.0;
+        __syncthreads();
+    }
     // in-place Gauss-Jordan inverse of each SPD block
     for (int k = 0; k < n; ++k) {
         for (int e = threadIdx.x; e < ncell * n; e += blockDim.x) {
@@ -394,6 +419,20 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
         }
         __syncthreads();
     }
+    // FP32 solves: flag the cells whose 1-norm condition number exceeds
+    // kFp32CondLimit (a non-finite one included); their FP64 inverse is kept
+    // for the FP32 apply.  Without an FP64 linearisation (omega64 null) only
+    // the flagged cells' inverses are written to sinv64.
+    if (sflag) {
+        block_norm1();
+        if (threadIdx.x < ncell) {
+            const int ci = threadIdx.x;
+            const int f = !(nrm_s * nrm[ci] <= kFp32CondLimit);
+            nrm[ci] = f ? 1.0 : 0.0;
+            if (live(cell0 + ci)) sflag[cell0 + ci] = f;
+        }
+        __syncthreads();
+    }
     for (int e = threadIdx.x; e < ncell * n * n; e += blockDim.x) {
         const int ci = e / (n * n), r = e - ci * n * n;
         // symmetrise (the exact inverse is symmetric)
@@ -401,7 +440,7 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
         const double v = 0.5 * (Dm[ci * n * n + i * n + j] + Dm[ci * n * n + j * n + i]);
         const int64_t off = (cell0 + ci) * (int64_t)n * n + r;
         if (!live(cell0 + ci)) continue;
-        if (sinv64) sinv64[off] = v;
+        if (sinv64 && (!sflag || omega64 || nrm[ci] != 0.0)) sinv64[off] = v;
         if (sinv32) sinv32[off] = (float)v;
     }
     (void)per;
@@ -531,7 +570,9 @@ __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, 
                                      const T* __restrict__ sinv, const T* __restrict__ r,
                                      T* __restrict__ z, double* __restrict__ partial,
                                      const int* __restrict__ done, T* Sb, double* red,
-                                     const VhatSrc<T>* vs = nullptr, int64_t voff = 0) {
+                                     const VhatSrc<T>* vs = nullptr, int64_t voff = 0,
+                                     const double* __restrict__ s64h = nullptr,
+                                     const int* __restrict__ flg = nullptr) {
     if (done && *done) return;
     const int nn = n * n;
     T* Rb = Sb + cpb * nn;
@@ -564,8 +605,18 @@ __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, 
         __syncthreads();
         for (int i = threadIdx.x; i < nc * n; i += 256) {
             const int ci = i / n, row = i - ci * n;
-            const T* S = Sb + ci * nn;
             const T* rr = Rb + ci * n;
+            if (flg && flg[cell0 + ci]) {
+                // a block too ill-conditioned for an FP32 product: its FP64
+                // inverse with FP64 sums (the dot from the FP64 product)
+                const double* S = s64h + (cell0 + ci) * (int64_t)nn;
+                double acc = 0.0;
+                for (int j = 0; j < n; ++j) acc += S[(int64_t)j * n + row] * (double)rr[j];
+                z[cell0 * n + i] = (T)acc;
+                part += acc * (double)rr[row];
+                continue;
+            }
+            const T* S = Sb + ci * nn;
             T acc = 0;
             for (int j = 0; j < n; ++j) acc += S[j * n + row] * rr[j];
             z[cell0 * n + i] = acc;
@@ -585,13 +636,16 @@ __global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cp
                                                   const T* __restrict__ sinv,
                                                   const T* __restrict__ r, T* __restrict__ z,
                                                   double* __restrict__ partial,
-                                                  const int* __restrict__ done, PsiBatch bt) {
+                                                  const int* __restrict__ done, PsiBatch bt,
+                                                  PsiHi hi) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
     const int64_t rb = blockIdx.y;
     prec_psi_body<T>(blockIdx.x, gridDim.x, n_cells, n, cpb, sinv + rb * bt.sinv, r + rb * bt.r,
                      z + rb * bt.z, partial ? partial + rb * bt.part : nullptr,
-                     done ? done + rb * bt.done : nullptr, reinterpret_cast<T*>(smem_raw), red);
+                     done ? done + rb * bt.done : nullptr, reinterpret_cast<T*>(smem_raw), red,
+                     nullptr, 0, hi.s64 ? hi.s64 + rb * bt.sinv : nullptr,
+                     hi.flag ? hi.flag + rb * bt.flag : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -797,7 +851,8 @@ __global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, con
                                                         double* __restrict__ ppart, KState* st,
                                                         const double* __restrict__ gpart, int npg,
                                                         const T* Gq, const T* vcur,
-                                                        const T* vprev, T* vhat, int64_t n_u) {
+                                                        const T* vprev, T* vhat, int64_t n_u,
+                                                        PsiHi hi) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ T red[4 * TS * TS * 256];
     __shared__ double rsum[4];
@@ -813,7 +868,8 @@ __global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, con
                                     nullptr, ep, red, rsum, &vs);
     } else {
         prec_psi_body<T, true>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv, nullptr,
-                               z, ppart, nullptr, reinterpret_cast<T*>(smem_raw), rsum, &vs, n_u);
+                               z, ppart, nullptr, reinterpret_cast<T*>(smem_raw), rsum, &vs, n_u,
+                               hi.s64, hi.flag);
     }
 }
 
@@ -826,7 +882,7 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
                                                    const T* __restrict__ sinv,
                                                    const T* __restrict__ r, T* __restrict__ z,
                                                    double* __restrict__ ppart, int64_t sA,
-                                                   int64_t sC, PsiBatch bt) {
+                                                   int64_t sC, PsiBatch bt, PsiHi hi) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ T red[4 * TS * TS * 256];
     __shared__ double rsum[4];
@@ -842,7 +898,8 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
         prec_psi_body<T>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv + rb * bt.sinv,
                          r + rb * bt.r, z + rb * bt.z, ppart ? ppart + rb * bt.part : nullptr,
                          done ? done + rb * bt.done : nullptr, reinterpret_cast<T*>(smem_raw),
-                         rsum);
+                         rsum, nullptr, 0, hi.s64 ? hi.s64 + rb * bt.sinv : nullptr,
+                         hi.flag ? hi.flag + rb * bt.flag : nullptr);
     }
 }
 
@@ -1149,7 +1206,7 @@ size_t setup_smem_per_cell(const Geo& g) {
     const int n = g.Pd, q = g.q, P = g.P;
     const int sT1 = (g.d == 1) ? 1 : ((g.d == 2) ? q * P * P : q * q * P * P);
     const int sT2 = (g.d == 3) ? q * P * P * P * P : 1;
-    return (size_t)(2 * g.S + sT1 + sT2 + n * n + 2 * n) * sizeof(double);
+    return (size_t)(2 * g.S + sT1 + sT2 + n * n + 2 * n + 1) * sizeof(double);
 }
 
 size_t setup_big_smem(const Geo& g, bool t2) {
@@ -1162,7 +1219,7 @@ size_t setup_big_smem(const Geo& g, bool t2) {
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
                   float* om32, double* s64, float* s32, hipStream_t s, const double* prm_req,
-                  const int* mask, int64_t cpr) {
+                  const int* mask, int64_t cpr, int* sflag) {
     if (big) {
         const bool t2 = big == SETUP_HBM_T2;
         const size_t shm = setup_big_smem(g, t2);
@@ -1180,7 +1237,7 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, con
     size_t shm = setup_smem_per_cell(g) * cpb;
 #define HPG_S(DD)                                                                        \
     hipLaunchKernelGGL((k_setup<DD>), grid, blk, shm, s, g, tb, cpb, psi, alpha, beta, C, \
-                       cclass, om64, om32, s64, s32, prm_req, mask, cpr)
+                       cclass, om64, om32, s64, s32, prm_req, mask, cpr, sflag)
     if (g.d == 1) HPG_S(1);
     else if (g.d == 2) HPG_S(2);
     else HPG_S(3);
@@ -1189,11 +1246,12 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, con
 
 template <typename T>
 void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
-                     double* partial, const int* done, hipStream_t s, const PsiBatch& bt) {
+                     double* partial, const int* done, hipStream_t s, const PsiBatch& bt,
+                     const PsiHi& hi) {
     const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
     const unsigned grid = (unsigned)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
     hipLaunchKernelGGL((k_prec_psi<T>), dim3(grid, (unsigned)bt.nb), dim3(256), shm, s, n_cells,
-                       n, cpb, sinv, r, z, partial, done, bt);
+                       n, cpb, sinv, r, z, partial, done, bt, hi);
 }
 
 template <typename T>
@@ -1221,7 +1279,7 @@ template <typename T>
 void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
                       int64_t ldc, const int* done, const GemmEpi<T>& ep, int64_t n_cells, int n,
                       int cpb, const T* sinv, const T* r, T* z, double* ppart, hipStream_t s,
-                      int64_t sA, int64_t sC, const PsiBatch& bt) {
+                      int64_t sA, int64_t sC, const PsiBatch& bt, const PsiHi& hi) {
     const int e = 16 * gemm_ts(ep);
     const int gx = (N + e - 1) / e, gy = (M + e - 1) / e;
     const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
@@ -1229,7 +1287,7 @@ void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, 
 #define HPG_G(TS)                                                                                \
     hipLaunchKernelGGL((k_gemm_prec<T, TS>), dim3(gx * gy + np, (unsigned)bt.nb), dim3(256), shm, \
                        s, M, N, K, A, lda, B, ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb, sinv, \
-                       r, z, ppart, sA, sC, bt)
+                       r, z, ppart, sA, sC, bt, hi)
     if (e == 32) HPG_G(2);
     else HPG_G(1);
 #undef HPG_G
@@ -1239,7 +1297,8 @@ template <typename T>
 void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep, int64_t n_cells,
                            int n, int cpb, const T* sinv, T* z, double* ppart, KState* st,
                            const double* gpart, int npg, const T* Gq, const T* vcur,
-                           const T* vprev, T* vhat, int64_t n_u, hipStream_t s) {
+                           const T* vprev, T* vhat, int64_t n_u, hipStream_t s,
+                           const PsiHi& hi) {
     const int e = 16 * gemm_ts(ep);
     const int gx = (N + e - 1) / e, gy = (M + e - 1) / e;
     const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
@@ -1247,7 +1306,7 @@ void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep,
 #define HPG_G(TS)                                                                                \
     hipLaunchKernelGGL((k_vhat_gemm_prec<T, TS>), dim3(gx * gy + np), dim3(256), shm, s, M, N, N, \
                        B, N, C, N, ep, gx, gy, n_cells, n, cpb, sinv, z, ppart, st, gpart, npg, Gq, \
-                       vcur, vprev, vhat, n_u)
+                       vcur, vprev, vhat, n_u, hi)
     if (e == 32) HPG_G(2);
     else HPG_G(1);
 #undef HPG_G
@@ -1314,14 +1373,14 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
                                      const T*, const double*, T*, double*, const int*, int,     \
                                      hipStream_t, const double*);                                \
     template void launch_prec_psi<T>(int64_t, int, int, const T*, const T*, T*, double*,         \
-                                     const int*, hipStream_t, const PsiBatch&);                  \
+                                     const int*, hipStream_t, const PsiBatch&, const PsiHi&);    \
     template void launch_gemm<T>(int, int, int, const T*, int64_t, int64_t, const T*, int64_t,    \
                                  int64_t, T*, int64_t, int64_t, int, const int*,                 \
                                  const GemmEpi<T>&, hipStream_t, const KernelEvents*);           \
     template void launch_gemm_prec<T>(int, int, int, const T*, int64_t, const T*, int64_t, T*,   \
                                       int64_t, const int*, const GemmEpi<T>&, int64_t, int, int,  \
                                       const T*, const T*, T*, double*, hipStream_t, int64_t,     \
-                                      int64_t, const PsiBatch&);                                 \
+                                      int64_t, const PsiBatch&, const PsiHi&);                   \
     template void launch_kr_start<T>(int64_t, KState*, const double*, int, double, int, const T*, \
                                      const T*, T*, T*, T*, T*, T*, T*, hipStream_t,              \
                                      const VecBatch&);                                           \
@@ -1333,7 +1392,7 @@ void launch_l2(const Geo& g, const PsiTabs<double>& tb, int cpb, const double* u
     template void launch_vhat_gemm_prec<T>(int, int, const T*, T*, const GemmEpi<T>&, int64_t,   \
                                            int, int, const T*, T*, double*, KState*,             \
                                            const double*, int, const T*, const T*, const T*, T*, \
-                                           int64_t, hipStream_t);                                \
+                                           int64_t, hipStream_t, const PsiHi&);                  \
     template void launch_axpy_to<T>(int64_t, const double*, double, const T*, double*,          \
                                     hipStream_t);                                                \
     template void launch_dot<T>(int64_t, const T*, const T*, double*, int, const int*, hipStream_t);

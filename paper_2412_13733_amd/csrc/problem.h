@@ -170,6 +170,7 @@ struct Problem {
     int precision = HPG_FP64;
     bool linearised = false;
     DBuf om64, om32, sinv64, sinv32;
+    DBuf sflag;   // mixed: per cell, 1 if its psi-block is applied from sinv64 (kFp32CondLimit)
     // Krylov
     KrylovWork<double> kw64;
     KrylovWork<float> kw32;
@@ -215,6 +216,18 @@ struct Problem {
     template <typename T>
     void apply_prec(const T* r, T* z, double* partial, const int* done, hipStream_t s,
                     const VhatIn<T>* vin = nullptr);
+    // the FP64 blocks of the ill-conditioned cells for an FP32 psi-block apply
+    // (uniform-degree obstacle meshes with LDS-formed blocks; empty otherwise)
+    bool flags_psi() const { return !M.hp && !gradient && !setup_mode; }
+    template <typename T>
+    dev::PsiHi psi_hi() const {
+        dev::PsiHi h;
+        if (sizeof(T) == 4 && flags_psi() && sflag.p) {
+            h.s64 = sinv64.as<double>();
+            h.flag = sflag.as<int>();
+        }
+        return h;
+    }
     template <typename T>
     int minres(const T* b, T* x, double rtol, int maxit, int chunk, hipStream_t s);
     template <typename T>

@@ -139,6 +139,7 @@ size_t footprint_bytes(const Mesh& M, int precision) {
         // FP64 operator, Krylov vectors and solution of the steps that fall back to FP64
         b += 8.0 * n + 8.0 * (7 * n + 2 * nu);
         b += 8.0 * nc * (double)M.Qd * npair + 8.0 * nc * blk;
+        b += 4.0 * nc;                                                 // ill-conditioned cell flags
     }
     return (size_t)(1.15 * b) + ((size_t)8 << 20);
 }
@@ -774,9 +775,15 @@ void Problem::ensure_linearisation_buffers() {
     } else {
         om32.alloc(nq * sizeof(float));
         sinv32.alloc(ns * sizeof(float));
-        // blocks too large for LDS are formed and inverted in FP64 in place
+        // blocks too large for LDS are formed and inverted in FP64 in place;
+        // LDS-formed obstacle blocks keep the FP64 inverses of the cells too
+        // ill-conditioned for an FP32 product
         if ((gradient && dev::setup_grad_in_hbm(geo)) || (!gradient && setup_mode))
             sinv64.alloc(ns * sizeof(double));
+        if (flags_psi()) {
+            sinv64.alloc(ns * sizeof(double));
+            sflag.alloc((size_t)M.n_cells * sizeof(int));
+        }
     }
 }
 
@@ -865,12 +872,14 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
                                (prec == HPG_FP64 || hbm) ? sinv64.as<double>() : nullptr,
                                prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
     } else {
+        const bool fl = prec != HPG_FP64 && flags_psi();
         dev::launch_setup(geo, tab64.view(), cpb_setup, setup_mode, d_psi, alpha, beta,
                           C.as<double>(), cclass.as<int>(),
                           prec == HPG_FP64 ? om64.as<double>() : nullptr,
                           prec == HPG_FP64 ? nullptr : om32.as<float>(),
-                          (prec == HPG_FP64 || setup_mode) ? sinv64.as<double>() : nullptr,
-                          prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s);
+                          (prec == HPG_FP64 || setup_mode || fl) ? sinv64.as<double>() : nullptr,
+                          prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s, nullptr, nullptr, 1,
+                          fl ? sflag.as<int>() : nullptr);
     }
     tstop("setup", s);
     HPG_HIP(hipGetLastError());
@@ -982,7 +991,8 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                                         np_prec, dn, s_psi);
         else
             dev::launch_prec_psi<T>(M.n_cells, (int)M.psi_per_cell, cpb_prec, Sel<T>::sinv(*this),
-                                    r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr, dn, s_psi);
+                                    r + M.n_u, z + M.n_u, part ? part + np_dot : nullptr, dn, s_psi,
+                                    dev::PsiBatch(), psi_hi<T>());
         tstop("prec_psi", s_psi);
     }
     // A-block: z_u = (alpha A)^{-1} r_u by fast diagonalisation: d forward
@@ -1023,12 +1033,13 @@ void Problem::apply_prec(const T* r, T* z, double* part, const int* dn, hipStrea
                                                   Sel<T>::sinv(*this), z + M.n_u,
                                                   part ? part + np_dot : nullptr, vin->st,
                                                   vin->gpart, vin->npg, vin->Gq, vin->vcur,
-                                                  vin->vprev, vin->vhat, M.n_u, s);
+                                                  vin->vprev, vin->vhat, M.n_u, s, psi_hi<T>());
                 else if (merged && pass == 1)
                     dev::launch_gemm_prec<T>(R, N, N, src, N, Bm, N, dst, N, dn, ep, M.n_cells,
                                              (int)M.psi_per_cell, cpb_prec, Sel<T>::sinv(*this),
                                              r + M.n_u, z + M.n_u,
-                                             part ? part + np_dot : nullptr, s);
+                                             part ? part + np_dot : nullptr, s, 0, 0,
+                                             dev::PsiBatch(), psi_hi<T>());
                 else
                     dev::launch_gemm<T>(R, N, N, src, N, 0, Bm, N, 0, dst, N, 0, 1, dn, ep, s,
                                         &ke);
