@@ -68,6 +68,18 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="prefix of the 512-request serving stream to run")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving stream: one JSON line with its section")
+    ap.add_argument("--serve-paths", default="fp64x1,fp64,mixed,poisson",
+                    help="serving runs: fp64x1 (one slot), fp64 and mixed (the slots, all "
+                         "requests at once), poisson (mixed, the arrival times)")
+    ap.add_argument("--serve-stratified", action="store_true",
+                    help="serve only the stratified sample of the 512-request stream "
+                         "(workloads.stratified_sample: 36 requests)")
+    ap.add_argument("--serve-save", default="",
+                    help="directory: u and stats of a stratified sample of the stream "
+                         "(workloads.stratified_sample) per run, for the oracle check "
+                         "tests/check_serving_stream.py")
     ap.add_argument("--serve-chunk", type=int, default=16,
                     help="MINRES iterations per captured chunk of a serving request")
     ap.add_argument("--no-hp", action="store_true",
@@ -104,6 +116,20 @@ def counters_run(args, torch, hpg, W):
         for _ in range(5):
             prob.op_apply_prec(v, w)
             prob.op_apply_G(v, w)
+    # the fast-diagonalisation passes with the 32x32 block tile too (the tile
+    # of a problem without a Krylov solve follows HPG_GEMM_TILE, else 16x16)
+    keep = os.environ.get("HPG_GEMM_TILE")
+    os.environ["HPG_GEMM_TILE"] = "32"
+    for prec, dt in ((hpg.MIXED, torch.float32), (hpg.FP64, torch.float64)):
+        prob.op_setup(psi, 4.0, 0.0, precision=prec)
+        v = torch.randn(n, dtype=dt, device="cuda", generator=g)
+        w = torch.empty_like(v)
+        for _ in range(5):
+            prob.op_apply_prec(v, w)
+    if keep is None:
+        del os.environ["HPG_GEMM_TILE"]
+    else:
+        os.environ["HPG_GEMM_TILE"] = keep
     torch.cuda.synchronize()
     prob.set_kernel_timing(None)
     del prob
@@ -329,16 +355,20 @@ def apply_probe(args, torch, hpg, dim, m, p, copy_gbs):
 
 # ---- serving: the Poisson request stream (2-D n x n cells, n in 8..64,
 # p in 2..10, 25% gradient constraint) through the continuous-batching server
-def serving_requests(hpg, W, n_req):
+def serving_requests(hpg, W, n_req, only=None):
+    """The first n_req requests of the 512-request stream (or the listed ones)."""
     arrivals, reqs = W.serving_stream(512, 40.0, 12345)
+    idx = list(only) if only is not None else list(range(n_req))
+    arrivals = arrivals[idx]
+    reqs = [reqs[i] for i in idx]
     built = []
-    for r in reqs[:n_req]:
+    for r in reqs:
         kind = hpg.GRADIENT if r["kind"] == "gradient" else hpg.OBSTACLE
         mesh = hpg.Mesh(2, [r["n"], r["n"]], r["p"], constraint=kind)
         x = mesh.quadrature_points()
         f, phi = W.request_data(r)
         built.append((mesh, f(x), phi(x), r))
-    return arrivals[:n_req], built
+    return arrivals, built
 
 
 SERVE_KRYLOV_CHUNK = 16   # MINRES iterations per captured chunk of a serving request
@@ -347,13 +377,17 @@ SERVE_KRYLOV_CHUNK = 16   # MINRES iterations per captured chunk of a serving re
 def request_opts(hpg, r, precision):
     """Obstacle requests: alpha_k = 2^k to the 1e-10 proximal tolerance.
     Gradient requests: the paper's schedule for that problem class,
-    alpha_1 = 2^-7, alpha_{k+1} = min(sqrt(2) alpha_k, 4), 20 steps.  A Newton
-    stall is accepted at error 1e-8 (the serving accuracy target); up to 100
-    Newton steps per subproblem (high-degree requests need ~35 damped steps
-    before the quadratic phase)."""
-    kw = dict(stall_tol=1e-8, max_newton=100, krylov_chunk=SERVE_KRYLOV_CHUNK)
+    alpha_1 = 2^-7, alpha_{k+1} = min(sqrt(2) alpha_k, 4), 20 steps, with up
+    to 20000 MINRES iterations per Newton step (P_D is weak once the gradient
+    constraint is active: a cap of 2000 stalls Newton at errors ~3e-3 on large
+    high-degree requests).  A Newton stall is accepted at error 1e-8 (the
+    serving accuracy target); up to 200 Newton steps per subproblem (large
+    high-degree obstacle requests need over 100 in their second subproblem,
+    whose linear tail cuts the error by ~e per step)."""
+    kw = dict(stall_tol=1e-8, max_newton=200, krylov_chunk=SERVE_KRYLOV_CHUNK)
     if r["kind"] == "gradient":
-        kw.update(alpha0=2.0 ** -7, alpha_factor=2.0 ** 0.5, alpha_max=4.0, fixed_prox_steps=20)
+        kw.update(alpha0=2.0 ** -7, alpha_factor=2.0 ** 0.5, alpha_max=4.0, fixed_prox_steps=20,
+                  max_krylov=20000)
     if precision == hpg.MIXED:
         kw.update(precision=hpg.MIXED, newton_tol=1e-10, krylov_rtol=1e-6)
     return hpg.default_opts(**kw)
@@ -389,7 +423,17 @@ def serve(hpg, built, arrivals, slots, precision, label):
 
 
 def serving_bench(args, hpg, W):
-    arrivals, built = serving_requests(hpg, W, args.serve_requests)
+    if args.serve_stratified:
+        # only the stratified sample of the whole stream, in stream order
+        _, allreqs = W.serving_stream(512, 40.0, 12345)
+        index = W.stratified_sample(allreqs)
+        arrivals, built = serving_requests(hpg, W, 0, only=index)
+        sample = list(range(len(built)))
+    else:
+        arrivals, built = serving_requests(hpg, W, args.serve_requests)
+        index = list(range(len(built)))
+        sample = W.stratified_sample([r for _, _, _, r in built])
+    paths = [x.strip() for x in args.serve_paths.split(",") if x.strip()]
 
     def summary(res, stats):
         ok = [st.status == 0 for _, st, _ in res]
@@ -399,42 +443,70 @@ def serving_bench(args, hpg, W):
                 "p50_latency_s": stats["p50_latency_s"], "p99_latency_s": stats["p99_latency_s"],
                 "max_running": stats["max_running"], "span_s": stats["span_s"],
                 "hbm_peak_reserved_GB": stats["hbm_peak_reserved"] / 1e9,
-                "fp64_fallbacks": int(sum(st.fp64_fallbacks for _, st, _ in res))}
+                "fp64_fallbacks": int(sum(st.fp64_fallbacks for _, st, _ in res)),
+                "fp64_recomputations": int(sum(st.fp64_recomputations for _, st, _ in res))}
 
-    seq, s_seq = serve(hpg, built, None, 1, hpg.FP64, "fp64 x1")
-    b64, s_b64 = serve(hpg, built, None, args.serve_slots, hpg.FP64,
-                       "fp64 x%d" % args.serve_slots)
-    bat, s_bat = serve(hpg, built, None, args.serve_slots, hpg.MIXED,
-                       "mixed x%d" % args.serve_slots)
-    live, s_live = serve(hpg, built, arrivals, args.serve_slots, hpg.MIXED, "mixed poisson")
-    # accuracy of the mixed path against the FP64 path over the requests both converged on
-    errs = [float(np.linalg.norm(ub - us) / max(np.linalg.norm(us), 1e-300))
-            for (ub, sb, _), (us, ss, _) in zip(bat, seq) if sb.status == 0 and ss.status == 0]
-    differ = [i for i, (a, b) in enumerate(zip(bat, live)) if not np.array_equal(a[0], b[0])]
+    def save(label, res):
+        if not args.serve_save:
+            return
+        os.makedirs(args.serve_save, exist_ok=True)
+        for i in sample:
+            u, st, info = res[i]
+            np.savez(os.path.join(args.serve_save, "req%03d_%s.npz" % (index[i], label)), u=u,
+                     stats=json.dumps(st.as_dict()), request=json.dumps(built[i][3]))
+
+    runs = {}
+    if "fp64x1" in paths:
+        runs["fp64_sequential"] = serve(hpg, built, None, 1, hpg.FP64, "fp64 x1")
+    if "fp64" in paths:
+        runs["fp64_batched"] = serve(hpg, built, None, args.serve_slots, hpg.FP64,
+                                     "fp64 x%d" % args.serve_slots)
+        save("fp64", runs["fp64_batched"][0])
+    if "mixed" in paths:
+        runs["mixed_batched"] = serve(hpg, built, None, args.serve_slots, hpg.MIXED,
+                                      "mixed x%d" % args.serve_slots)
+        save("mixed", runs["mixed_batched"][0])
+    if "poisson" in paths:
+        runs["mixed_poisson"] = serve(hpg, built, arrivals, args.serve_slots, hpg.MIXED,
+                                      "mixed poisson")
     kinds = [r["kind"] for _, _, _, r in built]
-    return {
-        "workload": "serving stream: first %d of 512 requests, Poisson arrivals 40/s (seed "
+    out = {
+        "workload": "serving stream: %s of 512 requests, Poisson arrivals 40/s (seed "
                     "12345); 2-D n x n cells, n in 8..64, p in 2..10, f sine family and "
                     "paraboloid / dip obstacle, 25%% gradient constraint with phi ~ U[0.2, 0.5]"
-                    % len(built),
+                    % ("the stratified sample (%d)" % len(built) if args.serve_stratified
+                       else "the first %d" % len(built)),
         "gradient_requests": kinds.count("gradient"),
         "slots": args.serve_slots,
-        "fp64_sequential": summary(seq, s_seq),
-        "fp64_batched": summary(b64, s_b64),
-        "mixed_batched": summary(bat, s_bat),
-        "mixed_poisson": summary(live, s_live),
-        # mixed x slots over FP64 x1 mixes precision and concurrency; the two
-        # ratios after it separate them
-        "speedup_batched_mixed_vs_fp64": s_bat["solves_per_s"] / max(s_seq["solves_per_s"], 1e-300),
-        "speedup_mixed_vs_fp64_same_slots": s_bat["solves_per_s"] / max(s_b64["solves_per_s"], 1e-300),
-        "speedup_fp64_slots_vs_one": s_b64["solves_per_s"] / max(s_seq["solves_per_s"], 1e-300),
-        "accuracy_note": "relative l2 distance of the mixed-path u to the FP64-path u, over the "
-                         "requests both paths converged on",
-        "max_rel_l2_mixed_vs_fp64": max(errs) if errs else None,
-        "median_rel_l2_mixed_vs_fp64": float(np.median(errs)) if errs else None,
-        "poisson_equals_batched": not differ,
-        "poisson_differs_at": differ,
     }
+    for k, (res, st) in runs.items():
+        out[k] = summary(res, st)
+    sps = {k: st["solves_per_s"] for k, (res, st) in runs.items()}
+    # mixed x slots over FP64 x1 mixes precision and concurrency; the two
+    # ratios after it separate them
+    if "mixed_batched" in sps and "fp64_sequential" in sps:
+        out["speedup_batched_mixed_vs_fp64"] = sps["mixed_batched"] / max(sps["fp64_sequential"], 1e-300)
+    if "mixed_batched" in sps and "fp64_batched" in sps:
+        out["speedup_mixed_vs_fp64_same_slots"] = sps["mixed_batched"] / max(sps["fp64_batched"], 1e-300)
+    if "fp64_batched" in sps and "fp64_sequential" in sps:
+        out["speedup_fp64_slots_vs_one"] = sps["fp64_batched"] / max(sps["fp64_sequential"], 1e-300)
+    ref = runs.get("fp64_sequential", runs.get("fp64_batched"))
+    if "mixed_batched" in runs and ref is not None:
+        errs = [float(np.linalg.norm(ub - us) / max(np.linalg.norm(us), 1e-300))
+                for (ub, sb, _), (us, ss, _) in zip(runs["mixed_batched"][0], ref[0])
+                if sb.status == 0 and ss.status == 0]
+        out["accuracy_note"] = ("relative l2 distance of the mixed-path u to the FP64-path u, over "
+                                "the requests both paths converged on")
+        out["max_rel_l2_mixed_vs_fp64"] = max(errs) if errs else None
+        out["median_rel_l2_mixed_vs_fp64"] = float(np.median(errs)) if errs else None
+    if "mixed_batched" in runs and "mixed_poisson" in runs:
+        differ = [i for i, (a, b) in enumerate(zip(runs["mixed_batched"][0], runs["mixed_poisson"][0]))
+                  if not np.array_equal(a[0], b[0])]
+        out["poisson_equals_batched"] = not differ
+        out["poisson_differs_at"] = differ
+    if args.serve_save:
+        out["saved_sample"] = [index[i] for i in sample]
+    return out
 
 
 HP_DEGREES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
@@ -645,6 +717,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_run(args, torch, hpg, W)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(args, hpg, W)}), flush=True)
         return
     if args.hp_only:
         print(json.dumps({"hp_dip_64x64": hp_bench(args, torch, hpg, W)}), flush=True)

@@ -119,3 +119,23 @@ def request_data(req):
     if req["phi"] == "dip":
         return w2d_dip(req["seed"])
     return f, paraboloid_phi
+
+
+def serving_strata(req):
+    """Stratum of a serving request: (constraint and obstacle kind, degree band)."""
+    kind = req["kind"] if req["kind"] == "gradient" else "obstacle-" + req["phi"]
+    band = "p2-4" if req["p"] <= 4 else ("p5-7" if req["p"] <= 7 else "p8-10")
+    return kind, band
+
+
+def stratified_sample(reqs, per_stratum=4):
+    """Indices of the per_stratum smallest-mesh requests (ties: lower index) of
+    each (kind, degree band) stratum of a serving stream, sorted."""
+    groups = {}
+    for i, r in enumerate(reqs):
+        groups.setdefault(serving_strata(r), []).append(i)
+    out = []
+    for key in sorted(groups):
+        idx = sorted(groups[key], key=lambda i: (reqs[i]["n"], i))
+        out.extend(idx[:per_stratum])
+    return sorted(out)
