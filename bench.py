@@ -56,6 +56,8 @@ def parse():
                     help="skip the batched solves and the batched apply probe B1")
     ap.add_argument("--batch-n", type=int, default=32,
                     help="slots of the batched solve of the headline mesh")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched stream: one JSON line with its section")
     ap.add_argument("--batch-requests", type=int, default=0,
                     help="requests (seeds 0..n-1) streamed through the slots (0: 3 x slots)")
     ap.add_argument("--b1-n", type=int, default=4096,
@@ -717,6 +719,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_run(args, torch, hpg, W)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": batch_bench(args, torch, hpg, W)}), flush=True)
         return
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(args, hpg, W)}), flush=True)

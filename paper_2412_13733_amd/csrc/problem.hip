@@ -1070,27 +1070,30 @@ int pick_gemm_tile(hipStream_t s, const std::function<void(int)>& run, const cha
     hipEvent_t e0, e1;
     HPG_HIP(hipEventCreate(&e0));
     HPG_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    int pick = 1;
-    for (int ts : {1, 2}) {
-        run(ts);
-        HPG_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r) run(ts);
-        HPG_HIP(hipEventRecord(e1, s));
-        HPG_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HPG_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (std::getenv("HPG_TRACE"))
-            std::fprintf(stderr, "[hpg] %s: GEMM tile %dx%d %.1f us per preconditioner apply\n",
-                         what, 16 * ts, 16 * ts, 1e3 * ms / 3);
-        if (ms < best) {
-            best = ms;
-            pick = ts;
+    // the tiles alternate over several rounds and each keeps its best round,
+    // so a clock still ramping up from idle does not favour the later one
+    float best[3] = {1e30f, 1e30f, 1e30f};
+    run(1);
+    run(2);
+    for (int round = 0; round < 5; ++round) {
+        for (int ts : {1, 2}) {
+            HPG_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < 3; ++r) run(ts);
+            HPG_HIP(hipEventRecord(e1, s));
+            HPG_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HPG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            best[ts] = std::min(best[ts], ms);
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return pick;
+    if (std::getenv("HPG_TRACE"))
+        std::fprintf(stderr, "[hpg] %s: GEMM tile 16x16 %.1f us, 32x32 %.1f us per apply\n", what,
+                     1e3 * best[1] / 3, 1e3 * best[2] / 3);
+    // the 32x32 tile only when clearly faster (the 16x16 one has 4x the blocks,
+    // the safer choice where the two are within timing noise)
+    return best[2] < 0.95f * best[1] ? 2 : 1;
 }
 
 // times one preconditioner apply with each GEMM tile on zero vectors (the
