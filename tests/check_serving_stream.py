@@ -7,9 +7,11 @@ requests' options of bench.request_opts: obstacle alpha_k = 2^k to the 1e-10
 proximal tolerance; gradient the paper's schedule over 20 steps; a Newton stall
 accepted at 1e-8; up to 200 Newton steps).
 
-    python tests/check_serving_stream.py DIR [OUT.md]
+    python tests/check_serving_stream.py DIR [OUT.md [MAX_DOF]]
 
-Prints one line per request and path; with OUT.md writes the table there."""
+Prints one line per request and path as the oracle finishes it (smallest
+first); with OUT.md keeps the table there up to date; requests with more than
+MAX_DOF unknowns (n_u + n_psi) are listed as not checked."""
 import glob
 import json
 import os
@@ -58,37 +60,61 @@ def check(idx_files):
     return rows
 
 
-def main():
-    d = sys.argv[1]
-    out_md = sys.argv[2] if len(sys.argv) > 2 else None
-    files = sorted(glob.glob(os.path.join(d, "req*_*.npz")))
-    by_idx = {}
-    for fn in files:
-        by_idx.setdefault(int(os.path.basename(fn)[3:6]), []).append(fn)
-    jobs = sorted(by_idx.items(), key=lambda kv: -json.loads(str(np.load(kv[1][0])["request"]))["n"])
-    with Pool(min(8, os.cpu_count() or 1)) as pool:
-        rows = [r for rs in pool.imap_unordered(check, jobs) for r in rs]
-    rows.sort(key=lambda r: (r["index"], r["path"]))
+def _dofs(req):
+    n, p = req["n"], req["p"]
+    return (n * p - 1) ** 2 + n * n * (p - 1) ** 2 * (2 if req["kind"] == "gradient" else 1)
+
+
+def _write(rows, out_md, skipped):
     lines = ["| request | stratum | n | p | path | GPU status | GPU / oracle prox steps | "
              "FP64 fallbacks | rel L2 vs oracle |", "|---|---|---|---|---|---|---|---|---|"]
-    for r in rows:
-        print("[check] request %3d %-28s n %2d p %2d %-5s status %d prox %d/%d rel L2 %.2e "
-              "(oracle %.0f s)" % (r["index"], r["stratum"], r["n"], r["p"], r["path"], r["status"],
-                                  r["gpu_prox"], r["oracle_prox"], r["rel_l2"], r["oracle_s"]),
-              flush=True)
+    for r in sorted(rows, key=lambda r: (r["index"], r["path"])):
         lines.append("| %d | %s | %d | %d | %s | %d | %d / %d | %d | %.2e |"
                      % (r["index"], r["stratum"], r["n"], r["p"], r["path"], r["status"],
                         r["gpu_prox"], r["oracle_prox"], r["fallbacks"], r["rel_l2"]))
     for path in sorted({r["path"] for r in rows}):
         e = [r["rel_l2"] for r in rows if r["path"] == path]
-        print("[check] %s: %d requests, max rel L2 %.2e, median %.2e" % (path, len(e), max(e),
-                                                                           float(np.median(e))))
         lines.append("")
         lines.append("%s: %d requests, max rel L2 %.2e, median %.2e" % (path, len(e), max(e),
                                                                        float(np.median(e))))
-    if out_md:
-        with open(out_md, "w") as fh:
-            fh.write("\n".join(lines) + "\n")
+    if skipped:
+        lines.append("")
+        lines.append("not checked (beyond the oracle's DOF budget): " + ", ".join(
+            "%d (n %d, p %d)" % s_ for s_ in skipped))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def main():
+    d = sys.argv[1]
+    out_md = sys.argv[2] if len(sys.argv) > 2 else None
+    max_dof = int(sys.argv[3]) if len(sys.argv) > 3 else 10 ** 9
+    files = sorted(glob.glob(os.path.join(d, "req*_*.npz")))
+    by_idx = {}
+    for fn in files:
+        by_idx.setdefault(int(os.path.basename(fn)[3:6]), []).append(fn)
+    reqs = {i: json.loads(str(np.load(f[0])["request"])) for i, f in by_idx.items()}
+    # smallest first, so that results accumulate early; the largest may be skipped
+    jobs = sorted(by_idx.items(), key=lambda kv: _dofs(reqs[kv[0]]))
+    skipped = [(i, reqs[i]["n"], reqs[i]["p"]) for i, _ in jobs if _dofs(reqs[i]) > max_dof]
+    jobs = [j for j in jobs if _dofs(reqs[j[0]]) <= max_dof]
+    rows = []
+    with Pool(min(8, os.cpu_count() or 1)) as pool:
+        for rs in pool.imap_unordered(check, jobs):
+            rows.extend(rs)
+            for r in rs:
+                print("[check] request %3d %-28s n %2d p %2d %-5s status %d prox %d/%d rel L2 %.2e "
+                      "(oracle %.0f s)" % (r["index"], r["stratum"], r["n"], r["p"], r["path"],
+                                          r["status"], r["gpu_prox"], r["oracle_prox"],
+                                          r["rel_l2"], r["oracle_s"]), flush=True)
+            if out_md:
+                _write(rows, out_md, skipped)
+    for path in sorted({r["path"] for r in rows}):
+        e = [r["rel_l2"] for r in rows if r["path"] == path]
+        print("[check] %s: %d requests, max rel L2 %.2e, median %.2e" % (path, len(e), max(e),
+                                                                           float(np.median(e))))
+    if skipped:
+        print("[check] not checked:", skipped)
 
 
 if __name__ == "__main__":
