@@ -284,7 +284,7 @@ void Batch::setup(const double* d_psi, const int* d_mask, bool want32, hipStream
                       P.C.as<double>(), cclass_rep.as<int>(), om64.as<double>(),
                       want32 ? om32.as<float>() : nullptr, s64.as<double>(),
                       want32 ? s32.as<float>() : nullptr, s, prm.as<double>(), d_mask, ncell,
-                      want32 ? sflag.as<int>() : nullptr);
+                      want32 ? sflag.as<int>() : nullptr, 1);
     P.tstop("setup", s);
     HPG_HIP(hipGetLastError());
 }
@@ -319,12 +319,13 @@ void Batch::apply_prec(const T* r, T* z, double* pr, const int* done, int dstrid
     const int d = M.d, npass = 2 * d, Pd = P.geo.Pd;
     dev::PsiBatch pb;
     pb.nb = nb;
-    pb.sinv = (int64_t)ncell * Pd * Pd;
+    pb.sinv = (int64_t)ncell * dev::psi_block_size(Pd, 1);   // packed blocks
     pb.r = pb.z = n;
     pb.part = PS;
     pb.done = dstride;
     pb.flag = ncell;
     dev::PsiHi hi;
+    hi.packed = 1;
     if (BSel<T>::prec == HPG_MIXED) {
         hi.s64 = s64.as<double>();
         hi.flag = sflag.as<int>();

@@ -87,7 +87,14 @@ struct PsiBatch {
 struct PsiHi {
     const double* s64 = nullptr;
     const int* flag = nullptr;
+    // the inverse blocks (and s64) stored packed: the upper triangle row by row,
+    // n (n + 1) / 2 values per cell (the blocks are symmetric)
+    int packed = 0;
 };
+// values per psi-block: n^2, or n (n + 1) / 2 packed
+__host__ __device__ inline int64_t psi_block_size(int n, int packed) {
+    return packed ? (int64_t)n * (n + 1) / 2 : (int64_t)n * n;
+}
 // 1-norm condition number of -S_hat_K above which the FP32 path applies the
 // cell's block in FP64: an FP32 product with a block of condition c carries a
 // relative error up to about n eps_32 c, which turns <S^{-1} v, v> negative
@@ -142,7 +149,7 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, con
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
                   float* om32, double* s64, float* s32, hipStream_t s,
                   const double* prm_req = nullptr, const int* mask = nullptr, int64_t cpr = 1,
-                  int* sflag = nullptr);
+                  int* sflag = nullptr, int packed = 0);
 template <typename T>
 void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
                      double* partial, const int* done, hipStream_t s,

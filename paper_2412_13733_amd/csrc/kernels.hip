@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
                                                float* __restrict__ sinv32,
                                                const double* __restrict__ prm_req,
                                                const int* __restrict__ mask, int64_t cpr,
-                                               int* __restrict__ sflag) {
+                                               int* __restrict__ sflag, int packed) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     const int n = g.Pd, q = g.q, P = g.P, Qd = g.Qd;
@@ -433,12 +433,15 @@ __global__ __launch_bounds__(256) void k_setup(Geo g, PsiTabs<double> tb, int cp
         }
         __syncthreads();
     }
+    const int64_t nt = psi_block_size(n, packed);
     for (int e = threadIdx.x; e < ncell * n * n; e += blockDim.x) {
         const int ci = e / (n * n), r = e - ci * n * n;
         // symmetrise (the exact inverse is symmetric)
         const int i = r / n, j = r % n;
+        if (packed && j < i) continue;   // packed: the upper triangle, row by row
         const double v = 0.5 * (Dm[ci * n * n + i * n + j] + Dm[ci * n * n + j * n + i]);
-        const int64_t off = (cell0 + ci) * (int64_t)n * n + r;
+        const int64_t off = (cell0 + ci) * nt +
+                            (packed ? (int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i) : r);
         if (!live(cell0 + ci)) continue;
         if (sinv64 && (!sflag || omega64 || nrm[ci] != 0.0)) sinv64[off] = v;
         if (sinv32) sinv32[off] = (float)v;
@@ -565,7 +568,7 @@ struct VhatSrc {
     __device__ inline T at(int64_t i) const { return Gq[i] - dl * vcur[i] - gm * vprev[i]; }
 };
 
-template <typename T, bool VH = false>
+template <typename T, bool VH = false, bool PK = false>
 __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, int cpb,
                                      const T* __restrict__ sinv, const T* __restrict__ r,
                                      T* __restrict__ z, double* __restrict__ partial,
@@ -574,7 +577,7 @@ __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, 
                                      const double* __restrict__ s64h = nullptr,
                                      const int* __restrict__ flg = nullptr) {
     if (done && *done) return;
-    const int nn = n * n;
+    const int nn = (int)psi_block_size(n, PK);   // values per block
     T* Rb = Sb + cpb * nn;
     double part = 0.0;
     const int64_t ngroups = (n_cells + cpb - 1) / cpb;
@@ -606,19 +609,42 @@ __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, 
         for (int i = threadIdx.x; i < nc * n; i += 256) {
             const int ci = i / n, row = i - ci * n;
             const T* rr = Rb + ci * n;
+            // z_row = sum_j S[j][row] r_j, j ascending.  Packed (upper triangle
+            // row by row): S[j][row] sits at tri(j) + row - j for j < row, where
+            // tri(j) = j n - j (j - 1) / 2 starts row j, and at tri(row) + j - row
+            // after; the same values in the same order as the full block
             if (flg && flg[cell0 + ci]) {
                 // a block too ill-conditioned for an FP32 product: its FP64
                 // inverse with FP64 sums (the dot from the FP64 product)
                 const double* S = s64h + (cell0 + ci) * (int64_t)nn;
                 double acc = 0.0;
-                for (int j = 0; j < n; ++j) acc += S[(int64_t)j * n + row] * (double)rr[j];
+                if (PK) {
+                    const int trow = row * n - row * (row - 1) / 2;
+                    int tj = 0;   // tri(j)
+                    for (int j = 0; j < n; ++j) {
+                        acc += S[j < row ? tj + row - j : trow + j - row] * (double)rr[j];
+                        tj += n - j;
+                    }
+                } else {
+                    for (int j = 0; j < n; ++j) acc += S[(int64_t)j * n + row] * (double)rr[j];
+                }
                 z[cell0 * n + i] = (T)acc;
                 part += acc * (double)rr[row];
                 continue;
             }
             const T* S = Sb + ci * nn;
             T acc = 0;
-            for (int j = 0; j < n; ++j) acc += S[j * n + row] * rr[j];
+            if (PK) {
+                // one loop of n steps for every thread (no per-row trip counts)
+                const int trow = row * n - row * (row - 1) / 2;
+                int tj = 0;   // tri(j)
+                for (int j = 0; j < n; ++j) {
+                    acc += S[j < row ? tj + row - j : trow + j - row] * rr[j];
+                    tj += n - j;
+                }
+            } else {
+                for (int j = 0; j < n; ++j) acc += S[j * n + row] * rr[j];
+            }
             z[cell0 * n + i] = acc;
             part += (double)acc * (double)rr[row];
         }
@@ -631,7 +657,7 @@ __device__ inline void prec_psi_body(int bid, int nblk, int64_t n_cells, int n, 
 }
 
 
-template <typename T>
+template <typename T, bool PK>
 __global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cpb,
                                                   const T* __restrict__ sinv,
                                                   const T* __restrict__ r, T* __restrict__ z,
@@ -641,11 +667,13 @@ __global__ __launch_bounds__(256) void k_prec_psi(int64_t n_cells, int n, int cp
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
     const int64_t rb = blockIdx.y;
-    prec_psi_body<T>(blockIdx.x, gridDim.x, n_cells, n, cpb, sinv + rb * bt.sinv, r + rb * bt.r,
-                     z + rb * bt.z, partial ? partial + rb * bt.part : nullptr,
-                     done ? done + rb * bt.done : nullptr, reinterpret_cast<T*>(smem_raw), red,
-                     nullptr, 0, hi.s64 ? hi.s64 + rb * bt.sinv : nullptr,
-                     hi.flag ? hi.flag + rb * bt.flag : nullptr);
+    prec_psi_body<T, false, PK>(blockIdx.x, gridDim.x, n_cells, n, cpb, sinv + rb * bt.sinv,
+                                r + rb * bt.r, z + rb * bt.z,
+                                partial ? partial + rb * bt.part : nullptr,
+                                done ? done + rb * bt.done : nullptr,
+                                reinterpret_cast<T*>(smem_raw), red, nullptr, 0,
+                                hi.s64 ? hi.s64 + rb * bt.sinv : nullptr,
+                                hi.flag ? hi.flag + rb * bt.flag : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -841,7 +869,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, const T*
 // fixed order (delta, stored by block 0), then the GEMM tiles and the
 // psi-block cells read vhat = Gq - delta v_cur - gamma v_prev where they load
 // the residual, and store it to vhat (each element by exactly one block).
-template <typename T, int TS>
+template <typename T, int TS, bool PK>
 __global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, const T* __restrict__ B,
                                                         int64_t ldb, T* __restrict__ C,
                                                         int64_t ldc, GemmEpi<T> ep, int gx,
@@ -867,13 +895,13 @@ __global__ __launch_bounds__(256) void k_vhat_gemm_prec(int M, int N, int K, con
         gemm_tile_body<T, TS, true>(bx, by, 0, M, N, K, nullptr, N, 0, B, ldb, 0, C, ldc, 0,
                                     nullptr, ep, red, rsum, &vs);
     } else {
-        prec_psi_body<T, true>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv, nullptr,
+        prec_psi_body<T, true, PK>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv, nullptr,
                                z, ppart, nullptr, reinterpret_cast<T*>(smem_raw), rsum, &vs, n_u,
                                hi.s64, hi.flag);
     }
 }
 
-template <typename T, int TS>
+template <typename T, int TS, bool PK>
 __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T* __restrict__ A,
                                                    int64_t lda, const T* __restrict__ B,
                                                    int64_t ldb, T* __restrict__ C, int64_t ldc,
@@ -895,7 +923,8 @@ __global__ __launch_bounds__(256) void k_gemm_prec(int M, int N, int K, const T*
         gemm_tile_body<T, TS>(bx, by, 0, M, N, K, A + rb * sA, lda, 0, B, ldb, 0, C + rb * sC,
                               ldc, 0, done ? done + rb * bt.done : nullptr, e2, red, rsum);
     } else {
-        prec_psi_body<T>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb, sinv + rb * bt.sinv,
+        prec_psi_body<T, false, PK>(blockIdx.x - ng, gridDim.x - ng, n_cells, n, cpb,
+                                    sinv + rb * bt.sinv,
                          r + rb * bt.r, z + rb * bt.z, ppart ? ppart + rb * bt.part : nullptr,
                          done ? done + rb * bt.done : nullptr, reinterpret_cast<T*>(smem_raw),
                          rsum, nullptr, 0, hi.s64 ? hi.s64 + rb * bt.sinv : nullptr,
@@ -1219,7 +1248,7 @@ size_t setup_big_smem(const Geo& g, bool t2) {
 void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, const double* psi,
                   double alpha, double beta, const double* C, const int* cclass, double* om64,
                   float* om32, double* s64, float* s32, hipStream_t s, const double* prm_req,
-                  const int* mask, int64_t cpr, int* sflag) {
+                  const int* mask, int64_t cpr, int* sflag, int packed) {
     if (big) {
         const bool t2 = big == SETUP_HBM_T2;
         const size_t shm = setup_big_smem(g, t2);
@@ -1237,7 +1266,7 @@ void launch_setup(const Geo& g, const PsiTabs<double>& tb, int cpb, int big, con
     size_t shm = setup_smem_per_cell(g) * cpb;
 #define HPG_S(DD)                                                                        \
     hipLaunchKernelGGL((k_setup<DD>), grid, blk, shm, s, g, tb, cpb, psi, alpha, beta, C, \
-                       cclass, om64, om32, s64, s32, prm_req, mask, cpr, sflag)
+                       cclass, om64, om32, s64, s32, prm_req, mask, cpr, sflag, packed)
     if (g.d == 1) HPG_S(1);
     else if (g.d == 2) HPG_S(2);
     else HPG_S(3);
@@ -1248,10 +1277,14 @@ template <typename T>
 void launch_prec_psi(int64_t n_cells, int n, int cpb, const T* sinv, const T* r, T* z,
                      double* partial, const int* done, hipStream_t s, const PsiBatch& bt,
                      const PsiHi& hi) {
-    const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
+    const size_t shm = (size_t)cpb * (psi_block_size(n, hi.packed) + n) * sizeof(T);
     const unsigned grid = (unsigned)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
-    hipLaunchKernelGGL((k_prec_psi<T>), dim3(grid, (unsigned)bt.nb), dim3(256), shm, s, n_cells,
-                       n, cpb, sinv, r, z, partial, done, bt, hi);
+    if (hi.packed)
+        hipLaunchKernelGGL((k_prec_psi<T, true>), dim3(grid, (unsigned)bt.nb), dim3(256), shm, s,
+                           n_cells, n, cpb, sinv, r, z, partial, done, bt, hi);
+    else
+        hipLaunchKernelGGL((k_prec_psi<T, false>), dim3(grid, (unsigned)bt.nb), dim3(256), shm, s,
+                           n_cells, n, cpb, sinv, r, z, partial, done, bt, hi);
 }
 
 template <typename T>
@@ -1283,13 +1316,15 @@ void launch_gemm_prec(int M, int N, int K, const T* A, int64_t lda, const T* B, 
     const int e = 16 * gemm_ts(ep);
     const int gx = (N + e - 1) / e, gy = (M + e - 1) / e;
     const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
-    const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
-#define HPG_G(TS)                                                                                \
-    hipLaunchKernelGGL((k_gemm_prec<T, TS>), dim3(gx * gy + np, (unsigned)bt.nb), dim3(256), shm, \
-                       s, M, N, K, A, lda, B, ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb, sinv, \
-                       r, z, ppart, sA, sC, bt, hi)
-    if (e == 32) HPG_G(2);
-    else HPG_G(1);
+    const size_t shm = (size_t)cpb * (psi_block_size(n, hi.packed) + n) * sizeof(T);
+#define HPG_G(TS, PK)                                                                             \
+    hipLaunchKernelGGL((k_gemm_prec<T, TS, PK>), dim3(gx * gy + np, (unsigned)bt.nb), dim3(256),   \
+                       shm, s, M, N, K, A, lda, B, ldb, C, ldc, done, ep, gx, gy, n_cells, n, cpb,  \
+                       sinv, r, z, ppart, sA, sC, bt, hi)
+    if (e == 32 && hi.packed) HPG_G(2, true);
+    else if (e == 32) HPG_G(2, false);
+    else if (hi.packed) HPG_G(1, true);
+    else HPG_G(1, false);
 #undef HPG_G
 }
 
@@ -1302,13 +1337,15 @@ void launch_vhat_gemm_prec(int M, int N, const T* B, T* C, const GemmEpi<T>& ep,
     const int e = 16 * gemm_ts(ep);
     const int gx = (N + e - 1) / e, gy = (M + e - 1) / e;
     const int np = (int)std::min<int64_t>((n_cells + cpb - 1) / cpb, 1024);
-    const size_t shm = (size_t)cpb * (n * n + n) * sizeof(T);
-#define HPG_G(TS)                                                                                \
-    hipLaunchKernelGGL((k_vhat_gemm_prec<T, TS>), dim3(gx * gy + np), dim3(256), shm, s, M, N, N, \
-                       B, N, C, N, ep, gx, gy, n_cells, n, cpb, sinv, z, ppart, st, gpart, npg, Gq, \
-                       vcur, vprev, vhat, n_u, hi)
-    if (e == 32) HPG_G(2);
-    else HPG_G(1);
+    const size_t shm = (size_t)cpb * (psi_block_size(n, hi.packed) + n) * sizeof(T);
+#define HPG_G(TS, PK)                                                                             \
+    hipLaunchKernelGGL((k_vhat_gemm_prec<T, TS, PK>), dim3(gx * gy + np), dim3(256), shm, s, M, N, \
+                       N, B, N, C, N, ep, gx, gy, n_cells, n, cpb, sinv, z, ppart, st, gpart, npg,  \
+                       Gq, vcur, vprev, vhat, n_u, hi)
+    if (e == 32 && hi.packed) HPG_G(2, true);
+    else if (e == 32) HPG_G(2, false);
+    else if (hi.packed) HPG_G(1, true);
+    else HPG_G(1, false);
 #undef HPG_G
 }
 

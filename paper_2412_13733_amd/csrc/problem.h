@@ -219,6 +219,9 @@ struct Problem {
     // the FP64 blocks of the ill-conditioned cells for an FP32 psi-block apply
     // (uniform-degree obstacle meshes with LDS-formed blocks; empty otherwise)
     bool flags_psi() const { return !M.hp && !gradient && !setup_mode; }
+    // psi-block inverses stored packed (upper triangle): the same meshes,
+    // with blocks applied from LDS
+    bool packed_psi() const { return flags_psi() && !prec_big; }
     template <typename T>
     dev::PsiHi psi_hi() const {
         dev::PsiHi h;
@@ -226,6 +229,7 @@ struct Problem {
             h.s64 = sinv64.as<double>();
             h.flag = sflag.as<int>();
         }
+        h.packed = packed_psi() ? 1 : 0;
         return h;
     }
     template <typename T>

@@ -447,8 +447,11 @@ void Problem::build(const Mesh& mesh, int dev_) {
     // psi-block preconditioner: ~16 KB of inverse blocks per block of 256
     // threads; blocks beyond 48 KB are streamed from HBM one cell per block
     prec_big = (size_t)(nblk * nblk + nblk) * 8 > 48 * 1024;
-    cpb_prec = std::max(1, (int)(2048 / std::max<int64_t>(1, nblk * nblk)));
-    while (cpb_prec > 1 && (size_t)cpb_prec * (nblk * nblk + nblk) * 8 > 48 * 1024) --cpb_prec;
+    // packed blocks (uniform-degree obstacle meshes) hold twice the cells per
+    // group in the same LDS, and use more of the block's threads (one per row)
+    const int64_t nbs = dev::psi_block_size((int)nblk, packed_psi() ? 1 : 0);
+    cpb_prec = std::max(1, (int)(2048 / std::max<int64_t>(1, nbs)));
+    while (cpb_prec > 1 && (size_t)cpb_prec * (nbs + nblk) * 8 > 48 * 1024) --cpb_prec;
     // 1-D rows per direction
     for (int k = 0; k < 3; ++k) {
         Rows1D R;
@@ -879,7 +882,7 @@ void Problem::setup(const double* d_psi, double alpha_, double beta_, int prec, 
                           prec == HPG_FP64 ? nullptr : om32.as<float>(),
                           (prec == HPG_FP64 || setup_mode || fl) ? sinv64.as<double>() : nullptr,
                           prec == HPG_FP64 ? nullptr : sinv32.as<float>(), s, nullptr, nullptr, 1,
-                          fl ? sflag.as<int>() : nullptr);
+                          fl ? sflag.as<int>() : nullptr, packed_psi() ? 1 : 0);
     }
     tstop("setup", s);
     HPG_HIP(hipGetLastError());
