@@ -661,7 +661,8 @@ def bench_3d(args, torch, hpg, W):
     if args.gradient3d:
         cases.append(("gradient_p4", hpg.GRADIENT, 4, W.w3d_gradient(),
                       dict(alpha0=2.0 ** -7, alpha_factor=2.0 ** 0.5, alpha_max=4.0,
-                           fixed_prox_steps=20, max_newton=200, stall_tol=1e-8)))
+                           fixed_prox_steps=20, max_newton=200, stall_tol=1e-8,
+                           max_krylov=20000)))
     for name, kind, p, (f, phi), extra in cases:
         mesh = hpg.Mesh(3, [16, 16, 16], p, constraint=kind)
         x = mesh.quadrature_points()
