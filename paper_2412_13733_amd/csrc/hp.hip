@@ -79,10 +79,8 @@ __global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha,
                                                  const T* __restrict__ omega,
                                                  const double* __restrict__ Phi,
                                                  T* __restrict__ yloc, T* __restrict__ ypsi,
-                                                 double* __restrict__ partial,
                                                  const int* __restrict__ done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[4];
     if (done && *done) return;
     if (prm) {
         alpha = (T)prm[0];
@@ -96,7 +94,6 @@ __global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha,
     T* bT = sm + 3 * SB;   // J B1^T x_K
     T* bA = sm + 4 * SB;
     T* bB = sm + 5 * SB;
-    double part = 0.0;
     for (int it = blockIdx.x; it < g.n_items; it += gridDim.x) {
         const int p = g.item_p[it], L = p + 1, P = p - 1, q = p + 1;
         const int start = g.item_start[it], ncell = g.item_count[it];
@@ -198,7 +195,6 @@ __global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha,
             if (MODE == MODE_RES) {
                 const double r = (double)bT[ci * S + a] + (double)dx[ci * S + a] - Phi[o];
                 ypsi[o] = (T)r;
-                part += r * r;
             } else {
                 T hk[3];
                 const T J = hp_jac<T, D>(g, tb, cell, hk);
@@ -207,14 +203,9 @@ __global__ __launch_bounds__(256) void k_hp_cell(HpGeo g, HpTabs<T> tb, T alpha,
                 for (int k = 0; k < D; ++k) md *= t.Mdiag[aa[k]];
                 const T y = bT[ci * S + a] - dx[ci * S + a] - beta * md * bX[ci * S + a];
                 ypsi[o] = y;
-                part += (double)y * (double)bX[ci * S + a];
             }
         }
         __syncthreads();   // the LDS buffers are reused by the next item
-    }
-    if (partial) {
-        const double s = block_sum(part, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
     }
 }
 
@@ -244,10 +235,8 @@ __global__ __launch_bounds__(256) void k_hp_cell2(HpGeo g, HpTabs<T> tb, T alpha
                                                   const T* __restrict__ omega,
                                                   const double* __restrict__ Phi,
                                                   T* __restrict__ yloc, T* __restrict__ ypsi,
-                                                  double* __restrict__ partial,
                                                   const int* __restrict__ done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[4];
     if (done && *done) return;
     if (prm) {
         alpha = (T)prm[0];
@@ -277,7 +266,6 @@ __global__ __launch_bounds__(256) void k_hp_cell2(HpGeo g, HpTabs<T> tb, T alpha
     T* cJ = sw + g.lmax;
     T* cC0 = cJ + lay.cmax;
     T* cC1 = cC0 + lay.cmax;
-    double part = 0.0;
     for (int it = blockIdx.x; it < g.n_items; it += gridDim.x) {
         const int p = g.item_p[it], L = p + 1, P = p - 1;
         const int S = L * L, LP = L * P, PP = P * P;
@@ -419,30 +407,29 @@ __global__ __launch_bounds__(256) void k_hp_cell2(HpGeo g, HpTabs<T> tb, T alpha
             if (MODE == MODE_RES) {
                 const double res = (double)bT[ci * S + r] + (double)dx - Phi[o];
                 ypsi[o] = (T)res;
-                part += res * res;
             } else {
                 const T xp = bX[ci * S + r];
                 const T md = cJ[ci] * sMd[a0] * sMd[a1];
                 const T y = bT[ci * S + r] - dx - beta * md * xp;
                 ypsi[o] = y;
-                part += (double)y * (double)xp;
             }
         }
         __syncthreads();   // the LDS buffers are reused by the next item
     }
-    if (partial) {
-        const double s = block_sum(part, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
-    }
 }
 
 // ---------------------------------------------------------------------------
+// The psi half of the reduction is taken here too, over fixed index ranges of
+// y_psi (written by the cell pass), so that no sum depends on how the cells
+// are grouped into work items.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_hp_gather(int64_t n_u, const int32_t* __restrict__ ip,
                                                    const int32_t* __restrict__ ix,
                                                    const T* __restrict__ yloc,
                                                    const double* __restrict__ F, double alpha,
                                                    const T* __restrict__ xu, T* __restrict__ yu,
+                                                   int64_t n_psi, const T* __restrict__ xpsi,
+                                                   const T* __restrict__ ypsi,
                                                    double* __restrict__ partial,
                                                    const int* __restrict__ done) {
     __shared__ double red[4];
@@ -461,9 +448,18 @@ __global__ __launch_bounds__(256) void k_hp_gather(int64_t n_u, const int32_t* _
             part += (double)s * (double)xu[gi];
         }
     }
-    if (partial) {
-        const double s = block_sum(part, red);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (!partial) return;
+    double pp = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_psi;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double y = (double)ypsi[k];
+        pp += MODE == MODE_RES ? y * y : y * (double)xpsi[k];
+    }
+    const double s = block_sum(part, red);
+    const double sp = block_sum(pp, red);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = s;
+        partial[gridDim.x + blockIdx.x] = sp;
     }
 }
 
@@ -482,25 +478,25 @@ __global__ __launch_bounds__(256) void k_hp_l2(HpGeo g, HpTabs<double> tb,
     double* bA = sm + 2 * SB;
     double* bB = sm + 3 * SB;
     double pd = 0.0, pn = 0.0;
-    for (int it = blockIdx.x; it < g.n_items; it += gridDim.x) {
-        const int p = g.item_p[it], L = p + 1, q = p + 1;
-        const int start = g.item_start[it], ncell = g.item_count[it];
+    // one cell at a time (cells blockIdx.x, + gridDim.x, ...): the sums do not
+    // depend on the work items
+    for (int64_t cell = blockIdx.x; cell < g.n_cells; cell += gridDim.x) {
+        const int p = g.cell_p[cell], L = p + 1, q = p + 1;
         int S = 1;
         for (int k = 0; k < D; ++k) S *= L;
         const HpCellTabs<double> t = hp_tabs(tb, p);
-        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
-            const int ci = e / S, l = e - ci * S;
-            const int gi = g.loc2glob[g.loc_off[g.order[start + ci]] + l];
-            bD[e] = gi >= 0 ? a[gi] - b[gi] : 0.0;
-            bN[e] = gi >= 0 ? a[gi] : 0.0;
+        for (int l = threadIdx.x; l < S; l += blockDim.x) {
+            const int gi = g.loc2glob[g.loc_off[cell] + l];
+            bD[l] = gi >= 0 ? a[gi] - b[gi] : 0.0;
+            bN[l] = gi >= 0 ? a[gi] : 0.0;
         }
         __syncthreads();
-        const double* vd = contract_all<double, D>(bD, bA, S, ncell, L, q, t.Vu, L, false);
-        const double* vn = contract_all<double, D>(bN, bB, S, ncell, L, q, t.Vu, L, false);
-        for (int e = threadIdx.x; e < ncell * S; e += blockDim.x) {
-            const int ci = e / S, j = e - ci * S;
+        const double* vd = contract_all<double, D>(bD, bA, S, 1, L, q, t.Vu, L, false);
+        const double* vn = contract_all<double, D>(bN, bB, S, 1, L, q, t.Vu, L, false);
+        for (int j = threadIdx.x; j < S; j += blockDim.x) {
+            const int e = j;
             double hk[3];
-            const double J = hp_jac<double, D>(g, tb, g.order[start + ci], hk);
+            const double J = hp_jac<double, D>(g, tb, cell, hk);
             int jj[3] = {j % q, (j / q) % q, j / (q * q)};
             double wq = J;
             for (int k = 0; k < D; ++k) wq *= t.w[jj[k]];
@@ -992,24 +988,24 @@ static inline unsigned grid_of(int64_t n, int b, int cap) {
 template <typename T>
 void launch_hp_cell(const HpGeo& g, const HpTabs<T>& tb, T alpha, T beta, const double* prm,
                     const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
-                    const double* Phi, T* yloc, T* ypsi, double* partial, int nblocks,
-                    const int* done, int mode, hipStream_t s) {
+                    const double* Phi, T* yloc, T* ypsi, int nblocks, const int* done, int mode,
+                    hipStream_t s) {
     const unsigned grid = (unsigned)std::max(1, std::min(g.n_items, nblocks));
     const size_t shm = hp_cell_lds(g.d, g.lds_elems, g.lmax, sizeof(T), mode);
     if (g.d == 2) {
         if (mode == MODE_RES)
             hipLaunchKernelGGL((k_hp_cell2<T, MODE_RES>), dim3(grid), dim3(256), shm, s, g, tb,
                                alpha, beta, prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi,
-                               partial, done);
+                               done);
         else
             hipLaunchKernelGGL((k_hp_cell2<T, MODE_APPLY>), dim3(grid), dim3(256), shm, s, g, tb,
                                alpha, beta, prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi,
-                               partial, done);
+                               done);
         return;
     }
 #define HPG_HC(DD, MM)                                                                          \
     hipLaunchKernelGGL((k_hp_cell<T, DD, MM>), dim3(grid), dim3(256), shm, s, g, tb, alpha, beta, \
-                       prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi, partial, done)
+                       prm, xu, xpsi, xpsi_prev, omega, Phi, yloc, ypsi, done)
     if (mode == MODE_RES) {
         if (g.d == 1) HPG_HC(1, MODE_RES);
         else HPG_HC(3, MODE_RES);
@@ -1022,20 +1018,21 @@ void launch_hp_cell(const HpGeo& g, const HpTabs<T>& tb, T alpha, T beta, const 
 
 template <typename T>
 void launch_hp_gather(int64_t n_u, const int32_t* inc_ptr, const int32_t* inc_idx, const T* yloc,
-                      const double* F, double alpha, const T* xu, T* yu, double* partial,
-                      int nblocks, const int* done, int mode, hipStream_t s) {
-    const unsigned grid = grid_of(n_u, 256, nblocks);
+                      const double* F, double alpha, const T* xu, T* yu, int64_t n_psi,
+                      const T* xpsi, const T* ypsi, double* partial, int nblocks, const int* done,
+                      int mode, hipStream_t s) {
+    const unsigned grid = (unsigned)std::max(1, nblocks);
     if (mode == MODE_RES)
         hipLaunchKernelGGL((k_hp_gather<T, MODE_RES>), dim3(grid), dim3(256), 0, s, n_u, inc_ptr,
-                           inc_idx, yloc, F, alpha, xu, yu, partial, done);
+                           inc_idx, yloc, F, alpha, xu, yu, n_psi, xpsi, ypsi, partial, done);
     else
         hipLaunchKernelGGL((k_hp_gather<T, MODE_APPLY>), dim3(grid), dim3(256), 0, s, n_u, inc_ptr,
-                           inc_idx, yloc, F, alpha, xu, yu, partial, done);
+                           inc_idx, yloc, F, alpha, xu, yu, n_psi, xpsi, ypsi, partial, done);
 }
 
 void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, const double* b,
                   double* partial, int nblocks, hipStream_t s) {
-    const unsigned grid = (unsigned)std::max(1, std::min(g.n_items, nblocks));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g.n_cells, nblocks));
     const size_t shm = (size_t)4 * g.lds_elems * sizeof(double);
     if (g.d == 1)
         hipLaunchKernelGGL((k_hp_l2<1>), dim3(grid), dim3(256), shm, s, g, tb, a, b, partial);
@@ -1137,11 +1134,11 @@ void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T
 
 #define HPG_INST(T)                                                                               \
     template void launch_hp_cell<T>(const HpGeo&, const HpTabs<T>&, T, T, const double*, const T*, \
-                                    const T*, const T*, const T*, const double*, T*, T*, double*,  \
-                                    int, const int*, int, hipStream_t);                            \
+                                    const T*, const T*, const T*, const double*, T*, T*, int,      \
+                                    const int*, int, hipStream_t);                                 \
     template void launch_hp_gather<T>(int64_t, const int32_t*, const int32_t*, const T*,          \
-                                      const double*, double, const T*, T*, double*, int,          \
-                                      const int*, int, hipStream_t);                               \
+                                      const double*, double, const T*, T*, int64_t, const T*,     \
+                                      const T*, double*, int, const int*, int, hipStream_t);      \
     template void launch_hp_prec_psi<T>(const HpGeo&, const T*, const T*, T*, double*, int, int,  \
                                         const int*, hipStream_t);                                  \
     template void launch_hp_vgather<T>(int64_t, const int32_t*, const T*, T*, const int*,         \

@@ -303,28 +303,34 @@ struct HpGeo {
 };
 constexpr int MODE_L2 = 2;
 // Cell pass of G (MODE_APPLY: y_loc = alpha A_K x_K + B_K x_psi, y_psi =
-// B_K^T x_K - (D_K + beta M_K) x_psi, partial <y_psi, x_psi>) or of the FP64
-// residual (MODE_RES: x_psi = psi, xpsi_prev = psi_{k-1}; y_loc = alpha A_K u_K
-// + B_K (psi - psi_prev), y_psi = B_K^T u_K + E_K(psi) - Phi_K, partial
-// |y_psi|^2).  y_loc is per local function, summed into y_u by launch_hp_gather.
+// B_K^T x_K - (D_K + beta M_K) x_psi) or of the FP64 residual (MODE_RES:
+// x_psi = psi, xpsi_prev = psi_{k-1}; y_loc = alpha A_K u_K + B_K (psi -
+// psi_prev), y_psi = B_K^T u_K + E_K(psi) - Phi_K).  y_loc is per local
+// function, summed into y_u by launch_hp_gather, which also takes both halves
+// of the reduction.
 // LDS bytes of the cell pass (element size tsize, MODE_APPLY or MODE_RES)
 size_t hp_cell_lds(int d, int lds_elems, int lmax, size_t tsize, int mode);
 template <typename T>
 void launch_hp_cell(const HpGeo& g, const HpTabs<T>& tb, T alpha, T beta, const double* prm,
                     const T* xu, const T* xpsi, const T* xpsi_prev, const T* omega,
-                    const double* Phi, T* yloc, T* ypsi, double* partial, int nblocks,
-                    const int* done, int mode, hipStream_t s);
+                    const double* Phi, T* yloc, T* ypsi, int nblocks, const int* done, int mode,
+                    hipStream_t s);
 // y_u[g] = sum of y_loc over the local functions of unknown g (fixed order),
-// minus alpha F[g] in MODE_RES; partial <y_u, x_u> (APPLY) or |y_u|^2 (RES)
+// minus alpha F[g] in MODE_RES, in nblocks blocks; partial[0, nblocks) gets
+// <y_u, x_u> (APPLY) or |y_u|^2 (RES) per block and partial[nblocks,
+// 2 nblocks) <y_psi, x_psi> or |y_psi|^2 over fixed ranges of the psi unknowns
+// (y_psi as the cell pass wrote it), independent of the work items
 template <typename T>
 void launch_hp_gather(int64_t n_u, const int32_t* inc_ptr, const int32_t* inc_idx, const T* yloc,
-                      const double* F, double alpha, const T* xu, T* yu, double* partial,
-                      int nblocks, const int* done, int mode, hipStream_t s);
+                      const double* F, double alpha, const T* xu, T* yu, int64_t n_psi,
+                      const T* xpsi, const T* ypsi, double* partial, int nblocks, const int* done,
+                      int mode, hipStream_t s);
 // launch_diag on a mesh with one degree per cell (obstacle constraint)
 void launch_hp_diag(const HpGeo& g, const HpTabs<double>& tb, const double* u, const double* psi,
                     const double* lam, const double* phiq, double* partial, int nblocks,
                     hipStream_t s);
-// ||a - b||_{L2}^2 and ||a||_{L2}^2 per block (partial[2 i], partial[2 i + 1])
+// ||a - b||_{L2}^2 and ||a||_{L2}^2 per block (partial[2 i], partial[2 i + 1]);
+// block i takes cells i, i + nblocks, ... (min(n_cells, nblocks) blocks)
 void launch_hp_l2(const HpGeo& g, const HpTabs<double>& tb, const double* a, const double* b,
                   double* partial, int nblocks, hipStream_t s);
 // Newton-step setup: omega_q = w_q |J| exp(-psi_h) at qp_off, and the inverse of

@@ -132,7 +132,7 @@ struct Problem {
         DBuf inv64, inv32, tab64, tab32, toff, h64[3], h32[3], yloc64, yloc32, cv64, cv32;
     } hpd;
     dev::HpGeo hgeo{};
-    int hp_lds_elems = 256, hp_nmax = 1, np_gath = 0, np_cell = 0;
+    int hp_lds_elems = 256, hp_nmax = 1, np_gath = 0, np_cell = 0, np_hpl2 = 0;
     size_t hp_setup_bytes = 0;
     bool hp_setup_in_lds = false;
     struct HpRun {

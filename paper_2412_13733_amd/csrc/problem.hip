@@ -1301,10 +1301,11 @@ void Problem::residual(const double* uu, const double* pp, const double* pprev, 
             }
             dev::launch_hp_cell<double>(hgeo, hp_tabs<double>(), alpha_, 0.0, nullptr, uu, pp,
                                         pprev, nullptr, Phi.as<double>(), yloc, RR + M.n_u,
-                                        part + np_u, np_cell, nullptr, dev::MODE_RES, s);
+                                        np_cell, nullptr, dev::MODE_RES, s);
             dev::launch_hp_gather<double>(M.n_u, hpd.inc_ptr.as<int32_t>(),
                                           hpd.inc_idx.as<int32_t>(), yloc, F.as<double>(), alpha_,
-                                          uu, RR, part, np_gath, nullptr, dev::MODE_RES, s);
+                                          uu, RR, M.n_psi, nullptr, RR + M.n_u, part, np_gath,
+                                          nullptr, dev::MODE_RES, s);
         } else if (gradient) {
             dev::launch_u_side_grad<double>(geo, r, alpha_, uu, pp, pprev, F.as<double>(), RR,
                                             part, nullptr, dev::MODE_RES, s, nullptr);
@@ -1361,8 +1362,8 @@ double Problem::l2_diff(const double* a, const double* b, double* norm_a, hipStr
     double* part = partial.as<double>();
     int nb;
     if (M.hp) {
-        dev::launch_hp_l2(hgeo, hp_tabs<double>(), a, b, part, np_cell, s);
-        nb = std::min(hgeo.n_items, np_cell);
+        dev::launch_hp_l2(hgeo, hp_tabs<double>(), a, b, part, np_hpl2, s);
+        nb = np_hpl2;
     } else {
         dev::launch_l2(geo, tab64.view(), cpb_l2, a, b, part, s);
         nb = (int)((M.n_cells + cpb_l2 - 1) / cpb_l2);

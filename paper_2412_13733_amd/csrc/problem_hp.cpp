@@ -112,17 +112,20 @@ void Problem::build_hp() {
     tune_hp_items();
     // reduction layout: G apply = [gather blocks | cell blocks] (the u / psi
     // halves of the generic layout), preconditioner = [dot blocks | psi blocks]
-    np_gath = (int)std::min<int64_t>((M.n_u + 255) / 256, 1024);
+    np_gath = (int)std::max<int64_t>(1, std::min<int64_t>((M.n_u + 255) / 256, 1024));
     np_cell = std::min(hgeo.n_items, 4096);   // one block per work item up to 4096
+    np_hpl2 = (int)std::min<int64_t>(M.n_cells, 2048);
+    // both halves from the gather pass's blocks (fixed index ranges), so the
+    // sums do not depend on the tuned work items
     np_u = np_gath;
-    np_psi = np_cell;
+    np_psi = np_gath;
     // <z_u, r_u>: the entity blocks' shares, then the vertex scatter's
     np_dot = dev::hp_prec_entity_blocks(M.n_u) +
              (H.vert.empty() ? 0 : dev::hp_vscatter_blocks((int64_t)H.vert.size()));
     np_prec = (int)std::min<int64_t>(M.n_cells, 4096);
     fdm_dot_fused = false;
     use_tile = false;
-    np_cap = std::max({np_u + np_psi, np_dot + np_prec, 2 * np_cell});
+    np_cap = std::max({np_u + np_psi, np_dot + np_prec, 2 * np_hpl2});
     partial.alloc((size_t)np_cap * sizeof(double));
     partial_g.alloc((size_t)np_cap * sizeof(double));
     params.alloc(4 * sizeof(double));
@@ -181,7 +184,7 @@ void Problem::tune_hp_items() {
         auto run = [&]() {
             dev::launch_hp_cell<float>(hgeo, hp_tabs<float>(), 1.0f, 0.0f, nullptr, x.as<float>(),
                                        x.as<float>() + M.n_u, nullptr, om.as<float>(), nullptr,
-                                       yl.as<float>(), y.as<float>() + M.n_u, nullptr,
+                                       yl.as<float>(), y.as<float>() + M.n_u,
                                        std::min(hgeo.n_items, 4096), nullptr, dev::MODE_APPLY, s);
         };
         run();
@@ -312,11 +315,11 @@ void Problem::apply_G_hp(const T* x, T* y, double* part, const int* dn, hipStrea
     const T* om = (dbl ? om64 : om32).template as<T>();
     tstart("apply_G", s);
     dev::launch_hp_cell<T>(hgeo, hp_tabs<T>(), (T)alpha, (T)beta, params.as<double>(), x,
-                           x + M.n_u, nullptr, om, nullptr, yl.as<T>(), y + M.n_u,
-                           part ? part + np_u : nullptr, np_cell, dn, dev::MODE_APPLY, s);
+                           x + M.n_u, nullptr, om, nullptr, yl.as<T>(), y + M.n_u, np_cell, dn,
+                           dev::MODE_APPLY, s);
     dev::launch_hp_gather<T>(M.n_u, hpd.inc_ptr.as<int32_t>(), hpd.inc_idx.as<int32_t>(),
-                             yl.as<T>(), nullptr, 0.0, x, y, part, np_gath, dn, dev::MODE_APPLY,
-                             s);
+                             yl.as<T>(), nullptr, 0.0, x, y, M.n_psi, x + M.n_u, y + M.n_u, part,
+                             np_gath, dn, dev::MODE_APPLY, s);
     tstop("apply_G", s);
 }
 
