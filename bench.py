@@ -93,7 +93,42 @@ def parse():
                     help="only a few operator launches for rocprofv3 --pmc passes: the "
                          "workload's G apply and preconditioner (FP32 and FP64), the G apply of "
                          "each roofline probe, and a 1 GiB device copy to calibrate the counters")
+    ap.add_argument("--hp-counters", action="store_true",
+                    help="only a few operator launches of the per-cell-degree workload for "
+                         "rocprofv3 --pmc passes: two setups, five G applies and five "
+                         "preconditioner applies per precision, each kernel group on its own")
     return ap.parse_args()
+
+
+def hp_counters_run(args, torch, hpg, W):
+    """Short, fixed sequence of launches of the 64 x 64 degree-2..12 workload
+    (the cell pass of G, the setup, the preconditioner parts) to read VALU
+    and LDS counters against."""
+    deg = np.loadtxt(HP_DEGREES, dtype=np.int32).reshape(-1)
+    f, phi = W.w2d_dip(0)
+    mesh = hpg.Mesh(2, [64, 64], 0, degree=deg)
+    x = mesh.quadrature_points()
+    prob = hpg.Problem(mesh, device=0)
+    prob.set_forcing(f(x))
+    prob.set_obstacle(phi(x))
+    n = mesh.n_u + mesh.n_psi
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    psi = 0.5 * torch.randn(mesh.n_psi, dtype=torch.float64, device="cuda", generator=g)
+    prob.set_kernel_timing("all")
+    for prec, dt in ((hpg.MIXED, torch.float32), (hpg.FP64, torch.float64)):
+        for _ in range(2):
+            prob.op_setup(psi, 4.0, 0.0, precision=prec)
+        v = torch.randn(n, dtype=dt, device="cuda", generator=g)
+        w = torch.empty_like(v)
+        for _ in range(5):
+            prob.op_apply_G(v, w)
+            prob.op_apply_prec(v, w)
+    torch.cuda.synchronize()
+    prob.set_kernel_timing(None)
+    print(json.dumps({"hp_counters_run": "done", "n_u": mesh.n_u, "n_psi": mesh.n_psi,
+                      "degree_histogram": np.bincount(deg, minlength=13)[2:].tolist()}),
+          flush=True)
 
 
 def counters_run(args, torch, hpg, W):
@@ -720,6 +755,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_run(args, torch, hpg, W)
+        return
+    if args.hp_counters:
+        hp_counters_run(args, torch, hpg, W)
         return
     if args.batch_only:
         print(json.dumps({"batch": batch_bench(args, torch, hpg, W)}), flush=True)
