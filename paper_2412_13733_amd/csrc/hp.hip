@@ -697,40 +697,90 @@ __global__ __launch_bounds__(256) void k_hp_vscatter(int64_t n, const int32_t* _
         z[idx[i]] = in[i];
 }
 
-// z_E = (1/alpha) Ainv_E r_E, one thread per unknown of a non-vertex entity
-// (ent_of[g]: its entity, -1 for vertices).  An entity's unknowns are
-// consecutive, so a wave reads consecutive columns of row j of the symmetric
-// inverse (coalesced) and broadcasts r_j.  Optionally the block's share of
-// <z, r> over those unknowns goes to partial[bid].
+// z_E = (1/alpha) Ainv_E r_E for the non-vertex entities, one chunk of
+// entities sharing an inverse at a time: their r_E side by side in LDS (rs),
+// then per row i of the inverse (read as column i, coalesced: it is
+// symmetric) all the chunk's z_E[i] from one read of the row.  Optionally the
+// block's share of <z, r> over those unknowns goes to partial[bid].
 template <typename T>
-__device__ inline void hp_entity_body(int64_t bid, int64_t nblk, int64_t n_u,
-                                      const int32_t* __restrict__ ent_of,
-                                      const int32_t* __restrict__ first,
-                                      const int32_t* __restrict__ cnt,
-                                      const int64_t* __restrict__ off, const T* __restrict__ inv,
-                                      T ia, const T* __restrict__ r, T* __restrict__ z,
-                                      double* __restrict__ partial, double* red) {
+__device__ inline void hp_entity_body(int64_t bid, int64_t nblk, const HpEnt& ent,
+                                      const T* __restrict__ inv, T ia, const T* __restrict__ r,
+                                      T* __restrict__ z, double* __restrict__ partial, T* rs,
+                                      double* red) {
     double part = 0.0;
-    for (int64_t gi = bid * blockDim.x + threadIdx.x; gi < n_u; gi += nblk * blockDim.x) {
-        const int e = ent_of[gi];
-        if (e < 0) continue;
-        const int64_t f = first[e];
-        const int n = cnt[e], i = (int)(gi - f);
-        const T* A = inv + off[e] + i;
-        const T* rr = r + f;
-        // four independent partial sums keep several loads in flight
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int j = 0;
-        for (; j + 4 <= n; j += 4) {
-            a0 += A[(int64_t)j * n] * rr[j];
-            a1 += A[(int64_t)(j + 1) * n] * rr[j + 1];
-            a2 += A[(int64_t)(j + 2) * n] * rr[j + 2];
-            a3 += A[(int64_t)(j + 3) * n] * rr[j + 3];
+    for (int64_t ch = bid; ch < ent.nchunk; ch += nblk) {
+        const int c0 = ent.cstart[ch], nc = ent.ccount[ch];
+        const int n = ent.cnt[ent.list[c0]];
+        const T* A = inv + ent.off[ent.list[c0]];
+        const bool rows = hp_ent_rows(n);
+        if (rows) {
+            // the chunk's right-hand sides interleaved, rs[j kHpEntChunk + c]
+            // (zeros past the last entity: the accumulators cover kHpEntChunk)
+            for (int k = threadIdx.x; k < kHpEntChunk * n; k += blockDim.x) {
+                const int j = k / kHpEntChunk, c = k - j * kHpEntChunk;
+                rs[k] = c < nc ? r[ent.first[ent.list[c0 + c]] + j] : T(0);
+            }
+        } else {
+            // entity by entity, rs[c n + j]
+            for (int k = threadIdx.x; k < nc * n; k += blockDim.x) {
+                const int c = k / n, j = k - c * n;
+                rs[k] = r[ent.first[ent.list[c0 + c]] + j];
+            }
         }
-        for (; j < n; ++j) a0 += A[(int64_t)j * n] * rr[j];
-        const T zv = ia * ((a0 + a1) + (a2 + a3));
-        z[gi] = zv;
-        part += (double)zv * (double)r[gi];
+        __syncthreads();
+        if (rows) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                T acc[kHpEntChunk];
+#pragma unroll
+                for (int c = 0; c < kHpEntChunk; ++c) acc[c] = 0;
+                // eight rows of loads in flight, then their products in order of j
+                int j = 0;
+                for (; j + 8 <= n; j += 8) {
+                    T a[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(j + u) * n + i];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const T* rj = rs + (j + u) * kHpEntChunk;
+#pragma unroll
+                        for (int c = 0; c < kHpEntChunk; ++c) acc[c] += a[u] * rj[c];
+                    }
+                }
+                for (; j < n; ++j) {
+                    const T a = A[(int64_t)j * n + i];
+                    const T* rj = rs + j * kHpEntChunk;
+#pragma unroll
+                    for (int c = 0; c < kHpEntChunk; ++c) acc[c] += a * rj[c];
+                }
+#pragma unroll
+                for (int c = 0; c < kHpEntChunk; ++c) {
+                    if (c < nc) {
+                        const T zv = ia * acc[c];
+                        z[ent.first[ent.list[c0 + c]] + i] = zv;
+                        part += (double)zv * (double)rs[i * kHpEntChunk + c];
+                    }
+                }
+            }
+        } else {
+            for (int k = threadIdx.x; k < nc * n; k += blockDim.x) {
+                const int c = k / n, i = k - c * n;
+                const T* rc = rs + c * n;
+                T acc = 0;
+                int j = 0;
+                for (; j + 8 <= n; j += 8) {
+                    T a[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(j + u) * n + i];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc += a[u] * rc[j + u];
+                }
+                for (; j < n; ++j) acc += A[(int64_t)j * n + i] * rc[j];
+                const T zv = ia * acc;
+                z[ent.first[ent.list[c0 + c]] + i] = zv;
+                part += (double)zv * (double)rs[k];
+            }
+        }
+        __syncthreads();   // rs is refilled by the next chunk
     }
     if (partial) {
         const double s = block_sum(part, red);
@@ -739,18 +789,15 @@ __device__ inline void hp_entity_body(int64_t bid, int64_t nblk, int64_t n_u,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_hp_entity(int64_t n_u, const int32_t* __restrict__ ent_of,
-                                                   const int32_t* __restrict__ first,
-                                                   const int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ off,
-                                                   const T* __restrict__ inv,
+__global__ __launch_bounds__(256) void k_hp_entity(HpEnt ent, const T* __restrict__ inv,
                                                    const double* __restrict__ prm,
                                                    const T* __restrict__ r, T* __restrict__ z,
                                                    const int* __restrict__ done) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[4];
     if (done && *done) return;
-    hp_entity_body<T>(blockIdx.x, gridDim.x, n_u, ent_of, first, cnt, off, inv, (T)prm[2], r, z,
-                      nullptr, red);
+    hp_entity_body<T>(blockIdx.x, gridDim.x, ent, inv, (T)prm[2], r, z, nullptr,
+                      reinterpret_cast<T*>(smem_raw), red);
 }
 
 // The three independent parts of the block preconditioner in one grid:
@@ -758,9 +805,7 @@ __global__ __launch_bounds__(256) void k_hp_entity(int64_t n_u, const int32_t* _
 // their share of <z, r> in epart), the rest gathers the vertex residual.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hp_prec_fused(HpGeo g, const T* __restrict__ sinv,
-                                                       int np, int ne, const int32_t* ent_of,
-                                                       const int32_t* first, const int32_t* cnt,
-                                                       const int64_t* off, const T* inv,
+                                                       int np, int ne, HpEnt ent, const T* inv,
                                                        const double* __restrict__ prm,
                                                        const int32_t* __restrict__ vidx,
                                                        int64_t nv, T* __restrict__ cv,
@@ -777,8 +822,8 @@ __global__ __launch_bounds__(256) void k_hp_prec_fused(HpGeo g, const T* __restr
         hp_prec_psi_body<T>(b, np, g, sinv, r + g.n_u, z + g.n_u, ppart,
                             reinterpret_cast<T*>(smem_raw), acc_s, red);
     } else if (b < np + ne) {
-        hp_entity_body<T>(b - np, ne, g.n_u, ent_of, first, cnt, off, inv, (T)prm[2], r, z,
-                          epart, red);
+        hp_entity_body<T>(b - np, ne, ent, inv, (T)prm[2], r, z, epart,
+                          reinterpret_cast<T*>(smem_raw), red);
     } else {
         const int64_t nb = gridDim.x - np - ne;
         for (int64_t i = (int64_t)(b - np - ne) * blockDim.x + threadIdx.x; i < nv;
@@ -1103,26 +1148,25 @@ void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const 
 }
 
 template <typename T>
-void launch_hp_entity(int64_t n_u, const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
-                      const int64_t* off, const T* inv, const double* prm, const T* r, T* z,
+void launch_hp_entity(const HpEnt& ent, const T* inv, const double* prm, const T* r, T* z,
                       const int* done, hipStream_t s) {
-    hipLaunchKernelGGL((k_hp_entity<T>), dim3(grid_of(n_u, 256, 8192)), dim3(256), 0, s, n_u,
-                       ent_of, first, cnt, off, inv, prm, r, z, done);
+    if (ent.nchunk <= 0) return;
+    hipLaunchKernelGGL((k_hp_entity<T>), dim3(grid_of(ent.nchunk, 1, 8192)), dim3(256),
+                       (size_t)ent.lds * sizeof(T), s, ent, inv, prm, r, z, done);
 }
 
-int hp_prec_entity_blocks(int64_t n_u) { return (int)grid_of(n_u, 256, 2048); }
+int hp_prec_entity_blocks(int nchunk) { return nchunk > 0 ? (int)grid_of(nchunk, 1, 2048) : 0; }
 int hp_vscatter_blocks(int64_t nv) { return (int)grid_of(nv, 256, 256); }
 
 template <typename T>
 void launch_hp_prec_fused(const HpGeo& g, const T* sinv, int np, int nmax, int ne,
-                          const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
-                          const int64_t* off, const T* inv, const double* prm, const int32_t* vidx,
+                          const HpEnt& ent, const T* inv, const double* prm, const int32_t* vidx,
                           int64_t nv, T* cv, const T* r, T* z, double* ppart, double* epart,
                           const int* done, hipStream_t s) {
     const int nvb = nv > 0 ? (int)grid_of(nv, 256, 64) : 0;
-    hipLaunchKernelGGL((k_hp_prec_fused<T>), dim3(np + ne + nvb), dim3(256),
-                       (size_t)nmax * sizeof(T), s, g, sinv, np, ne, ent_of, first, cnt, off, inv,
-                       prm, vidx, nv, cv, r, z, ppart, epart, done);
+    const size_t lds = (size_t)std::max(nmax, ne > 0 ? ent.lds : 0) * sizeof(T);
+    hipLaunchKernelGGL((k_hp_prec_fused<T>), dim3(np + ne + nvb), dim3(256), lds, s, g, sinv,
+                       np, ne, ent, inv, prm, vidx, nv, cv, r, z, ppart, epart, done);
 }
 
 template <typename T>
@@ -1145,8 +1189,7 @@ void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T
                                        hipStream_t);                                               \
     template void launch_hp_vscatter<T>(int64_t, const int32_t*, const T*, T*, const int*,        \
                                         hipStream_t);                                              \
-    template void launch_hp_prec_fused<T>(const HpGeo&, const T*, int, int, int, const int32_t*,  \
-                                          const int32_t*, const int32_t*, const int64_t*,         \
+    template void launch_hp_prec_fused<T>(const HpGeo&, const T*, int, int, int, const HpEnt&,    \
                                           const T*, const double*, const int32_t*, int64_t, T*,   \
                                           const T*, T*, double*, double*, const int*,             \
                                           hipStream_t);                                            \
@@ -1155,8 +1198,7 @@ void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T
     template void launch_hp_vsolve2<T>(int, int, const int32_t*, const T*, const T*, const T*,    \
                                        const T*, const double*, const T*, T*, double*, int,        \
                                        const int*, hipStream_t);                                   \
-    template void launch_hp_entity<T>(int64_t, const int32_t*, const int32_t*, const int32_t*,    \
-                                      const int64_t*, const T*, const double*, const T*, T*,      \
+    template void launch_hp_entity<T>(const HpEnt&, const T*, const double*, const T*, T*,       \
                                       const int*, hipStream_t);
 HPG_INST(double)
 HPG_INST(float)

@@ -330,9 +330,27 @@ void hp_build_host(const Mesh& M, int lds_elems, HpHost& H) {
                 H.ent_n.push_back(n);
                 H.ent_off.push_back(it->second);
             }
-    H.ent_of.assign(M.n_u, -1);
-    for (size_t e = 0; e < H.ent_n.size(); ++e)
-        for (int i = 0; i < H.ent_n[e]; ++i) H.ent_of[H.ent_first[e] + i] = (int32_t)e;
+    // chunks: entities with one inverse (equal offsets, so equal sizes) next to
+    // each other, larger entities first
+    const int ne = (int)H.ent_n.size();
+    H.ent_list.resize(ne);
+    for (int e = 0; e < ne; ++e) H.ent_list[e] = e;
+    std::stable_sort(H.ent_list.begin(), H.ent_list.end(), [&](int32_t a, int32_t b) {
+        if (H.ent_n[a] != H.ent_n[b]) return H.ent_n[a] > H.ent_n[b];
+        return H.ent_off[a] < H.ent_off[b];
+    });
+    H.ent_cstart.clear();
+    H.ent_ccount.clear();
+    H.ent_lds = 0;
+    for (int k = 0; k < ne;) {
+        const int n = H.ent_n[H.ent_list[k]], cap = dev::hp_ent_cap(n);
+        int j = k;
+        while (j < ne && j - k < cap && H.ent_off[H.ent_list[j]] == H.ent_off[H.ent_list[k]]) ++j;
+        H.ent_cstart.push_back(k);
+        H.ent_ccount.push_back(j - k);
+        H.ent_lds = std::max(H.ent_lds, dev::hp_ent_lds(n));
+        k = j;
+    }
 }
 
 }  // namespace hpg

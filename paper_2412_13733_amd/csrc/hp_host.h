@@ -23,9 +23,13 @@ struct HpHost {
     std::vector<int32_t> vert;              // interior-vertex unknowns, tensor order
     int nv[3] = {1, 1, 1};                  // interior vertices per direction
     std::vector<int32_t> ent_first, ent_n;  // other entities: first unknown, count
-    std::vector<int32_t> ent_of;            // entity of each u unknown (-1: vertex)
     std::vector<int64_t> ent_off;           // offset of the entity's inverse in inv
     std::vector<double> inv;                // inverses of A restricted to an entity
+    // chunks of entities sharing one inverse (dev::hp_ent_cap per chunk), the
+    // largest entities first: entity numbers chunk by chunk, each chunk's
+    // first position and count, and the LDS elements of the largest chunk
+    std::vector<int32_t> ent_list, ent_cstart, ent_ccount;
+    int ent_lds = 0;
 };
 
 // lds_elems: LDS elements per buffer of the cell kernels (bounds cells per item)

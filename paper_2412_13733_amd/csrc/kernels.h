@@ -358,16 +358,43 @@ void launch_hp_vgather(int64_t n, const int32_t* idx, const T* r, T* out, const 
 template <typename T>
 void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const int* done,
                         hipStream_t s);
-// The psi-block (np blocks, LDS nmax values), the entity blocks (ne blocks,
+// Edge / face / interior entities of the block-Jacobi A-block, in chunks of
+// entities that share one (deduplicated) inverse: a chunk's right-hand sides
+// sit side by side in LDS, so each entry of the inverse is read once per
+// chunk.  Entities of kHpEntRowMin..kHpEntRowMax unknowns: up to kHpEntChunk
+// per chunk, a row per thread for all of them (LDS kHpEntChunk n); smaller
+// ones: up to 256 / n per chunk, a thread per (entity, row); larger ones: one
+// per chunk.
+constexpr int kHpEntChunk = 8;
+constexpr int kHpEntRowMin = 32, kHpEntRowMax = 768;
+__host__ __device__ inline bool hp_ent_rows(int n) {
+    return n >= kHpEntRowMin && n <= kHpEntRowMax;
+}
+__host__ __device__ inline int hp_ent_cap(int n) {
+    return hp_ent_rows(n) ? kHpEntChunk : (n < kHpEntRowMin ? 256 / n : 1);
+}
+__host__ __device__ inline int hp_ent_lds(int n) {   // LDS elements of a chunk
+    return hp_ent_rows(n) ? kHpEntChunk * n : hp_ent_cap(n) * n;
+}
+struct HpEnt {
+    int nchunk;
+    int lds;                  // largest hp_ent_lds over the entities
+    const int32_t* cstart;    // chunk -> first position in list
+    const int32_t* ccount;    // entities in the chunk
+    const int32_t* list;      // entity numbers, chunk by chunk
+    const int32_t* first;     // first unknown of each entity (its unknowns are consecutive)
+    const int32_t* cnt;       // unknowns of each entity
+    const int64_t* off;       // offset of each entity's inverse (row-major, symmetric)
+};
+// The psi-block (np blocks, LDS nmax values), the entity chunks (ne blocks,
 // their <z, r> shares in epart[0..ne)) and the vertex gather (into cv) in one
-// launch; hp_prec_entity_blocks gives ne for n_u unknowns.  The vertex
+// launch; hp_prec_entity_blocks gives ne for nchunk chunks.  The vertex
 // scatter then adds its <z, r> shares (hp_vscatter_blocks(nv) of them).
-int hp_prec_entity_blocks(int64_t n_u);
+int hp_prec_entity_blocks(int nchunk);
 int hp_vscatter_blocks(int64_t nv);
 template <typename T>
 void launch_hp_prec_fused(const HpGeo& g, const T* sinv, int np, int nmax, int ne,
-                          const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
-                          const int64_t* off, const T* inv, const double* prm, const int32_t* vidx,
+                          const HpEnt& ent, const T* inv, const double* prm, const int32_t* vidx,
                           int64_t nv, T* cv, const T* r, T* z, double* ppart, double* epart,
                           const int* done, hipStream_t s);
 // 2-D vertex block of the preconditioner in one workgroup (n0, n1 <= 64
@@ -382,10 +409,9 @@ void launch_hp_vsolve2(int n0, int n1, const int32_t* vidx, const T* V0, const T
 template <typename T>
 void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T* r, T* z,
                             double* partial, const int* done, hipStream_t s);
-// (ent_of: entity of each u unknown, -1 for vertices; one thread per unknown)
+// the entity chunks alone (z_E = prm[2] Ainv_E r_E)
 template <typename T>
-void launch_hp_entity(int64_t n_u, const int32_t* ent_of, const int32_t* first, const int32_t* cnt,
-                      const int64_t* off, const T* inv, const double* prm, const T* r, T* z,
+void launch_hp_entity(const HpEnt& ent, const T* inv, const double* prm, const T* r, T* z,
                       const int* done, hipStream_t s);
 
 }  // namespace dev

@@ -128,10 +128,12 @@ struct Problem {
     HpHost hph;
     struct HpDev {
         DBuf cell_p, loc_off, psi_off, qp_off, sinv_off, loc2glob, inc_ptr, inc_idx, order;
-        DBuf item_start, item_count, item_p, cclass, c_off, C, vert, ent_first, ent_n, ent_off, ent_of;
+        DBuf item_start, item_count, item_p, cclass, c_off, C, vert, ent_first, ent_n, ent_off;
+        DBuf ent_list, ent_cstart, ent_ccount;
         DBuf inv64, inv32, tab64, tab32, toff, h64[3], h32[3], yloc64, yloc32, cv64, cv32;
     } hpd;
     dev::HpGeo hgeo{};
+    dev::HpEnt hent{};
     int hp_lds_elems = 256, hp_nmax = 1, np_gath = 0, np_cell = 0, np_hpl2 = 0;
     size_t hp_setup_bytes = 0;
     bool hp_setup_in_lds = false;

@@ -76,7 +76,19 @@ void Problem::build_hp() {
     upload(hpd.ent_first, H.ent_first.empty() ? std::vector<int32_t>(1, 0) : H.ent_first);
     upload(hpd.ent_n, H.ent_n.empty() ? std::vector<int32_t>(1, 0) : H.ent_n);
     upload(hpd.ent_off, H.ent_off.empty() ? std::vector<int64_t>(1, 0) : H.ent_off);
-    upload(hpd.ent_of, H.ent_of);
+    upload(hpd.ent_list, H.ent_list.empty() ? std::vector<int32_t>(1, 0) : H.ent_list);
+    upload(hpd.ent_cstart, H.ent_cstart.empty() ? std::vector<int32_t>(1, 0) : H.ent_cstart);
+    upload(hpd.ent_ccount, H.ent_ccount.empty() ? std::vector<int32_t>(1, 0) : H.ent_ccount);
+    if ((size_t)std::max(H.ent_lds, hp_nmax) * sizeof(double) + 4096 > lds_max)
+        fail(HPG_ERR_INVALID_ARG, "entity blocks too large for the preconditioner's LDS");
+    hent.nchunk = (int)H.ent_cstart.size();
+    hent.lds = H.ent_lds;
+    hent.cstart = hpd.ent_cstart.as<int32_t>();
+    hent.ccount = hpd.ent_ccount.as<int32_t>();
+    hent.list = hpd.ent_list.as<int32_t>();
+    hent.first = hpd.ent_first.as<int32_t>();
+    hent.cnt = hpd.ent_n.as<int32_t>();
+    hent.off = hpd.ent_off.as<int64_t>();
     upload(hpd.inv64, H.inv.empty() ? std::vector<double>(1, 0.0) : H.inv);
     upload(hpd.inv32, cast<float>(H.inv.empty() ? std::vector<double>(1, 0.0) : H.inv));
     upload(hpd.tab64, H.tab);
@@ -120,7 +132,7 @@ void Problem::build_hp() {
     np_u = np_gath;
     np_psi = np_gath;
     // <z_u, r_u>: the entity blocks' shares, then the vertex scatter's
-    np_dot = dev::hp_prec_entity_blocks(M.n_u) +
+    np_dot = dev::hp_prec_entity_blocks(hent.nchunk) +
              (H.vert.empty() ? 0 : dev::hp_vscatter_blocks((int64_t)H.vert.size()));
     np_prec = (int)std::min<int64_t>(M.n_cells, 4096);
     fdm_dot_fused = false;
@@ -334,7 +346,7 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
     const T* sinv = (dbl ? sinv64 : sinv32).template as<T>();
     const T* inv = (dbl ? hpd.inv64 : hpd.inv32).template as<T>();
     const int64_t nv = (int64_t)hph.vert.size();
-    const int ne = dev::hp_prec_entity_blocks(M.n_u);
+    const int ne = dev::hp_prec_entity_blocks(hent.nchunk);
     T* cv = (dbl ? hpd.cv64 : hpd.cv32).template as<T>();
     const int32_t* vidx = hpd.vert.as<int32_t>();
     // 2-D vertex grids up to 64 x 64: gather, solve and scatter in one workgroup
@@ -350,18 +362,15 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
         tstop("prec_psi", s);
         tstart("prec_u", s);
         if (!hph.ent_n.empty())
-            dev::launch_hp_entity<T>(M.n_u, hpd.ent_of.as<int32_t>(), hpd.ent_first.as<int32_t>(),
-                                     hpd.ent_n.as<int32_t>(), hpd.ent_off.as<int64_t>(), inv, prm,
-                                     r, z, dn, s);
+            dev::launch_hp_entity<T>(hent, inv, prm, r, z, dn, s);
         if (nv > 0 && !vs2) dev::launch_hp_vgather<T>(nv, vidx, r, cv, dn, s);
     } else {
         // psi-block, entity blocks (with their <z, r> shares) and the vertex
         // gather in one launch
         tstart("prec_u", s);
-        dev::launch_hp_prec_fused<T>(hgeo, sinv, np_prec, hp_nmax, ne, hpd.ent_of.as<int32_t>(),
-                                     hpd.ent_first.as<int32_t>(), hpd.ent_n.as<int32_t>(),
-                                     hpd.ent_off.as<int64_t>(), inv, prm, vidx, vs2 ? 0 : nv, cv,
-                                     r, z, part ? part + np_dot : nullptr, part, dn, s);
+        dev::launch_hp_prec_fused<T>(hgeo, sinv, np_prec, hp_nmax, ne, hent, inv, prm, vidx,
+                                     vs2 ? 0 : nv, cv, r, z, part ? part + np_dot : nullptr, part,
+                                     dn, s);
     }
     // vertices: (alpha A_VV)^{-1} by fast diagonalisation on the interior-vertex grid
     if (vs2) {
