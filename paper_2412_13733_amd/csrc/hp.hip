@@ -729,35 +729,63 @@ __device__ inline void hp_entity_body(int64_t bid, int64_t nblk, const HpEnt& en
         }
         __syncthreads();
         if (rows) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            // ng groups of 256 / ng threads, group g summing j in its range for
+            // the rows i0 + t; groups 1.. leave their sums in ps, group 0 adds
+            // them in order of g
+            const int ng = hp_ent_groups(n), rpg = 256 / ng, jc = (n + ng - 1) / ng;
+            T* ps = rs + kHpEntChunk * n;
+            const int t = threadIdx.x, grp = t / rpg;
+            for (int i0 = 0; i0 < n; i0 += rpg) {
+                const int i = i0 + t % rpg;
                 T acc[kHpEntChunk];
 #pragma unroll
                 for (int c = 0; c < kHpEntChunk; ++c) acc[c] = 0;
-                // eight rows of loads in flight, then their products in order of j
-                int j = 0;
-                for (; j + 8 <= n; j += 8) {
-                    T a[8];
+                if (i < n) {
+                    const int j1 = min(n, (grp + 1) * jc);
+                    // eight rows of loads in flight, then their products in order of j
+                    int j = grp * jc;
+                    for (; j + 8 <= j1; j += 8) {
+                        T a[8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(j + u) * n + i];
+                        for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(j + u) * n + i];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const T* rj = rs + (j + u) * kHpEntChunk;
+                        for (int u = 0; u < 8; ++u) {
+                            const T* rj = rs + (j + u) * kHpEntChunk;
 #pragma unroll
-                        for (int c = 0; c < kHpEntChunk; ++c) acc[c] += a[u] * rj[c];
+                            for (int c = 0; c < kHpEntChunk; ++c) acc[c] += a[u] * rj[c];
+                        }
+                    }
+                    for (; j < j1; ++j) {
+                        const T a = A[(int64_t)j * n + i];
+                        const T* rj = rs + j * kHpEntChunk;
+#pragma unroll
+                        for (int c = 0; c < kHpEntChunk; ++c) acc[c] += a * rj[c];
                     }
                 }
-                for (; j < n; ++j) {
-                    const T a = A[(int64_t)j * n + i];
-                    const T* rj = rs + j * kHpEntChunk;
+                if (ng > 1) {
+                    if (grp > 0) {
 #pragma unroll
-                    for (int c = 0; c < kHpEntChunk; ++c) acc[c] += a * rj[c];
+                        for (int c = 0; c < kHpEntChunk; ++c)
+                            ps[((grp - 1) * rpg + t % rpg) * kHpEntChunk + c] = acc[c];
+                    }
+                    __syncthreads();
+                    if (grp == 0) {
+                        for (int q = 1; q < ng; ++q) {
+#pragma unroll
+                            for (int c = 0; c < kHpEntChunk; ++c)
+                                acc[c] += ps[((q - 1) * rpg + t) * kHpEntChunk + c];
+                        }
+                    }
+                    __syncthreads();   // ps is reused by the next rows
                 }
+                if (grp == 0 && i < n) {
 #pragma unroll
-                for (int c = 0; c < kHpEntChunk; ++c) {
-                    if (c < nc) {
-                        const T zv = ia * acc[c];
-                        z[ent.first[ent.list[c0 + c]] + i] = zv;
-                        part += (double)zv * (double)rs[i * kHpEntChunk + c];
+                    for (int c = 0; c < kHpEntChunk; ++c) {
+                        if (c < nc) {
+                            const T zv = ia * acc[c];
+                            z[ent.first[ent.list[c0 + c]] + i] = zv;
+                            part += (double)zv * (double)rs[i * kHpEntChunk + c];
+                        }
                     }
                 }
             }

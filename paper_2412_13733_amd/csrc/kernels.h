@@ -362,7 +362,7 @@ void launch_hp_vscatter(int64_t n, const int32_t* idx, const T* in, T* z, const 
 // entities that share one (deduplicated) inverse: a chunk's right-hand sides
 // sit side by side in LDS, so each entry of the inverse is read once per
 // chunk.  Entities of kHpEntRowMin..kHpEntRowMax unknowns: up to kHpEntChunk
-// per chunk, a row per thread for all of them (LDS kHpEntChunk n); smaller
+// per chunk, a row (or a part of one) per thread for all of them; smaller
 // ones: up to 256 / n per chunk, a thread per (entity, row); larger ones: one
 // per chunk.
 constexpr int kHpEntChunk = 8;
@@ -373,8 +373,13 @@ __host__ __device__ inline bool hp_ent_rows(int n) {
 __host__ __device__ inline int hp_ent_cap(int n) {
     return hp_ent_rows(n) ? kHpEntChunk : (n < kHpEntRowMin ? 256 / n : 1);
 }
+// row path: the 256 threads form groups that each sum a range of j for
+// 256 / groups rows; the groups' sums meet in LDS
+__host__ __device__ inline int hp_ent_groups(int n) { return n > 128 ? 1 : (n > 64 ? 2 : 4); }
 __host__ __device__ inline int hp_ent_lds(int n) {   // LDS elements of a chunk
-    return hp_ent_rows(n) ? kHpEntChunk * n : hp_ent_cap(n) * n;
+    if (!hp_ent_rows(n)) return hp_ent_cap(n) * n;
+    const int g = hp_ent_groups(n);
+    return kHpEntChunk * n + (g - 1) * (256 / g) * kHpEntChunk;
 }
 struct HpEnt {
     int nchunk;
