@@ -742,14 +742,17 @@ __device__ inline void hp_entity_body(int64_t bid, int64_t nblk, const HpEnt& en
                 for (int c = 0; c < kHpEntChunk; ++c) acc[c] = 0;
                 if (i < n) {
                     const int j1 = min(n, (grp + 1) * jc);
-                    // eight rows of loads in flight, then their products in order of j
+                    // U rows of loads in flight, then their products in order of
+                    // j (FP32: 2, so that the fused launch's psi blocks, which
+                    // share its register budget, keep their occupancy)
+                    constexpr int U = sizeof(T) == sizeof(double) ? 8 : 2;
                     int j = grp * jc;
-                    for (; j + 8 <= j1; j += 8) {
-                        T a[8];
+                    for (; j + U <= j1; j += U) {
+                        T a[U];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(j + u) * n + i];
+                        for (int u = 0; u < U; ++u) a[u] = A[(int64_t)(j + u) * n + i];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
+                        for (int u = 0; u < U; ++u) {
                             const T* rj = rs + (j + u) * kHpEntChunk;
 #pragma unroll
                             for (int c = 0; c < kHpEntChunk; ++c) acc[c] += a[u] * rj[c];
