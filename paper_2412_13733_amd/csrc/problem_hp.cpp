@@ -122,13 +122,13 @@ void Problem::build_hp() {
     hgeo.item_count = hpd.item_count.as<int32_t>();
     hgeo.item_p = hpd.item_p.as<int32_t>();
     tune_hp_items();
-    // reduction layout: G apply = [gather blocks | cell blocks] (the u / psi
-    // halves of the generic layout), preconditioner = [dot blocks | psi blocks]
+    // reduction layout: G apply = [u sums | psi sums] of the gather blocks
+    // (the u / psi halves of the generic layout; both over fixed index ranges,
+    // so the sums do not depend on the tuned work items), preconditioner =
+    // [dot blocks | psi blocks]
     np_gath = (int)std::max<int64_t>(1, std::min<int64_t>((M.n_u + 255) / 256, 1024));
     np_cell = std::min(hgeo.n_items, 4096);   // one block per work item up to 4096
     np_hpl2 = (int)std::min<int64_t>(M.n_cells, 2048);
-    // both halves from the gather pass's blocks (fixed index ranges), so the
-    // sums do not depend on the tuned work items
     np_u = np_gath;
     np_psi = np_gath;
     // <z_u, r_u>: the entity blocks' shares, then the vertex scatter's
