@@ -832,8 +832,10 @@ __global__ __launch_bounds__(256) void k_hp_entity(HpEnt ent, const T* __restric
 }
 
 // The three independent parts of the block preconditioner in one grid:
-// blocks [0, np) the psi-block cells, [np, np + ne) the entity unknowns (with
-// their share of <z, r> in epart), the rest gathers the vertex residual.
+// blocks [0, ne) the entity chunks (with their share of <z, r> in epart;
+// first, so that their cache-bound work overlaps the streaming of the
+// psi-blocks), [ne, ne + np) the psi-block cells, the rest gathers the vertex
+// residual.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hp_prec_fused(HpGeo g, const T* __restrict__ sinv,
                                                        int np, int ne, HpEnt ent, const T* inv,
@@ -849,12 +851,12 @@ __global__ __launch_bounds__(256) void k_hp_prec_fused(HpGeo g, const T* __restr
     __shared__ T acc_s[256];
     if (done && *done) return;
     const int b = blockIdx.x;
-    if (b < np) {
-        hp_prec_psi_body<T>(b, np, g, sinv, r + g.n_u, z + g.n_u, ppart,
-                            reinterpret_cast<T*>(smem_raw), acc_s, red);
-    } else if (b < np + ne) {
-        hp_entity_body<T>(b - np, ne, ent, inv, (T)prm[2], r, z, epart,
+    if (b < ne) {
+        hp_entity_body<T>(b, ne, ent, inv, (T)prm[2], r, z, epart,
                           reinterpret_cast<T*>(smem_raw), red);
+    } else if (b < ne + np) {
+        hp_prec_psi_body<T>(b - ne, np, g, sinv, r + g.n_u, z + g.n_u, ppart,
+                            reinterpret_cast<T*>(smem_raw), acc_s, red);
     } else {
         const int64_t nb = gridDim.x - np - ne;
         for (int64_t i = (int64_t)(b - np - ne) * blockDim.x + threadIdx.x; i < nv;
