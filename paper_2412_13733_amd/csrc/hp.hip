@@ -960,7 +960,7 @@ __global__ __launch_bounds__(1024) void k_hp_vsolve2(int n0, int n1,
                                                      const T* __restrict__ l0,
                                                      const T* __restrict__ l1,
                                                      const double* __restrict__ prm,
-                                                     const T* __restrict__ r, T* __restrict__ z,
+                                                     const T* __restrict__ rv, T* __restrict__ z,
                                                      double* __restrict__ partial, int npart,
                                                      const int* __restrict__ done) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -973,8 +973,9 @@ __global__ __launch_bounds__(1024) void k_hp_vsolve2(int n0, int n1,
     T* X = sV1 + N1 * P1;                        // N1 x N0, pitch P0
     T* Y = X + N1 * P0;
     // every global load is issued before the first LDS store (each thread has
-    // at most 4 entries of each 64 x 64 array), so the prologue waits for two
-    // memory round trips: the vertex indices, then the residual through them
+    // at most 4 entries of each 64 x 64 array), so the prologue waits for one
+    // memory round trip: the vertex residual rv comes gathered (by the launch
+    // before), the vertex indices are needed only for the scatter
     constexpr int NT = 1024, NE = 4;
     const int tid = (int)threadIdx.x, nv = n0 * n1;
     T a0[NE], a1[NE], rr[NE];
@@ -989,7 +990,7 @@ __global__ __launch_bounds__(1024) void k_hp_vsolve2(int n0, int n1,
     }
     T el0 = tid < n0 ? l0[tid] : (T)1, el1 = tid < n1 ? l1[tid] : (T)1;
 #pragma unroll
-    for (int m = 0; m < NE; ++m) rr[m] = tid + NT * m < nv ? r[gi[m]] : (T)0;
+    for (int m = 0; m < NE; ++m) rr[m] = tid + NT * m < nv ? rv[tid + NT * m] : (T)0;
     if (tid < 64) {
         sl0[tid] = el0;
         sl1[tid] = el1;
@@ -1052,10 +1053,10 @@ __global__ __launch_bounds__(1024) void k_hp_vsolve2(int n0, int n1,
 
 template <typename T>
 void launch_hp_vsolve2(int n0, int n1, const int32_t* vidx, const T* V0, const T* V1, const T* l0,
-                       const T* l1, const double* prm, const T* r, T* z, double* partial,
+                       const T* l1, const double* prm, const T* rv, T* z, double* partial,
                        int npart, const int* done, hipStream_t s) {
     hipLaunchKernelGGL((k_hp_vsolve2<T>), dim3(1), dim3(1024), hp_vsolve2_lds(n0, n1, sizeof(T)),
-                       s, n0, n1, vidx, V0, V1, l0, l1, prm, r, z, partial, npart, done);
+                       s, n0, n1, vidx, V0, V1, l0, l1, prm, rv, z, partial, npart, done);
 }
 
 // ---------------------------------------------------------------------------

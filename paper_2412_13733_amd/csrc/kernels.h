@@ -403,13 +403,14 @@ void launch_hp_prec_fused(const HpGeo& g, const T* sinv, int np, int nmax, int n
                           int64_t nv, T* cv, const T* r, T* z, double* ppart, double* epart,
                           const int* done, hipStream_t s);
 // 2-D vertex block of the preconditioner in one workgroup (n0, n1 <= 64
-// interior vertices per direction): z[vidx] = (alpha A_VV)^{-1} r[vidx] by fast
-// diagonalisation (V0, V1: eigenvectors row-major; l0, l1: eigenvalues;
-// prm[2] = 1 / alpha), partial[0] = <z_V, r_V> and partial[1 .. npart) = 0
+// interior vertices per direction): z[vidx] = (alpha A_VV)^{-1} rv by fast
+// diagonalisation, rv = r[vidx] gathered beforehand (launch_hp_vgather or the
+// fused launch) (V0, V1: eigenvectors row-major; l0, l1: eigenvalues; prm[2] =
+// 1 / alpha), partial[0] = <z_V, r_V> and partial[1 .. npart) = 0
 size_t hp_vsolve2_lds(int n0, int n1, size_t tsize);
 template <typename T>
 void launch_hp_vsolve2(int n0, int n1, const int32_t* vidx, const T* V0, const T* V1, const T* l0,
-                       const T* l1, const double* prm, const T* r, T* z, double* partial,
+                       const T* l1, const double* prm, const T* rv, T* z, double* partial,
                        int npart, const int* done, hipStream_t s);
 template <typename T>
 void launch_hp_vscatter_dot(int64_t nv, const int32_t* idx, const T* in, const T* r, T* z,

@@ -363,20 +363,19 @@ void Problem::apply_prec_hp(const T* r, T* z, double* part, const int* dn, hipSt
         tstart("prec_u", s);
         if (!hph.ent_n.empty())
             dev::launch_hp_entity<T>(hent, inv, prm, r, z, dn, s);
-        if (nv > 0 && !vs2) dev::launch_hp_vgather<T>(nv, vidx, r, cv, dn, s);
+        if (nv > 0) dev::launch_hp_vgather<T>(nv, vidx, r, cv, dn, s);
     } else {
         // psi-block, entity blocks (with their <z, r> shares) and the vertex
         // gather in one launch
         tstart("prec_u", s);
-        dev::launch_hp_prec_fused<T>(hgeo, sinv, np_prec, hp_nmax, ne, hent, inv, prm, vidx,
-                                     vs2 ? 0 : nv, cv, r, z, part ? part + np_dot : nullptr, part,
-                                     dn, s);
+        dev::launch_hp_prec_fused<T>(hgeo, sinv, np_prec, hp_nmax, ne, hent, inv, prm, vidx, nv,
+                                     cv, r, z, part ? part + np_dot : nullptr, part, dn, s);
     }
     // vertices: (alpha A_VV)^{-1} by fast diagonalisation on the interior-vertex grid
     if (vs2) {
         dev::launch_hp_vsolve2<T>(hph.nv[0], hph.nv[1], vidx, F.V[0].template as<T>(),
                                   F.V[1].template as<T>(), F.lam[0].template as<T>(),
-                                  F.lam[1].template as<T>(), prm, r, z,
+                                  F.lam[1].template as<T>(), prm, cv, z,
                                   (part && !timing) ? part + ne : nullptr,
                                   dev::hp_vscatter_blocks(nv), dn, s);
     } else if (nv > 0) {
